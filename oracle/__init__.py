@@ -1,0 +1,6 @@
+"""FP64 CPU oracle (test infrastructure only; see rl_oracle's header)."""
+from .rl_oracle import (  # noqa: F401
+    EPS, dft_matrix, dft3, idft3, psf_centre, check_psf, centred_kernel, otf,
+    forward, adjoint, conv3d, conv_direct, corr_direct, conv_direct_at,
+    ratio, loglik, rl, rl_direct, rel_l2,
+)
