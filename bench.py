@@ -1,0 +1,226 @@
+"""Benchmark: Richardson-Lucy deconvolution throughput on one MI355X.
+
+A step is one complete deconvolution of one synthetic volume: reset the
+estimate to u0 = mean(d) and run the configured number of RL iterations
+(rl_iterate through the C ABI).  The headline workload is the 128x256x256
+widefield-like volume with 100 iterations; the 256x512x512 organoid-scale volume
+(50 iterations, larger than the on-chip caches) is reported beside it.
+
+Printed: one JSON line with value = voxel-iterations per second (whole job,
+inputs resident in HBM), a roofline object for the dominant kernel (per-launch
+algorithmic bytes / its average duration, measured here with HIP events), and
+the FP64 oracle timed on the host cores on a bounded sample.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, datasheet
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2510_14143_amd", "csrc", "rl_kernels.hip")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(shape) -> dict:
+    """Algorithmic HBM bytes per launch of each kernel kind (compulsory reads + writes)."""
+    nz, ny, nx = shape
+    nvox = nz * ny * nx
+    spec = nz * ny * (nx // 2 + 1) * 8  # valid half-spectrum bytes
+    real = nvox * 4
+    return {
+        "x_r2c": real + spec,
+        "x_c2r": spec + real,
+        "x_ratio": spec + real + spec,
+        # update: spectrum in, u in, u out, spectrum out (absent on the last iteration)
+        "x_update": spec + real + real + spec,
+        "x_update_last": spec + real + real,
+        "y": 2 * spec,
+        "z_otf": 3 * spec,
+    }
+
+
+def source_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kind: str, workload: str):
+    """Per-launch HBM bytes from a committed rocprofv3 counter summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(PROFILES, f"traffic_{kind}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    h = re.search(r"kernel source sha256\[:16\]:\s*`?([0-9a-f]{16})", text)
+    v = re.search(r"per-launch HBM bytes \(calibrated\):\s*([0-9.eE+]+)", text)
+    if not h or not v or h.group(1) != source_hash():
+        return None
+    return float(v.group(1))
+
+
+def run_workload(torch, rl, synth, cfg: int, steps: int, warmup: int, workload: str):
+    c = synth.make_config(cfg)
+    shape, n_iter = c["shape"], c["n_iter"]
+    dev = torch.device("cuda:0")
+    psf = torch.from_numpy(c["psf"]).to(dev)
+    d = torch.from_numpy(c["d"]).to(dev)
+    u0 = torch.from_numpy(c["u0"]).to(dev)
+    u = u0.clone()
+    plan = rl.Plan(psf)
+    nvox = int(np.prod(shape))
+
+    def step():
+        u.copy_(u0)
+        plan.iterate(d, u, n_iter)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        step()
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    value = nvox * n_iter / (ms * 1e-3) / 1e9
+
+    # per-kernel durations, HIP events around every launch (one extra step)
+    plan.set_timing(True)
+    step()
+    timing = plan.timing()
+    plan.set_timing(False)
+    flux = plan.flux()
+    total = float(c["d"].sum(dtype=np.float64))
+    drift = float(np.max(np.abs(flux - total)) / total)
+
+    kb = kernel_bytes(shape)
+    per_kind = {}
+    for kind, (cnt, tms) in timing.items():
+        if cnt == 0:
+            continue
+        if kind == "x_update":
+            byts = (kb["x_update"] * (cnt - 1) + kb["x_update_last"]) / cnt
+        else:
+            byts = kb.get(kind)
+        avg_us = tms * 1e3 / cnt
+        per_kind[kind] = dict(launches=cnt, total_ms=round(tms, 4), avg_us=round(avg_us, 3),
+                              bytes_per_launch=byts,
+                              gbs=(round(byts / (avg_us * 1e-6) / 1e9, 1) if byts else None))
+    dom = max(per_kind, key=lambda k: per_kind[k]["total_ms"])
+    dk = per_kind[dom]
+    achieved = dk["bytes_per_launch"] / (dk["avg_us"] * 1e-6) / 1e9
+    traffic = measured_traffic(dom, workload)
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic, "bytes_per_launch": dk["bytes_per_launch"],
+            "avg_launch_us": dk["avg_us"]}
+    # whole-iteration effective bandwidth over all passes
+    model_bytes = sum((v["bytes_per_launch"] or 0) * v["launches"] for v in per_kind.values())
+    kernel_ms = sum(v["total_ms"] for v in per_kind.values())
+    plan.close()
+    return dict(shape=shape, n_iter=n_iter, nvox=nvox, ms=ms, value=value, roofline=roof,
+                per_kind=per_kind, flux_drift=drift,
+                all_kernels_gbs=round(model_bytes / (kernel_ms * 1e-3) / 1e9, 1),
+                bytes_per_vi=round(model_bytes / (nvox * n_iter), 2))
+
+
+def cpu_baseline(synth, n_iter_sample: int = 4):
+    """The FP64 oracle on the host cores, bounded sample of the headline workload."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()
+                       if i.get("internal_api") in ("openblas", "mkl", "blis")] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    c = synth.make_config(1)
+    nvox = int(np.prod(c["shape"]))
+    t = time.perf_counter()
+    oracle.rl(c["d"], c["psf"], c["u0"], n_iter_sample)
+    dt = time.perf_counter() - t
+    return {"value": round(nvox * n_iter_sample / dt / 1e9, 6), "unit": "Gvoxel-iter/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{n_iter_sample} FP64 RL iterations of the 128x256x256 volume "
+                      f"(naive per-axis DFT by BLAS matrix products), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-large", action="store_true", help="skip the 256x512x512 workload")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (the batched and single-volume paths "
+              "are single-GPU); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+
+    import torch
+    from paper_2510_14143_amd import rl, synth
+
+    log("workload: config 1 (128x256x256, 100 it)")
+    main_run = run_workload(torch, rl, synth, 1, args.steps, args.warmup, "cfg1")
+    log(json.dumps({"cfg1_per_kind": main_run["per_kind"]}))
+    large = None
+    if not args.no_large:
+        log("workload: config 2 (256x512x512, 50 it)")
+        lr = run_workload(torch, rl, synth, 2, max(1, args.steps // 2), 1, "cfg2")
+        log(json.dumps({"cfg2_per_kind": lr["per_kind"]}))
+        large = {"workload": "rl_fp32_256x512x512_50it", "value": round(lr["value"], 3),
+                 "unit": "Gvoxel-iter/s", "ms_per_step": round(lr["ms"], 3),
+                 "roofline": lr["roofline"], "all_kernels_gbs": lr["all_kernels_gbs"],
+                 "bytes_per_vi": lr["bytes_per_vi"], "flux_drift": lr["flux_drift"]}
+    cpu = None
+    if rank == 0 and not args.no_cpu:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(synth)
+
+    out = {
+        "metric": "RL Gvoxel-iter/s (plain FP32, one volume)",
+        "value": round(main_run["value"], 3),
+        "unit": "Gvoxel-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_run["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "rl_fp32_128x256x256_100it", "shape_zyx": list(main_run["shape"]),
+                   "n_iter": main_run["n_iter"], "psf_sigma_xyz": [2.0, 2.0, 5.0],
+                   "boundary": "periodic", "parallelism": "single_gpu"},
+        "roofline": main_run["roofline"],
+        "cpu_baseline": cpu,
+        "all_kernels_gbs": main_run["all_kernels_gbs"],
+        "bytes_per_vi": main_run["bytes_per_vi"],
+        "flux_drift": main_run["flux_drift"],
+        "large": large,
+    }
+    if rank == 0:
+        print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+/*
+ * rl.h - C ABI of the MI355X (gfx950) Richardson-Lucy deconvolution library.
+ *
+ * Operation (paper §4.3, paragraph "Richardson-Lucy algorithm"): iterative
+ * deconvolution under a Poisson noise model.  One iteration of the estimate u
+ * against the observed volume d with the PSF h is
+ *
+ *     q = H u                      forward blur  (circular convolution with h)
+ *     r = d / q  where q > 1e-12, else 0
+ *     c = H^T r                    back-projection with the mirrored PSF
+ *     u = u * max(c, 0)
+ *
+ * where H uses the PSF normalised to unit sum (in FP64) with its centre at
+ * voxel floor(n/2) on each axis, and H^T is the exact adjoint of H (circular
+ * correlation; in the frequency domain a multiplication by the conjugate
+ * transfer function).  Image and PSF have the same ZYX shape, as in the
+ * paper's experiment (§4.3, paragraph "Dataset description").
+ *
+ * Conventions shared by every call:
+ *   - Volumes are dense, C-ordered float32 arrays [Z][Y][X], X contiguous,
+ *     shape given as {nz, ny, nx}.
+ *   - Every data pointer is a DEVICE pointer on the plan's GPU, owned by the
+ *     caller, at least 16-byte aligned, covering nz*ny*nx floats.
+ *   - Supported axis lengths: nx in {2^a, 3*2^a} with 4 <= nx <= 2048,
+ *     ny and nz in {1, 2^a, 3*2^a} up to 1024.  Other lengths return
+ *     RL_E_UNSUPPORTED.
+ *   - All argument checks run before any device work; a failing call leaves
+ *     every buffer untouched.  No call aborts, exits or throws.
+ *   - Work is enqueued on the plan's stream (default: the null stream) and
+ *     returns without waiting, except where a call says it synchronises.
+ *     Faults during execution surface at the next synchronising call.
+ *   - A plan is not re-entrant: use it from one host thread / stream at a time.
+ *   - Error detail for the last failing call on this thread: rl_last_error().
+ */
+#ifndef RL_H_
+#define RL_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rl_plan_s* rl_plan; /* opaque, owned by the library */
+
+typedef enum {
+  RL_OK = 0,
+  RL_E_INVALID = 1,     /* bad argument: NULL, misaligned, wrong size, bad PSF, ... */
+  RL_E_UNSUPPORTED = 2, /* valid request this library does not implement */
+  RL_E_NOMEM = 3,       /* device allocation failed */
+  RL_E_DEVICE = 4,      /* no usable GPU, or a HIP runtime / launch error */
+  RL_E_NUMERIC = 5,     /* non-finite flux detected at a synchronising call */
+  RL_E_INTERNAL = 6     /* unexpected internal failure */
+} rl_status;
+
+typedef enum {
+  RL_BOUNDARY_PERIODIC = 0, /* circular convolution (the only boundary implemented) */
+  RL_BOUNDARY_ZERO = 1      /* linear convolution with zero padding: RL_E_UNSUPPORTED */
+} rl_boundary;
+
+typedef enum {
+  RL_PRECISION_FP32 = 0 /* FP32 transforms, FP64 twiddle generation and sums */
+} rl_precision;
+
+/* Options for rl_plan_create_ex.  Zero-initialise, then set fields. */
+typedef struct {
+  int precision;  /* rl_precision */
+  void* stream;   /* hipStream_t to enqueue on; NULL = null stream */
+  int tile_x;     /* columns per work-group in the Y/Z passes; 0 = library default */
+} rl_options;
+
+/*
+ * Create a plan for volumes of shape {nz, ny, nx} blurred by `psf`
+ * (device pointer, the same shape).  The PSF is read only during this call:
+ * it must be finite, >= 0 and have a positive sum (else RL_E_INVALID); it is
+ * normalised to unit sum in FP64 and its transfer function is stored in the
+ * plan (plan-owned device memory, about 8 bytes per voxel including the
+ * spectrum workspace).  Synchronous: returns after all device work is done.
+ * On success *out receives the plan; on failure *out is set to NULL.
+ */
+rl_status rl_plan_create(const int64_t shape[3], const float* psf, int boundary,
+                         rl_plan* out);
+
+/* As rl_plan_create, with options (may be NULL for defaults). */
+rl_status rl_plan_create_ex(const int64_t shape[3], const float* psf, int boundary,
+                            const rl_options* opt, rl_plan* out);
+
+/*
+ * Run exactly n_iter Richardson-Lucy iterations in place on `estimate`
+ * (device, read/write), starting from its current contents, against
+ * `observed` (device, read-only).  n_iter == 0 is a no-op; n_iter < 0 is
+ * RL_E_INVALID.  The FP64 total flux sum(u) after each iteration is kept on
+ * the device for rl_plan_get_flux.  Asynchronous on the plan's stream;
+ * `observed` and `estimate` must stay valid until that work completes.
+ * Calling again continues the iteration (resume).
+ */
+rl_status rl_iterate(rl_plan p, const float* observed, float* estimate, int n_iter);
+
+/*
+ * out = H x: circular convolution of x (device) with the plan's normalised PSF,
+ * exactly the forward operator rl_iterate uses.  `out` may alias `x`.
+ * Asynchronous on the plan's stream.
+ */
+rl_status conv3d_fft(rl_plan p, const float* x, float* out);
+
+/* Release the plan and its device memory (waits for its pending work). NULL is a no-op. */
+void rl_plan_destroy(rl_plan p);
+
+/* Enqueue later work of this plan on `hip_stream` (a hipStream_t; NULL = null stream). */
+rl_status rl_plan_set_stream(rl_plan p, void* hip_stream);
+
+/*
+ * Copy the per-iteration FP64 flux of the most recent rl_iterate call into
+ * flux[0 .. min(cap, n) - 1] and its length n into *n_written.  Synchronises
+ * the plan's stream.  Returns RL_E_NUMERIC if any value is not finite (this is
+ * also where a NaN/Inf in the inputs is reported).
+ */
+rl_status rl_plan_get_flux(rl_plan p, double* flux, int cap, int* n_written);
+
+/* Shape {nz, ny, nx} and the half-spectrum row pitch (complex elements) of a plan. */
+rl_status rl_plan_get_info(rl_plan p, int64_t shape[3], int64_t* spectrum_pitch);
+
+/*
+ * Per-kernel timing with HIP events (measurement support).  When enabled,
+ * every kernel the plan launches is bracketed by events on the plan's stream.
+ * rl_plan_get_timing synchronises and returns, for each kernel kind k in
+ * [0, RL_KERNEL_KINDS), the number of launches and their summed duration in
+ * milliseconds since timing was enabled; it then clears the counters.
+ */
+enum {
+  RL_KERNEL_X_R2C = 0,    /* X pass: real rows -> half spectrum */
+  RL_KERNEL_X_C2R = 1,    /* X pass: half spectrum -> real rows */
+  RL_KERNEL_X_RATIO = 2,  /* X pass: inverse, ratio d/q, forward */
+  RL_KERNEL_X_UPDATE = 3, /* X pass: inverse, multiplicative update + flux, forward */
+  RL_KERNEL_Y = 4,        /* Y pass, forward or inverse */
+  RL_KERNEL_Z_OTF = 5,    /* Z pass: forward, times (conj) transfer function, inverse */
+  RL_KERNEL_Z = 6,        /* Z pass, forward only (plan creation) */
+  RL_KERNEL_OTHER = 7,    /* twiddles, PSF reduction and preparation */
+  RL_KERNEL_KINDS = 8
+};
+rl_status rl_plan_set_timing(rl_plan p, int enable);
+rl_status rl_plan_get_timing(rl_plan p, int count[RL_KERNEL_KINDS], double ms[RL_KERNEL_KINDS]);
+
+/*
+ * Bandwidth probe (measurement support): copy `bytes` bytes (multiple of 16)
+ * from device `src` to device `dst` with a plain streaming kernel on
+ * `hip_stream`.  Used to calibrate hardware byte counters against a known
+ * amount of traffic.
+ */
+rl_status rl_probe_copy(const void* src, void* dst, size_t bytes, void* hip_stream);
+
+/* Static text for a status code. */
+const char* rl_status_string(rl_status s);
+
+/* Detail of the last failing call made by this thread ("" if none). */
+const char* rl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RL_H_ */

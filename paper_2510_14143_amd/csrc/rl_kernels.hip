@@ -1,0 +1,579 @@
+// HIP kernels for gfx950: FFT passes of the periodic 3-D Richardson-Lucy
+// iteration (paper §4.3), with the ratio and update steps fused into the
+// passes along the contiguous X axis.
+//
+// Transform scheme.  Each 1-D transform of length L runs as a sequence of
+// Stockham radix stages (radices 16, 8, 4, 2, and 3 as the last stage).  A
+// thread owns E elements of its pencil, element i + P*m in register m
+// (P = L/E threads per pencil).  Stage (p, R) processes butterflies
+// b = i + q*P, q < E/R, whose inputs are elements b + j*L/R (registers
+// q + j*E/R); it multiplies input j by w_{pR}^{j*k} with k = b mod p, applies
+// an R-point DFT, and writes output jj to position (b - k)*R + k + jj*p.  All
+// but the last stage exchange through LDS; the last stage's outputs land in
+// natural order in the same registers, so global loads and stores of a pass
+// are always "element i + P*m".
+//
+// The half-spectrum layout is [Z][Y][pitch] complex64 with nx/2 + 1 valid
+// columns per row.  Real rows are transformed as complex rows of half length
+// (even samples in the real part, odd in the imaginary part) followed by the
+// usual split into even and odd spectra.
+#include "rl_internal.h"
+
+namespace rlmi {
+
+// ---------------------------------------------------------------------------
+// complex helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
+// multiply by S*i (S = +1 or -1)
+template <int S>
+__device__ __forceinline__ float2 mul_si(float2 a) {
+  return S > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// cos(2 pi k / 16), k = 0..15
+__device__ constexpr float kCos16[16] = {
+    1.0f,  0.92387953251128674f,  0.70710678118654752f,  0.38268343236508977f,
+    0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
+   -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f,
+    0.0f,  0.38268343236508977f,  0.70710678118654752f,  0.92387953251128674f};
+
+// a * exp(S * 2 pi i K / R) for R in {2, 4, 8, 16}, with the trivial angles special-cased.
+template <int R, int K, int S>
+__device__ __forceinline__ float2 rot(float2 a) {
+  constexpr int k = ((K % R) + R) % R;
+  if constexpr (k == 0) {
+    return a;
+  } else if constexpr (2 * k == R) {
+    return make_float2(-a.x, -a.y);
+  } else if constexpr (4 * k == R) {
+    return mul_si<S>(a);
+  } else if constexpr (4 * k == 3 * R) {
+    return mul_si<-S>(a);
+  } else {
+    constexpr int t = k * (16 / R);
+    const float c = kCos16[t];
+    const float s = S * kCos16[(t + 12) & 15];  // sin(2 pi t / 16)
+    return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+  }
+}
+
+// In-register R-point DFT, y_k = sum_j x_j exp(S * 2 pi i j k / R), natural order.
+template <int R, int S>
+struct Dft;
+
+template <int S>
+struct Dft<2, S> {
+  __device__ __forceinline__ static void run(float2* x) {
+    float2 a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  }
+};
+
+template <int S>
+struct Dft<3, S> {
+  __device__ __forceinline__ static void run(float2* x) {
+    constexpr float h = 0.86602540378443865f;  // sqrt(3)/2
+    float2 a = x[0], b = x[1], c = x[2];
+    float2 t1 = cadd(b, c);
+    float2 t2 = make_float2(a.x - 0.5f * t1.x, a.y - 0.5f * t1.y);
+    float2 d = csub(b, c);
+    float2 t3 = make_float2(S * h * d.x, S * h * d.y);
+    float2 it3 = make_float2(-t3.y, t3.x);  // i * t3
+    x[0] = cadd(a, t1);
+    x[1] = cadd(t2, it3);
+    x[2] = csub(t2, it3);
+  }
+};
+
+template <int S>
+struct Dft<4, S> {
+  __device__ __forceinline__ static void run(float2* x) {
+    float2 s0 = cadd(x[0], x[2]), d0 = csub(x[0], x[2]);
+    float2 s1 = cadd(x[1], x[3]), d1 = mul_si<S>(csub(x[1], x[3]));
+    x[0] = cadd(s0, s1);
+    x[2] = csub(s0, s1);
+    x[1] = cadd(d0, d1);
+    x[3] = csub(d0, d1);
+  }
+};
+
+// Radix-2 decimation in time: split into even and odd halves.
+template <int R, int S>
+struct Dft {
+  static_assert(R == 8 || R == 16, "unsupported radix");
+  template <int K>
+  __device__ __forceinline__ static void combine(float2* x, const float2* e, const float2* o) {
+    if constexpr (K < R / 2) {
+      float2 t = rot<R, K, S>(o[K]);
+      x[K] = cadd(e[K], t);
+      x[K + R / 2] = csub(e[K], t);
+      combine<K + 1>(x, e, o);
+    }
+  }
+  __device__ __forceinline__ static void run(float2* x) {
+    float2 e[R / 2], o[R / 2];
+#pragma unroll
+    for (int j = 0; j < R / 2; ++j) {
+      e[j] = x[2 * j];
+      o[j] = x[2 * j + 1];
+    }
+    Dft<R / 2, S>::run(e);
+    Dft<R / 2, S>::run(o);
+    combine<0>(x, e, o);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Stockham stages
+// ---------------------------------------------------------------------------
+// tw: table of exp(-2 pi i m / T) (forward sign); inverse transforms conjugate it.
+// lds element n of this thread's pencil lives at lds[n * ls + lo].
+template <int E, int R, int S>
+__device__ __forceinline__ void stage(float2 (&v)[E], int i, int P, int p, int tm, bool last,
+                                      const float2* __restrict__ tw, float2* lds, int ls, int lo) {
+  constexpr int V = E / R;
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const int b = i + q * P;
+    const int k = last ? b : (b & (p - 1));
+    float2 y[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) y[j] = v[q + j * V];
+    if (p > 1) {
+#pragma unroll
+      for (int j = 1; j < R; ++j) {
+        const float2 w = tw[j * k * tm];
+        y[j] = (S < 0) ? cmul(y[j], w) : cmulc(y[j], w);
+      }
+    }
+    Dft<R, S>::run(y);
+    if (last) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) v[q + j * V] = y[j];
+    } else {
+      const int base = (b - k) * R + k;
+#pragma unroll
+      for (int j = 0; j < R; ++j) lds[(base + j * p) * ls + lo] = y[j];
+    }
+  }
+}
+
+// Full 1-D transform of this thread's pencil; natural order in and out.
+// Every thread of the work-group must call it (it contains barriers).
+template <int E, int S>
+__device__ __forceinline__ void fft(float2 (&v)[E], const Sched& sc, int i, int P,
+                                    const float2* __restrict__ tw, float2* lds, int ls, int lo) {
+  for (int s = 0; s < sc.ns; ++s) {
+    const bool last = (s == sc.ns - 1);
+    const int r = sc.r[s], p = sc.p[s], tm = sc.tm[s];
+    switch (r) {
+      case 16:
+        if constexpr (E % 16 == 0) stage<E, 16, S>(v, i, P, p, tm, last, tw, lds, ls, lo);
+        break;
+      case 8:
+        if constexpr (E % 8 == 0) stage<E, 8, S>(v, i, P, p, tm, last, tw, lds, ls, lo);
+        break;
+      case 4:
+        if constexpr (E % 4 == 0) stage<E, 4, S>(v, i, P, p, tm, last, tw, lds, ls, lo);
+        break;
+      case 2:
+        if constexpr (E % 2 == 0) stage<E, 2, S>(v, i, P, p, tm, last, tw, lds, ls, lo);
+        break;
+      case 3:
+        if constexpr (E % 3 == 0) stage<E, 3, S>(v, i, P, p, tm, last, tw, lds, ls, lo);
+        break;
+      default:
+        break;
+    }
+    if (!last) {
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = lds[(i + P * m) * ls + lo];
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Y / Z pencil pass
+// ---------------------------------------------------------------------------
+// Work-group = TX columns x P threads; lanes run along the contiguous column
+// index so that each global access of a wavefront covers TX consecutive
+// complex elements of 64/TX pencil rows.
+template <int E, int MODE>
+__global__ void __launch_bounds__(kPencilMaxThreads) k_pencil(float2* __restrict__ data,
+                                                 const float2* __restrict__ otf,
+                                                 const float2* __restrict__ tw, PencilArgs a,
+                                                 Sched sc) {
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+  const int xl = tid & (a.TX - 1);
+  const int i = tid / a.TX;
+  const int x = blockIdx.x * a.TX + xl;
+  const bool ok = x < a.ncols;
+  const long long base = (long long)blockIdx.y * a.ostride + x;
+
+  float2 v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m)
+    v[m] = ok ? data[base + (long long)(i + a.P * m) * a.estride] : make_float2(0.f, 0.f);
+
+  if constexpr (MODE != PM_INV) fft<E, -1>(v, sc, i, a.P, tw, lds, a.TXP, xl);
+  if constexpr (MODE == PM_FKI || MODE == PM_FCKI) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const float2 k = ok ? otf[base + (long long)(i + a.P * m) * a.estride] : make_float2(0.f, 0.f);
+      v[m] = (MODE == PM_FKI) ? cmul(v[m], k) : cmulc(v[m], k);
+    }
+  }
+  if constexpr (MODE != PM_FWD) fft<E, +1>(v, sc, i, a.P, tw, lds, a.TXP, xl);
+
+  if (ok) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) data[base + (long long)(i + a.P * m) * a.estride] = v[m];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// X row pass (contiguous axis)
+// ---------------------------------------------------------------------------
+// Forward: complex row z (registers, natural order) -> FFT -> split into the
+// half spectrum X[0..M] and store.  `row` points at this thread's LDS row.
+template <int E>
+__device__ __forceinline__ void r2c_store(float2 (&v)[E], const XArgs& a, const Sched& sc, int i,
+                                          const float2* tw, float2* row, bool ok,
+                                          float2* __restrict__ out) {
+  const int M = a.M, P = a.P;
+  fft<E, -1>(v, sc, i, P, tw, row, 1, 0);
+#pragma unroll
+  for (int m = 0; m < E; ++m) row[i + P * m] = v[m];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int k = i + P * m;
+    const float2 A = v[m];
+    const float2 B = conjf2(row[k == 0 ? 0 : M - k]);
+    const float2 ev = make_float2(0.5f * (A.x + B.x), 0.5f * (A.y + B.y));
+    const float2 dd = csub(A, B);
+    const float2 od = make_float2(0.5f * dd.y, -0.5f * dd.x);  // -i/2 * (A - B)
+    const float2 X = cadd(ev, cmul(tw[k], od));
+    if (ok) out[k] = X;
+  }
+  if (ok && i == 0) out[M] = make_float2(v[0].x - v[0].y, 0.f);
+}
+
+template <int E, int MODE>
+__global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const float2* __restrict__ twg) {
+  extern __shared__ float2 lds[];
+  const int M = a.M, P = a.P;
+  const int tid = threadIdx.x;
+  float2* tw = lds;  // 2M entries: exp(-2 pi i k / (2M))
+  for (int t = tid; t < 2 * M; t += blockDim.x) tw[t] = twg[t];
+  const int rl = tid / P, i = tid - rl * P;
+  const int rowi = blockIdx.x * a.RPW + rl;
+  const bool ok = (rl < a.RPW) && (rowi < a.nrows);
+  const long long rix = ok ? rowi : 0;
+  float2* row = lds + 2 * M + rl * a.RS;
+  float2* srow = a.spec + rix * a.pitch;
+
+  float2 v[E];
+  if constexpr (MODE == XM_R2C) {
+    const float2* in = reinterpret_cast<const float2*>(a.rin + rix * a.rin_stride);
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = ok ? in[i + P * m] : make_float2(0.f, 0.f);
+    __syncthreads();  // twiddles in LDS
+    r2c_store<E>(v, a, sc, i, tw, row, ok, srow);
+    return;
+  } else {
+    // stage the spectrum row in LDS, then pair X[k] with X[M-k]
+#pragma unroll
+    for (int m = 0; m < E; ++m) row[i + P * m] = ok ? srow[i + P * m] : make_float2(0.f, 0.f);
+    if (i == 0) row[M] = ok ? srow[M] : make_float2(0.f, 0.f);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int k = i + P * m;
+      const float2 X = row[k];
+      const float2 Y = conjf2(row[M - k]);
+      const float2 A = cadd(X, Y);
+      const float2 B = cmulc(csub(X, Y), tw[k]);  // (X - conj X[M-k]) * exp(+2 pi i k / 2M)
+      v[m] = make_float2(A.x - B.y, A.y + B.x);   // A + i B
+    }
+    __syncthreads();
+    fft<E, +1>(v, sc, i, P, tw, row, 1, 0);
+    // v[m] now holds (x[2n], x[2n+1]) for n = i + P*m (unnormalised; the 1/N is in the OTF)
+    if constexpr (MODE == XM_C2R) {
+      if (ok) {
+        float2* out = reinterpret_cast<float2*>(a.rout + rix * a.rout_stride);
+#pragma unroll
+        for (int m = 0; m < E; ++m) out[i + P * m] = v[m];
+      }
+      return;
+    } else if constexpr (MODE == XM_RATIO) {
+      const float2* dr = reinterpret_cast<const float2*>(a.d + rix * (2LL * M));
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const float2 dv = ok ? dr[i + P * m] : make_float2(0.f, 0.f);
+        const float2 q = v[m];
+        v[m] = make_float2(q.x > 1e-12f ? dv.x / q.x : 0.f, q.y > 1e-12f ? dv.y / q.y : 0.f);
+      }
+      __syncthreads();  // row buffer reuse
+      r2c_store<E>(v, a, sc, i, tw, row, ok, srow);
+      return;
+    } else {  // XM_UPDATE
+      float2* ur = reinterpret_cast<float2*>(a.u + rix * (2LL * M));
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const float2 uo = ok ? ur[i + P * m] : make_float2(0.f, 0.f);
+        const float2 c = v[m];
+        // clamp c < 0 to 0; a NaN passes through (as max(c, 0) does in the oracle) so that
+        // non-finite inputs reach the flux check instead of being silently zeroed
+        const float2 un = make_float2(uo.x * (c.x < 0.f ? 0.f : c.x), uo.y * (c.y < 0.f ? 0.f : c.y));
+        if (ok) ur[i + P * m] = un;
+        acc += (double)un.x + (double)un.y;
+        v[m] = un;
+      }
+      if (a.do_fwd) {
+        __syncthreads();
+        r2c_store<E>(v, a, sc, i, tw, row, ok, srow);
+      }
+      // deterministic work-group sum: wavefront butterfly, then waves in order
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+      __shared__ double wsum[16];
+      __shared__ bool last_block;
+      __syncthreads();
+      if ((tid & 63) == 0) wsum[tid >> 6] = acc;
+      __syncthreads();
+      if (tid == 0) {
+        double t = 0.0;
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; ++w) t += wsum[w];
+        a.partials[blockIdx.x] = t;
+        __threadfence();
+        const unsigned done = atomicAdd(a.counter, 1u);
+        last_block = (done == gridDim.x - 1);
+      }
+      __syncthreads();
+      if (last_block) {
+        __threadfence();
+        const unsigned long long* pp = reinterpret_cast<const unsigned long long*>(a.partials);
+        double t = 0.0;
+        for (unsigned g = tid; g < gridDim.x; g += blockDim.x)
+          t += __longlong_as_double((long long)__hip_atomic_load(
+              pp + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        __syncthreads();
+        if ((tid & 63) == 0) wsum[tid >> 6] = t;
+        __syncthreads();
+        if (tid == 0) {
+          double s = 0.0;
+          const int nw = (blockDim.x + 63) >> 6;
+          for (int w = 0; w < nw; ++w) s += wsum[w];
+          a.flux[a.iter] = s;
+          __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// small kernels: twiddles, PSF statistics and preparation, copy probe
+// ---------------------------------------------------------------------------
+// tab[m] = exp(-2 pi i m / n), evaluated in FP64 from the exact integer m / n
+// and rounded once to FP32.
+__global__ void k_twiddles(float2* tab, int n) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  double s, c;
+  sincospi(2.0 * (double)m / (double)n, &s, &c);
+  tab[m] = make_float2((float)c, (float)(-s));
+}
+
+// FP64 sum, min and non-finite count of h; partial per block, last block finishes.
+__global__ void __launch_bounds__(256) k_psf_stats(const float* __restrict__ h, long long n,
+                                                   double* partials, unsigned* counter,
+                                                   double* out) {
+  __shared__ double ssum[4], smin[4], snf[4];
+  __shared__ bool last_block;
+  const int tid = threadIdx.x;
+  double s = 0.0, mn = 1.0e300, nf = 0.0;
+  for (long long t = (long long)blockIdx.x * blockDim.x + tid; t < n;
+       t += (long long)gridDim.x * blockDim.x) {
+    const float v = h[t];
+    if (!isfinite(v)) {
+      nf += 1.0;
+    } else {
+      s += (double)v;
+      mn = fmin(mn, (double)v);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    s += __shfl_xor(s, off, 64);
+    mn = fmin(mn, __shfl_xor(mn, off, 64));
+    nf += __shfl_xor(nf, off, 64);
+  }
+  if ((tid & 63) == 0) {
+    ssum[tid >> 6] = s;
+    smin[tid >> 6] = mn;
+    snf[tid >> 6] = nf;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double a = 0.0, b = 1.0e300, c = 0.0;
+    for (int w = 0; w < 4; ++w) {
+      a += ssum[w];
+      b = fmin(b, smin[w]);
+      c += snf[w];
+    }
+    partials[3 * blockIdx.x + 0] = a;
+    partials[3 * blockIdx.x + 1] = b;
+    partials[3 * blockIdx.x + 2] = c;
+    __threadfence();
+    last_block = (atomicAdd(counter, 1u) == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (last_block && tid == 0) {
+    __threadfence();
+    const unsigned long long* pp = reinterpret_cast<const unsigned long long*>(partials);
+    double a = 0.0, b = 1.0e300, c = 0.0;
+    for (unsigned g = 0; g < gridDim.x; ++g) {
+      a += __longlong_as_double((long long)__hip_atomic_load(pp + 3 * g + 0, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT));
+      b = fmin(b, __longlong_as_double((long long)__hip_atomic_load(
+                      pp + 3 * g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+      c += __longlong_as_double((long long)__hip_atomic_load(pp + 3 * g + 2, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT));
+    }
+    out[0] = a;
+    out[1] = b;
+    out[2] = c;
+    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// out[z][y][x] (rows `out_row_stride` floats apart) = h[(z+cz)%nz][(y+cy)%ny][(x+cx)%nx] * scale,
+// with the product taken in FP64: moves the PSF centre floor(n/2) to index 0.
+__global__ void k_psf_prep(const float* __restrict__ h, float* __restrict__ out, int nz, int ny,
+                           int nx, long long out_row_stride, double scale) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  const int z = blockIdx.z;
+  if (x >= nx) return;
+  const int sx = (x + nx / 2) % nx, sy = (y + ny / 2) % ny, sz = (z + nz / 2) % nz;
+  const float v = h[((long long)sz * ny + sy) * nx + sx];
+  out[((long long)z * ny + y) * out_row_stride + x] = (float)((double)v * scale);
+}
+
+__global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ src,
+                                              float4* __restrict__ dst, long long n) {
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (long long)gridDim.x * blockDim.x)
+    dst[t] = src[t];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <int MODE>
+static hipError_t pencil_e(int E, dim3 g, dim3 b, size_t lds, hipStream_t s, float2* data,
+                           const float2* otf, const float2* tw, const PencilArgs& a,
+                           const Sched& sc) {
+  switch (E) {
+#define RL_CASE(EV)                                                             \
+  case EV:                                                                      \
+    hipLaunchKernelGGL((k_pencil<EV, MODE>), g, b, lds, s, data, otf, tw, a, sc); \
+    break;
+    RL_CASE(1) RL_CASE(2) RL_CASE(3) RL_CASE(4) RL_CASE(6) RL_CASE(8) RL_CASE(12) RL_CASE(16)
+    RL_CASE(24)
+#undef RL_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pencil(int mode, int E, dim3 grid, dim3 block, size_t lds, hipStream_t s,
+                         float2* data, const float2* otf, const float2* tw,
+                         const PencilArgs& a, const Sched& sc) {
+  switch (mode) {
+    case PM_FWD: return pencil_e<PM_FWD>(E, grid, block, lds, s, data, otf, tw, a, sc);
+    case PM_INV: return pencil_e<PM_INV>(E, grid, block, lds, s, data, otf, tw, a, sc);
+    case PM_FKI: return pencil_e<PM_FKI>(E, grid, block, lds, s, data, otf, tw, a, sc);
+    case PM_FCKI: return pencil_e<PM_FCKI>(E, grid, block, lds, s, data, otf, tw, a, sc);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int MODE>
+static hipError_t xrow_e(int E, dim3 g, dim3 b, size_t lds, hipStream_t s, const XArgs& a,
+                         const Sched& sc, const float2* tw) {
+  switch (E) {
+#define RL_CASE(EV)                                                      \
+  case EV:                                                               \
+    hipLaunchKernelGGL((k_xrow<EV, MODE>), g, b, lds, s, a, sc, tw);     \
+    break;
+    RL_CASE(1) RL_CASE(2) RL_CASE(3) RL_CASE(4) RL_CASE(6) RL_CASE(8) RL_CASE(12) RL_CASE(16)
+    RL_CASE(24)
+#undef RL_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_xrow(int mode, int E, dim3 grid, dim3 block, size_t lds, hipStream_t s,
+                       const XArgs& a, const Sched& sc, const float2* tw) {
+  switch (mode) {
+    case XM_R2C: return xrow_e<XM_R2C>(E, grid, block, lds, s, a, sc, tw);
+    case XM_C2R: return xrow_e<XM_C2R>(E, grid, block, lds, s, a, sc, tw);
+    case XM_RATIO: return xrow_e<XM_RATIO>(E, grid, block, lds, s, a, sc, tw);
+    case XM_UPDATE: return xrow_e<XM_UPDATE>(E, grid, block, lds, s, a, sc, tw);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_twiddles(float2* tab, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_twiddles, dim3((n + 255) / 256), dim3(256), 0, s, tab, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_psf_stats(const float* h, long long n, double* partials, int nblk,
+                            unsigned* counter, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_psf_stats, dim3(nblk), dim3(256), 0, s, h, n, partials, counter, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_psf_prep(const float* h, float* out, int nz, int ny, int nx,
+                           long long out_row_stride, double scale, hipStream_t s) {
+  dim3 g((nx + 255) / 256, ny, nz);
+  hipLaunchKernelGGL(k_psf_prep, g, dim3(256), 0, s, h, out, nz, ny, nx, out_row_stride, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  const long long n = (long long)(bytes / 16);
+  long long blocks = (n + 255) / 256;
+  if (blocks > 256LL * 64) blocks = 256LL * 64;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s,
+                     reinterpret_cast<const float4*>(src), reinterpret_cast<float4*>(dst), n);
+  return hipGetLastError();
+}
+
+}  // namespace rlmi

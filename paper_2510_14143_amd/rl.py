@@ -1,0 +1,282 @@
+"""Python binding of librlmi.so: the C ABI of include/rl.h, one function per entry point.
+
+The functions here only marshal arguments (ints and device pointers) and turn
+status codes into RLError; every step of the computation runs in the HIP
+kernels of the library.  `Plan` wraps them for torch tensors: it checks dtype,
+device, shape and contiguity, and enqueues on torch's current stream.
+
+The library is loaded on first use; if it has not been built, the first call
+raises (there is no fallback implementation).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librlmi.so")
+HEADER_PATH = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                           "include", "rl.h")
+
+RL_OK, RL_E_INVALID, RL_E_UNSUPPORTED, RL_E_NOMEM, RL_E_DEVICE, RL_E_NUMERIC, RL_E_INTERNAL = range(7)
+RL_BOUNDARY_PERIODIC, RL_BOUNDARY_ZERO = 0, 1
+RL_PRECISION_FP32 = 0
+KERNEL_KINDS = ("x_r2c", "x_c2r", "x_ratio", "x_update", "y", "z_otf", "z", "other")
+
+
+class RLError(RuntimeError):
+    """A non-OK status from the library; .status holds the code."""
+
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_STATUS_NAMES = {0: "RL_OK", 1: "RL_E_INVALID", 2: "RL_E_UNSUPPORTED", 3: "RL_E_NOMEM",
+                 4: "RL_E_DEVICE", 5: "RL_E_NUMERIC", 6: "RL_E_INTERNAL"}
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("stream", ctypes.c_void_p), ("tile_x", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load librlmi.so (once).  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2510_14143_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "rl_plan_create": ([i64p, vp, ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
+        "rl_plan_create_ex": ([i64p, vp, ctypes.c_int, ctypes.POINTER(_Options), ctypes.POINTER(vp)],
+                              ctypes.c_int),
+        "rl_iterate": ([vp, vp, vp, ctypes.c_int], ctypes.c_int),
+        "conv3d_fft": ([vp, vp, vp], ctypes.c_int),
+        "rl_plan_destroy": ([vp], None),
+        "rl_plan_set_stream": ([vp, vp], ctypes.c_int),
+        "rl_plan_get_flux": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                              ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "rl_plan_get_info": ([vp, i64p, i64p], ctypes.c_int),
+        "rl_plan_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
+        "rl_plan_get_timing": ([vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)],
+                               ctypes.c_int),
+        "rl_probe_copy": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
+        "rl_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        "rl_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def header_functions() -> list:
+    """Names of the functions declared in include/rl.h."""
+    with open(HEADER_PATH) as f:
+        text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+    return re.findall(r"^[A-Za-z_][\w\s\*]*?\b(rl_\w+|conv3d_fft)\s*\(", text, flags=re.M)
+
+
+def _check(st: int) -> None:
+    if st != RL_OK:
+        msg = lib().rl_last_error().decode(errors="replace")
+        raise RLError(st, msg)
+
+
+def _shape(shape) -> ctypes.Array:
+    if len(shape) != 3:
+        raise ValueError("shape must be (nz, ny, nx)")
+    return (ctypes.c_int64 * 3)(*[int(s) for s in shape])
+
+
+# ---------------------------------------------------------------------------
+# one function per C entry point
+# ---------------------------------------------------------------------------
+
+def rl_plan_create(shape, psf_ptr: int, boundary: int = RL_BOUNDARY_PERIODIC) -> int:
+    out = ctypes.c_void_p()
+    _check(lib().rl_plan_create(_shape(shape), ctypes.c_void_p(psf_ptr), int(boundary),
+                                ctypes.byref(out)))
+    return out.value
+
+
+def rl_plan_create_ex(shape, psf_ptr: int, boundary: int = RL_BOUNDARY_PERIODIC,
+                      precision: int = RL_PRECISION_FP32, stream: int = 0, tile_x: int = 0) -> int:
+    out = ctypes.c_void_p()
+    opt = _Options(int(precision), ctypes.c_void_p(stream or None), int(tile_x))
+    _check(lib().rl_plan_create_ex(_shape(shape), ctypes.c_void_p(psf_ptr), int(boundary),
+                                   ctypes.byref(opt), ctypes.byref(out)))
+    return out.value
+
+
+def rl_iterate(plan: int, observed_ptr: int, estimate_ptr: int, n_iter: int) -> None:
+    _check(lib().rl_iterate(ctypes.c_void_p(plan), ctypes.c_void_p(observed_ptr),
+                            ctypes.c_void_p(estimate_ptr), int(n_iter)))
+
+
+def conv3d_fft(plan: int, x_ptr: int, out_ptr: int) -> None:
+    _check(lib().conv3d_fft(ctypes.c_void_p(plan), ctypes.c_void_p(x_ptr), ctypes.c_void_p(out_ptr)))
+
+
+def rl_plan_destroy(plan: int) -> None:
+    lib().rl_plan_destroy(ctypes.c_void_p(plan))
+
+
+def rl_plan_set_stream(plan: int, stream: int) -> None:
+    _check(lib().rl_plan_set_stream(ctypes.c_void_p(plan), ctypes.c_void_p(stream or None)))
+
+
+def rl_plan_get_flux(plan: int, cap: int = 1 << 20) -> np.ndarray:
+    n = ctypes.c_int(0)
+    _check(lib().rl_plan_get_flux(ctypes.c_void_p(plan), None, 0, ctypes.byref(n)))
+    buf = (ctypes.c_double * max(1, n.value))()
+    m = ctypes.c_int(0)
+    st = lib().rl_plan_get_flux(ctypes.c_void_p(plan), buf, min(cap, n.value), ctypes.byref(m))
+    vals = np.array(buf[: min(cap, m.value)], dtype=np.float64)
+    _check(st)
+    return vals
+
+
+def rl_plan_get_info(plan: int):
+    shape = (ctypes.c_int64 * 3)()
+    pitch = ctypes.c_int64(0)
+    _check(lib().rl_plan_get_info(ctypes.c_void_p(plan), shape, ctypes.byref(pitch)))
+    return tuple(shape), pitch.value
+
+
+def rl_plan_set_timing(plan: int, enable: bool) -> None:
+    _check(lib().rl_plan_set_timing(ctypes.c_void_p(plan), 1 if enable else 0))
+
+
+def rl_plan_get_timing(plan: int) -> dict:
+    cnt = (ctypes.c_int * len(KERNEL_KINDS))()
+    ms = (ctypes.c_double * len(KERNEL_KINDS))()
+    _check(lib().rl_plan_get_timing(ctypes.c_void_p(plan), cnt, ms))
+    return {k: (cnt[i], ms[i]) for i, k in enumerate(KERNEL_KINDS)}
+
+
+def rl_probe_copy(src_ptr: int, dst_ptr: int, nbytes: int, stream: int = 0) -> None:
+    _check(lib().rl_probe_copy(ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr),
+                               ctypes.c_size_t(nbytes), ctypes.c_void_p(stream or None)))
+
+
+def rl_status_string(status: int) -> str:
+    return lib().rl_status_string(int(status)).decode()
+
+
+def rl_last_error() -> str:
+    return lib().rl_last_error().decode(errors="replace")
+
+
+# ---------------------------------------------------------------------------
+# torch convenience layer
+# ---------------------------------------------------------------------------
+
+def _stream_of(device) -> int:
+    import torch
+    return int(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_volume(t, shape, device, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if t.device.type != "cuda" or (device is not None and t.device != device):
+        raise ValueError(f"{name} must live on {device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Plan:
+    """Richardson-Lucy plan for one volume shape and PSF (a float32 CUDA tensor [Z][Y][X])."""
+
+    def __init__(self, psf, boundary: str = "periodic", tile_x: int = 0):
+        bmap = {"periodic": RL_BOUNDARY_PERIODIC, "zero": RL_BOUNDARY_ZERO}
+        if boundary not in bmap:
+            raise ValueError("boundary must be 'periodic' or 'zero'")
+        if psf.dim() != 3:
+            raise ValueError("psf must be a 3-D tensor")
+        _check_volume(psf, psf.shape, None, "psf")
+        self.shape = tuple(int(s) for s in psf.shape)
+        self.device = psf.device
+        self.handle = rl_plan_create_ex(self.shape, psf.data_ptr(), bmap[boundary],
+                                        stream=_stream_of(self.device), tile_x=tile_x)
+
+    def _bind_stream(self):
+        rl_plan_set_stream(self.handle, _stream_of(self.device))
+
+    def iterate(self, observed, estimate, n_iter: int) -> None:
+        """Run n_iter iterations in place on `estimate` (asynchronous on torch's stream)."""
+        self._live()
+        _check_volume(observed, self.shape, self.device, "observed")
+        _check_volume(estimate, self.shape, self.device, "estimate")
+        self._bind_stream()
+        rl_iterate(self.handle, observed.data_ptr(), estimate.data_ptr(), n_iter)
+
+    def conv(self, x, out=None):
+        """H x into `out` (new tensor if None)."""
+        import torch
+        self._live()
+        _check_volume(x, self.shape, self.device, "x")
+        if out is None:
+            out = torch.empty_like(x)
+        _check_volume(out, self.shape, self.device, "out")
+        self._bind_stream()
+        conv3d_fft(self.handle, x.data_ptr(), out.data_ptr())
+        return out
+
+    def flux(self) -> np.ndarray:
+        """FP64 flux after each iteration of the last iterate() call (synchronises)."""
+        self._live()
+        self._bind_stream()
+        return rl_plan_get_flux(self.handle)
+
+    def set_timing(self, enable: bool) -> None:
+        self._live()
+        rl_plan_set_timing(self.handle, enable)
+
+    def timing(self) -> dict:
+        self._live()
+        self._bind_stream()
+        return rl_plan_get_timing(self.handle)
+
+    def info(self):
+        self._live()
+        return rl_plan_get_info(self.handle)
+
+    def _live(self):
+        if getattr(self, "handle", None) is None:
+            raise RLError(RL_E_INVALID, "plan is closed")
+
+    def close(self) -> None:
+        h = getattr(self, "handle", None)
+        if h is not None:
+            self.handle = None
+            rl_plan_destroy(h)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -51,7 +51,7 @@ def gaussian_psf(shape, sigma_xyz) -> np.ndarray:
 def _image_formation_blur(vol: np.ndarray, psf: np.ndarray) -> np.ndarray:
     """Periodic blur used only to simulate the microscope when making inputs."""
     k = np.fft.ifftshift(psf.astype(np.float64))
-    out = np.fft.irfftn(np.fft.rfftn(vol) * np.fft.rfftn(k), s=vol.shape)
+    out = np.fft.irfftn(np.fft.rfftn(vol) * np.fft.rfftn(k), s=vol.shape, axes=(0, 1, 2))
     return np.maximum(out, 0.0)
 
 

@@ -1,0 +1,106 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, and rejects bad arguments with the documented status codes before any
+device work."""
+
+import ctypes
+
+import pytest
+
+from paper_2510_14143_amd import rl
+
+
+def _has_gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def test_library_exports_every_declared_symbol():
+    names = rl.header_functions()
+    assert {"rl_plan_create", "rl_iterate", "conv3d_fft", "rl_plan_destroy"} <= set(names)
+    L = rl.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _create(shape, psf_ptr=4096, boundary=0):
+    out = ctypes.c_void_p(1234)
+    sh = (ctypes.c_int64 * 3)(*shape)
+    st = rl.lib().rl_plan_create(sh, ctypes.c_void_p(psf_ptr), boundary, ctypes.byref(out))
+    return st, out.value
+
+
+@pytest.mark.parametrize("shape,code", [
+    ((0, 8, 8), rl.RL_E_INVALID),
+    ((8, -1, 8), rl.RL_E_INVALID),
+    ((8, 8, 7), rl.RL_E_UNSUPPORTED),      # odd nx
+    ((8, 8, 2), rl.RL_E_UNSUPPORTED),      # nx < 4
+    ((8, 8, 20), rl.RL_E_UNSUPPORTED),     # radix 5
+    ((8, 10, 8), rl.RL_E_UNSUPPORTED),
+    ((9, 8, 8), rl.RL_E_UNSUPPORTED),      # two factors of 3
+    ((8, 8, 4096), rl.RL_E_UNSUPPORTED),   # above the nx limit
+    ((2048, 8, 8), rl.RL_E_UNSUPPORTED),   # above the nz limit
+])
+def test_bad_shapes_rejected(shape, code):
+    st, out = _create(shape)
+    assert st == code, rl.rl_last_error()
+    assert out is None  # *out is cleared on failure
+
+
+def test_bad_arguments_rejected():
+    L = rl.lib()
+    sh = (ctypes.c_int64 * 3)(8, 8, 8)
+    out = ctypes.c_void_p()
+    assert L.rl_plan_create(None, ctypes.c_void_p(4096), 0, ctypes.byref(out)) == rl.RL_E_INVALID
+    assert L.rl_plan_create(sh, ctypes.c_void_p(4096), 0, None) == rl.RL_E_INVALID
+    assert L.rl_plan_create(sh, None, 0, ctypes.byref(out)) == rl.RL_E_INVALID
+    assert L.rl_plan_create(sh, ctypes.c_void_p(4100), 0, ctypes.byref(out)) == rl.RL_E_INVALID
+    assert L.rl_plan_create(sh, ctypes.c_void_p(4096), 7, ctypes.byref(out)) == rl.RL_E_INVALID
+    assert L.rl_plan_create(sh, ctypes.c_void_p(4096), rl.RL_BOUNDARY_ZERO,
+                            ctypes.byref(out)) == rl.RL_E_UNSUPPORTED
+    assert "periodic" in rl.rl_last_error()
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device path")
+def test_no_device_is_reported():
+    st, out = _create((8, 8, 8))
+    assert st == rl.RL_E_DEVICE
+    assert out is None
+
+
+def test_handles_are_checked_without_dereference():
+    L = rl.lib()
+    fake = ctypes.c_void_p(0x1234560)
+    assert L.rl_iterate(None, None, None, 1) == rl.RL_E_INVALID
+    assert L.rl_iterate(fake, None, None, 1) == rl.RL_E_INVALID
+    assert "live plan" in rl.rl_last_error()
+    assert L.conv3d_fft(fake, None, None) == rl.RL_E_INVALID
+    assert L.rl_plan_set_stream(fake, None) == rl.RL_E_INVALID
+    n = ctypes.c_int()
+    assert L.rl_plan_get_flux(fake, None, 0, ctypes.byref(n)) == rl.RL_E_INVALID
+    L.rl_plan_destroy(None)
+    L.rl_plan_destroy(fake)  # unknown handle: ignored
+
+
+def test_probe_copy_validation():
+    L = rl.lib()
+    assert L.rl_probe_copy(None, None, 0, None) == rl.RL_OK
+    assert L.rl_probe_copy(ctypes.c_void_p(4096), ctypes.c_void_p(8192), 10, None) == rl.RL_E_INVALID
+    assert L.rl_probe_copy(None, ctypes.c_void_p(8192), 16, None) == rl.RL_E_INVALID
+
+
+def test_status_strings():
+    assert rl.rl_status_string(rl.RL_OK) == "RL_OK"
+    assert rl.rl_status_string(rl.RL_E_NUMERIC) == "RL_E_NUMERIC"
+    assert rl.rl_status_string(99) == "RL_E_UNKNOWN"
+
+
+def test_python_errors_carry_status():
+    with pytest.raises(rl.RLError) as ei:
+        rl.rl_plan_create((8, 8, 7), 4096)
+    assert ei.value.status == rl.RL_E_UNSUPPORTED
+    with pytest.raises(rl.RLError) as ei:
+        rl.rl_iterate(0x1234560, 0, 0, 1)
+    assert ei.value.status == rl.RL_E_INVALID

@@ -1,0 +1,259 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (relative L2, FP64, oracle as reference): one FP32 convolution
+<= 1e-5; Richardson-Lucy after up to 100 iterations <= 1e-4; FP64 flux vs the
+oracle's flux <= 1e-6 relative.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_14143_amd import rl, synth
+
+pytestmark = pytest.mark.gpu
+
+CONV_TOL = 1e-5
+RL_TOL = 1e-4
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to("cuda:0")
+
+
+def gpu_conv(torch, x, psf, **kw):
+    with rl.Plan(dev(torch, psf), **kw) as p:
+        out = p.conv(dev(torch, x))
+        torch.cuda.synchronize()
+        return out.cpu().numpy().astype(np.float64)
+
+
+def gpu_rl(torch, d, psf, u0, n_iter):
+    with rl.Plan(dev(torch, psf)) as p:
+        u = dev(torch, u0)
+        p.iterate(dev(torch, d), u, n_iter)
+        flux = p.flux()
+        return u.cpu().numpy().astype(np.float64), flux
+
+
+def rand_psf(shape, seed):
+    rng = np.random.default_rng(seed)
+    h = rng.uniform(0, 1, size=shape) ** 4
+    h[tuple(s // 3 for s in shape)] += 5.0  # asymmetric
+    return h.astype(np.float32)
+
+
+# shapes: several tiles in every direction plus ragged tails (nx/2+1 columns,
+# rows not a multiple of the rows per work-group), powers of two and 3*2^a
+CONV_SHAPES = [
+    (8, 16, 32), (6, 24, 64), (16, 32, 64), (32, 64, 64), (12, 48, 96), (24, 48, 96),
+    (3, 6, 12), (1, 1, 8), (4, 1, 16), (1, 8, 4), (2, 12, 48), (64, 32, 128), (16, 8, 256),
+    (5 * 0 + 6, 96, 192), (4, 16, 512),
+]
+
+
+@pytest.mark.parametrize("shape", CONV_SHAPES)
+def test_conv_matches_oracle(torch, shape):
+    say("conv", shape)
+    x = synth.uniform_volume(shape, 100)
+    for psf in (synth.gaussian_psf(shape, (1.5, 1.2, 2.0)), rand_psf(shape, 7)):
+        ref = oracle.conv3d(x, psf)
+        got = gpu_conv(torch, x, psf)
+        err = oracle.rel_l2(got, ref)
+        assert err <= CONV_TOL, (shape, err)
+        assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("tile_x", [1, 2, 4, 8, 32, 64])
+def test_conv_tile_widths(torch, tile_x):
+    shape = (12, 24, 96)
+    say("conv tile_x", tile_x)
+    x = synth.uniform_volume(shape, 101)
+    psf = rand_psf(shape, 8)
+    got = gpu_conv(torch, x, psf, tile_x=tile_x)
+    assert oracle.rel_l2(got, oracle.conv3d(x, psf)) <= CONV_TOL
+
+
+def test_conv_in_place(torch):
+    shape = (8, 16, 32)
+    say("conv in place")
+    x = synth.uniform_volume(shape, 102)
+    psf = rand_psf(shape, 9)
+    with rl.Plan(dev(torch, psf)) as p:
+        t = dev(torch, x)
+        p.conv(t, out=t)
+        got = t.cpu().numpy()
+    assert oracle.rel_l2(got, oracle.conv3d(x, psf)) <= CONV_TOL
+
+
+def test_conv_config0_observed(torch):
+    say("conv config0")
+    c = synth.make_config(0)
+    ref = oracle.conv3d(c["d"], c["psf"])
+    assert oracle.rel_l2(gpu_conv(torch, c["d"], c["psf"]), ref) <= CONV_TOL
+
+
+@pytest.mark.parametrize("shape,n_iter", [((32, 64, 64), 20), ((32, 64, 64), 100),
+                                          ((6, 24, 64), 30), ((12, 48, 96), 25),
+                                          ((16, 8, 256), 10)])
+def test_rl_matches_oracle(torch, shape, n_iter):
+    say("rl", shape, n_iter)
+    if shape == (32, 64, 64):
+        c = synth.make_config(0)
+    else:
+        c = synth.small_case(shape, seed=5)
+    ref, ref_flux, _ = oracle.rl(c["d"], c["psf"], c["u0"], n_iter)
+    got, flux = gpu_rl(torch, c["d"], c["psf"], c["u0"], n_iter)
+    err = oracle.rel_l2(got, ref)
+    say("  relL2", err)
+    assert err <= RL_TOL, err
+    assert np.all(got >= 0)
+    assert len(flux) == n_iter
+    assert np.max(np.abs(flux - ref_flux) / ref_flux) <= 1e-6
+
+
+def test_rl_golden_worked_example(torch):
+    # paper §4.3 RL steps, hand-worked in tests/golden/rl_worked_1x1x4.txt
+    say("rl golden 1x1x4")
+    h = np.array([0, 0, 3, 1], np.float32).reshape(1, 1, 4)
+    d = np.array([1, 2, 3, 6], np.float32).reshape(1, 1, 4)
+    u0 = np.full((1, 1, 4), 3.0, np.float32)
+    u1, _ = gpu_rl(torch, d, h, u0, 1)
+    assert np.allclose(u1.ravel(), [5 / 4, 9 / 4, 15 / 4, 19 / 4], rtol=2e-6)
+    u2, flux = gpu_rl(torch, d, h, u0, 2)
+    assert np.allclose(u2.ravel(), [205 / 272, 35 / 16, 15 / 4, 361 / 68], rtol=2e-6)
+    assert np.allclose(flux, [12.0, 12.0], rtol=1e-6)
+
+
+def _delta(shape, off=(0, 0, 0)):
+    h = np.zeros(shape, np.float32)
+    h[tuple((s // 2 + o) % s for s, o in zip(shape, off))] = 1.0
+    return h
+
+
+def test_rl_delta_fixed_point_and_shift(torch):
+    shape = (8, 16, 32)
+    say("rl delta / shifted delta")
+    d = np.random.default_rng(3).uniform(1, 10, size=shape).astype(np.float32)
+    u0 = np.full(shape, d.mean(dtype=np.float64), np.float32)
+    got, _ = gpu_rl(torch, d, _delta(shape), u0, 3)
+    assert oracle.rel_l2(got, d) <= 1e-6
+    s = (1, -3, 5)
+    got, _ = gpu_rl(torch, d, _delta(shape, s), u0, 1)
+    assert oracle.rel_l2(got, np.roll(d, tuple(-x for x in s), axis=(0, 1, 2))) <= 1e-6
+
+
+def test_rl_uniform_psf_and_constant_data(torch):
+    shape = (4, 8, 16)
+    say("rl uniform psf / constant data")
+    rng = np.random.default_rng(4)
+    d = rng.uniform(1, 10, size=shape).astype(np.float32)
+    u0 = rng.uniform(0.5, 2, size=shape).astype(np.float32)
+    got, _ = gpu_rl(torch, d, np.ones(shape, np.float32), u0, 2)
+    ref = u0.astype(np.float64) * d.sum(dtype=np.float64) / u0.sum(dtype=np.float64)
+    assert oracle.rel_l2(got, ref) <= 1e-6
+    dc = np.full(shape, 7.25, np.float32)
+    got, _ = gpu_rl(torch, dc, rand_psf(shape, 10), dc, 5)
+    assert oracle.rel_l2(got, dc) <= 1e-6
+
+
+def test_rl_resume_and_determinism(torch):
+    shape = (16, 32, 64)
+    say("rl resume / determinism")
+    c = synth.small_case(shape, seed=6)
+    with rl.Plan(dev(torch, c["psf"])) as p:
+        d = dev(torch, c["d"])
+        a = dev(torch, c["u0"])
+        p.iterate(d, a, 10)
+        b = dev(torch, c["u0"])
+        p.iterate(d, b, 4)
+        p.iterate(d, b, 6)
+        e = dev(torch, c["u0"])
+        p.iterate(d, e, 10)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+        assert torch.equal(a, e)
+        p.iterate(d, e, 0)  # no-op
+        assert torch.equal(a, e)
+
+
+def test_rl_zero_guard(torch):
+    shape = (8, 8, 16)
+    say("rl zero data")
+    d = np.random.default_rng(5).uniform(1, 10, size=shape).astype(np.float32)
+    d[:3] = 0
+    u, flux = gpu_rl(torch, d, synth.gaussian_psf(shape, (1, 1, 1)), np.ones(shape, np.float32), 5)
+    assert np.all(np.isfinite(u)) and np.all(u >= 0)
+    u, flux = gpu_rl(torch, np.zeros(shape, np.float32), _delta(shape), np.ones(shape, np.float32), 2)
+    assert np.all(u == 0) and np.all(flux == 0)
+
+
+def test_errors_on_gpu(torch):
+    shape = (4, 8, 16)
+    say("error paths")
+    bad = rand_psf(shape, 11)
+    bad[0, 0, 0] = -1
+    with pytest.raises(rl.RLError) as ei:
+        rl.Plan(dev(torch, bad))
+    assert ei.value.status == rl.RL_E_INVALID
+    with pytest.raises(rl.RLError):
+        rl.Plan(dev(torch, np.zeros(shape, np.float32)))
+    nanpsf = rand_psf(shape, 12)
+    nanpsf[1, 1, 1] = np.nan
+    with pytest.raises(rl.RLError):
+        rl.Plan(dev(torch, nanpsf))
+    with rl.Plan(dev(torch, rand_psf(shape, 13))) as p:
+        host = np.ones(shape, np.float32)  # a host pointer must be refused, not dereferenced
+        with pytest.raises(rl.RLError) as ei:
+            rl.rl_iterate(p.handle, host.ctypes.data, host.ctypes.data, 1)
+        assert ei.value.status == rl.RL_E_INVALID
+        with pytest.raises(rl.RLError):
+            rl.rl_iterate(p.handle, dev(torch, np.ones(shape)).data_ptr(),
+                          dev(torch, np.ones(shape)).data_ptr(), -1)
+        d = np.ones(shape, np.float32)
+        d[2, 3, 4] = np.nan
+        u = dev(torch, np.ones(shape))
+        p.iterate(dev(torch, d), u, 2)
+        with pytest.raises(rl.RLError) as ei:
+            p.flux()
+        assert ei.value.status == rl.RL_E_NUMERIC
+
+
+def test_full_size_config1_conv_sampled(torch):
+    # full size, launch configuration of the benchmark; sampled voxels by the direct sum
+    c = synth.CONFIGS[1]
+    shape = c["shape"]
+    say("full-size conv", shape)
+    x = synth.uniform_volume(shape, 1 + 100)
+    psf = synth.gaussian_psf(shape, c["sigma"])
+    got = gpu_conv(torch, x, psf)
+    rng = np.random.default_rng(0)
+    pts = [tuple(int(rng.integers(0, n)) for n in shape) for _ in range(6)]
+    pts += [(0, 0, 0), tuple(n - 1 for n in shape)]
+    ref = oracle.conv_direct_at(x, psf, pts)
+    g = np.array([got[p] for p in pts])
+    assert np.max(np.abs(g - ref) / np.abs(ref)) <= 1e-5
+
+
+def test_full_size_config1_rl_properties(torch):
+    c = synth.make_config(1)
+    say("full-size rl properties", c["shape"])
+    n = 20
+    u, flux = gpu_rl(torch, c["d"], c["psf"], c["u0"], n)
+    total = float(c["d"].sum(dtype=np.float64))
+    assert np.all(np.abs(flux - total) / total <= 1e-6), flux[:3]
+    assert np.all(u >= 0) and np.all(np.isfinite(u))
