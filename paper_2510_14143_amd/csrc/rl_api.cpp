@@ -393,15 +393,17 @@ rl_status create_impl(const int64_t shape[3], const float* psf, int boundary,
   p->axx.E = pick_e(p->M);
   p->axx.P = (int)(p->M / p->axx.E);
   p->axx.sc = make_sched(p->M, p->axx.E, 2);
-  p->x_rpw = rlmi::kXMaxThreads / p->axx.P;
-  if (p->x_rpw < 1) p->x_rpw = 1;
+  // each wavefront owns 64 / P whole rows; up to kXMaxThreads / 64 waves per work-group
+  const int rows_per_wave = 64 / p->axx.P;
+  int waves = rlmi::kXMaxThreads / 64;
   p->x_rs = (int)(p->M + 1);
-  p->x_lds = (size_t)(2 * p->M + (int64_t)p->x_rpw * p->x_rs) * sizeof(float2);
-  while (p->x_lds > kMaxLds && p->x_rpw > 1) {
-    p->x_rpw >>= 1;
-    p->x_lds = (size_t)(2 * p->M + (int64_t)p->x_rpw * p->x_rs) * sizeof(float2);
-  }
-  p->x_block = dim3((unsigned)(p->x_rpw * p->axx.P));
+  auto x_lds_for = [&](int w) {
+    return (size_t)(2 * p->M + (int64_t)w * rows_per_wave * p->x_rs) * sizeof(float2);
+  };
+  while (waves > 1 && x_lds_for(waves) > kMaxLds) waves >>= 1;
+  p->x_rpw = waves * rows_per_wave;
+  p->x_lds = x_lds_for(waves);
+  p->x_block = dim3((unsigned)(64 * waves));
   p->x_grid = dim3((unsigned)((p->nrows + p->x_rpw - 1) / p->x_rpw));
   // Y: pencils along Y, outer = z; Z: pencils along Z, outer = y
   const int tile_x = opt ? opt->tile_x : 0;
@@ -416,9 +418,9 @@ rl_status create_impl(const int64_t shape[3], const float* psf, int boundary,
     delete p;
     return hip_fail(e, "hipSetDevice");
   }
-  p->n_partials = p->x_grid.x;
+  p->flux_cap = 128;
+  p->n_partials = (size_t)p->x_grid.x * p->flux_cap;
   if (p->n_partials < 3 * (size_t)kStatBlocks) p->n_partials = 3 * kStatBlocks;
-  p->flux_cap = 1024;
   const size_t spec_bytes = p->spec_elems * sizeof(float2);
   if ((e = hipMalloc(&p->spec, spec_bytes)) != hipSuccess ||
       (e = hipMalloc(&p->otf, spec_bytes)) != hipSuccess ||
@@ -499,13 +501,23 @@ rl_status iterate_impl(rl_plan p, const float* observed, float* estimate, int n_
   hipError_t e = hipSetDevice(p->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   if (n_iter > p->flux_cap) {
+    // grow the flux array and the [iteration][work-group] partial table
     double* nf = nullptr;
+    double* np = nullptr;
+    const size_t nparts = (size_t)n_iter * p->x_grid.x;
     if ((e = hipMalloc(&nf, (size_t)n_iter * sizeof(double))) != hipSuccess)
       return hip_fail(e, "hipMalloc(flux)");
+    if ((e = hipMalloc(&np, nparts * sizeof(double))) != hipSuccess) {
+      (void)hipFree(nf);
+      return hip_fail(e, "hipMalloc(flux partials)");
+    }
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     else (void)hipDeviceSynchronize();
     (void)hipFree(p->flux);
+    (void)hipFree(p->partials);
     p->flux = nf;
+    p->partials = np;
+    p->n_partials = nparts;
     p->flux_cap = n_iter;
   }
   p->flux_count = n_iter;
@@ -524,14 +536,17 @@ rl_status iterate_impl(rl_plan p, const float* observed, float* estimate, int n_
     XArgs u = base_xargs(p, p->spec);
     u.u = estimate;
     u.partials = p->partials;
-    u.counter = p->counter;
-    u.flux = p->flux;
     u.iter = it;
     u.do_fwd = (it + 1 < n_iter) ? 1 : 0;
     if ((st = run_x(p, rlmi::XM_UPDATE, u, RL_KERNEL_X_UPDATE)) != RL_OK) return st;
     if (u.do_fwd && (st = run_yz_filter(p, false)) != RL_OK) return st;
   }
-  return RL_OK;
+  size_t slot = 0;
+  if ((st = timed_begin(p, RL_KERNEL_OTHER, &slot)) != RL_OK) return st;
+  if ((e = rlmi::launch_flux_reduce(p->partials, (int)p->x_grid.x, n_iter, p->flux, p->stream)) !=
+      hipSuccess)
+    return hip_fail(e, "flux reduction launch");
+  return timed_end(p, slot);
 }
 
 rl_status conv_impl(rl_plan p, const float* x, float* out) {

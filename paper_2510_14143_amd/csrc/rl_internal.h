@@ -50,14 +50,12 @@ struct XArgs {
   long long rout_stride;
   const float* d;        // XM_RATIO: observed rows (dense, nx floats apart)
   float* u;              // XM_UPDATE: estimate rows (dense), updated in place
-  double* partials;      // XM_UPDATE: one FP64 partial flux per work-group
-  unsigned* counter;     // XM_UPDATE: arrival counter (0 between launches)
-  double* flux;          // XM_UPDATE: flux[iter] receives the total
+  double* partials;      // XM_UPDATE: FP64 partial flux, [iter][work-group]
   int iter;
   int do_fwd;            // XM_UPDATE: also transform the new estimate forward
   int M;                 // complex row length nx/2
   int P;                 // threads per row (M / E)
-  int RPW;               // rows per work-group
+  int RPW;               // rows per work-group (a multiple of 64 / P)
   int RS;                // LDS row stride in complex elements (>= M + 1)
   int nrows;             // nz * ny
 };
@@ -68,6 +66,9 @@ hipError_t launch_pencil(int mode, int E, dim3 grid, dim3 block, size_t lds, hip
 hipError_t launch_xrow(int mode, int E, dim3 grid, dim3 block, size_t lds, hipStream_t s,
                        const XArgs& a, const Sched& sc, const float2* tw);
 hipError_t launch_twiddles(float2* tab, int n, hipStream_t s);
+// flux[it] = sum_g partials[it * groups + g] for it < n_iter, summed in a fixed order.
+hipError_t launch_flux_reduce(const double* partials, int groups, int n_iter, double* flux,
+                              hipStream_t s);
 // out[0] = sum(h), out[1] = min(h), out[2] = number of non-finite entries (FP64).
 hipError_t launch_psf_stats(const float* h, long long n, double* partials, int nblk,
                             unsigned* counter, double* out, hipStream_t s);

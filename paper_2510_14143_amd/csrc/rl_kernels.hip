@@ -169,9 +169,25 @@ __device__ __forceinline__ void stage(float2 (&v)[E], int i, int P, int p, int t
   }
 }
 
+// Ordering point for LDS traffic that stays inside one wavefront: the lanes of
+// a wave execute in lock step and a wave's LDS operations complete in issue
+// order, so only the compiler must be kept from moving accesses across it.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool WAVE>
+__device__ __forceinline__ void exch_sync() {
+  if constexpr (WAVE) wave_sync();
+  else __syncthreads();
+}
+
 // Full 1-D transform of this thread's pencil; natural order in and out.
-// Every thread of the work-group must call it (it contains barriers).
-template <int E, int S>
+// WAVE = false: the pencil spans the work-group and every thread must call this
+// (it contains barriers).  WAVE = true: the pencil lives inside one wavefront.
+template <int E, int S, bool WAVE = false>
 __device__ __forceinline__ void fft(float2 (&v)[E], const Sched& sc, int i, int P,
                                     const float2* __restrict__ tw, float2* lds, int ls, int lo) {
   for (int s = 0; s < sc.ns; ++s) {
@@ -197,10 +213,10 @@ __device__ __forceinline__ void fft(float2 (&v)[E], const Sched& sc, int i, int 
         break;
     }
     if (!last) {
-      __syncthreads();
+      exch_sync<WAVE>();
 #pragma unroll
       for (int m = 0; m < E; ++m) v[m] = lds[(i + P * m) * ls + lo];
-      __syncthreads();
+      exch_sync<WAVE>();
     }
   }
 }
@@ -248,17 +264,21 @@ __global__ void __launch_bounds__(kPencilMaxThreads) k_pencil(float2* __restrict
 // ---------------------------------------------------------------------------
 // X row pass (contiguous axis)
 // ---------------------------------------------------------------------------
+// Each wavefront owns whole rows (P = M/E lanes per row, 64/P rows per wave), so
+// every LDS exchange of a row is wave-local and needs no work-group barrier.
+// All global loads of a row (half spectrum and the real operand) are issued
+// before any arithmetic.
+
 // Forward: complex row z (registers, natural order) -> FFT -> split into the
-// half spectrum X[0..M] and store.  `row` points at this thread's LDS row.
+// half spectrum X[0..M] and store.  `row` is this row's wave-private LDS.
 template <int E>
-__device__ __forceinline__ void r2c_store(float2 (&v)[E], const XArgs& a, const Sched& sc, int i,
+__device__ __forceinline__ void r2c_store(float2 (&v)[E], int M, int P, const Sched& sc, int i,
                                           const float2* tw, float2* row, bool ok,
                                           float2* __restrict__ out) {
-  const int M = a.M, P = a.P;
-  fft<E, -1>(v, sc, i, P, tw, row, 1, 0);
+  fft<E, -1, true>(v, sc, i, P, tw, row, 1, 0);
 #pragma unroll
   for (int m = 0; m < E; ++m) row[i + P * m] = v[m];
-  __syncthreads();
+  wave_sync();
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int k = i + P * m;
@@ -273,6 +293,27 @@ __device__ __forceinline__ void r2c_store(float2 (&v)[E], const XArgs& a, const 
   if (ok && i == 0) out[M] = make_float2(v[0].x - v[0].y, 0.f);
 }
 
+// Pairs X[k] with X[M-k] and forms z[k] = A + iB, the half-length complex
+// spectrum whose inverse FFT interleaves the even and odd real samples.
+template <int E>
+__device__ __forceinline__ void c2r_prepare(float2 (&v)[E], float2 nyq, int M, int P, int i,
+                                            const float2* tw, float2* row) {
+#pragma unroll
+  for (int m = 0; m < E; ++m) row[i + P * m] = v[m];
+  if (i == 0) row[M] = nyq;
+  wave_sync();
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int k = i + P * m;
+    const float2 X = v[m];
+    const float2 Y = conjf2(row[M - k]);
+    const float2 A = cadd(X, Y);
+    const float2 B = cmulc(csub(X, Y), tw[k]);  // (X - conj X[M-k]) * exp(+2 pi i k / 2M)
+    v[m] = make_float2(A.x - B.y, A.y + B.x);   // A + i B
+  }
+  wave_sync();
+}
+
 template <int E, int MODE>
 __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const float2* __restrict__ twg) {
   extern __shared__ float2 lds[];
@@ -280,11 +321,14 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
   const int tid = threadIdx.x;
   float2* tw = lds;  // 2M entries: exp(-2 pi i k / (2M))
   for (int t = tid; t < 2 * M; t += blockDim.x) tw[t] = twg[t];
-  const int rl = tid / P, i = tid - rl * P;
-  const int rowi = blockIdx.x * a.RPW + rl;
-  const bool ok = (rl < a.RPW) && (rowi < a.nrows);
+  const int rpw = 64 / P;                       // rows per wavefront
+  const int wave = tid >> 6, lane = tid & 63;
+  const int rw = lane / P, i = lane - rw * P;
+  const int lrow = wave * rpw + rw;             // row within the work-group
+  const int rowi = blockIdx.x * a.RPW + lrow;
+  const bool ok = rowi < a.nrows;
   const long long rix = ok ? rowi : 0;
-  float2* row = lds + 2 * M + rl * a.RS;
+  float2* row = lds + 2 * M + lrow * a.RS;
   float2* srow = a.spec + rix * a.pitch;
 
   float2 v[E];
@@ -293,102 +337,87 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = ok ? in[i + P * m] : make_float2(0.f, 0.f);
     __syncthreads();  // twiddles in LDS
-    r2c_store<E>(v, a, sc, i, tw, row, ok, srow);
-    return;
+    r2c_store<E>(v, M, P, sc, i, tw, row, ok, srow);
   } else {
-    // stage the spectrum row in LDS, then pair X[k] with X[M-k]
+    // issue every global load of the row first
+    float2 w[(MODE == XM_RATIO || MODE == XM_UPDATE) ? E : 1];
 #pragma unroll
-    for (int m = 0; m < E; ++m) row[i + P * m] = ok ? srow[i + P * m] : make_float2(0.f, 0.f);
-    if (i == 0) row[M] = ok ? srow[M] : make_float2(0.f, 0.f);
-    __syncthreads();
+    for (int m = 0; m < E; ++m) v[m] = ok ? srow[i + P * m] : make_float2(0.f, 0.f);
+    const float2 nyq = (ok && i == 0) ? srow[M] : make_float2(0.f, 0.f);
+    if constexpr (MODE == XM_RATIO) {
+      const float2* dr = reinterpret_cast<const float2*>(a.d + rix * (2LL * M));
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int k = i + P * m;
-      const float2 X = row[k];
-      const float2 Y = conjf2(row[M - k]);
-      const float2 A = cadd(X, Y);
-      const float2 B = cmulc(csub(X, Y), tw[k]);  // (X - conj X[M-k]) * exp(+2 pi i k / 2M)
-      v[m] = make_float2(A.x - B.y, A.y + B.x);   // A + i B
+      for (int m = 0; m < E; ++m) w[m] = ok ? dr[i + P * m] : make_float2(0.f, 0.f);
+    } else if constexpr (MODE == XM_UPDATE) {
+      const float2* ur = reinterpret_cast<const float2*>(a.u + rix * (2LL * M));
+#pragma unroll
+      for (int m = 0; m < E; ++m) w[m] = ok ? ur[i + P * m] : make_float2(0.f, 0.f);
     }
-    __syncthreads();
-    fft<E, +1>(v, sc, i, P, tw, row, 1, 0);
-    // v[m] now holds (x[2n], x[2n+1]) for n = i + P*m (unnormalised; the 1/N is in the OTF)
+    __syncthreads();  // twiddles in LDS
+    c2r_prepare<E>(v, nyq, M, P, i, tw, row);
+    fft<E, +1, true>(v, sc, i, P, tw, row, 1, 0);
+    // v[m] holds (x[2n], x[2n+1]) for n = i + P*m (unnormalised; the 1/N is in the OTF)
     if constexpr (MODE == XM_C2R) {
       if (ok) {
         float2* out = reinterpret_cast<float2*>(a.rout + rix * a.rout_stride);
 #pragma unroll
         for (int m = 0; m < E; ++m) out[i + P * m] = v[m];
       }
-      return;
     } else if constexpr (MODE == XM_RATIO) {
-      const float2* dr = reinterpret_cast<const float2*>(a.d + rix * (2LL * M));
 #pragma unroll
       for (int m = 0; m < E; ++m) {
-        const float2 dv = ok ? dr[i + P * m] : make_float2(0.f, 0.f);
         const float2 q = v[m];
-        v[m] = make_float2(q.x > 1e-12f ? dv.x / q.x : 0.f, q.y > 1e-12f ? dv.y / q.y : 0.f);
+        v[m] = make_float2(q.x > 1e-12f ? w[m].x / q.x : 0.f, q.y > 1e-12f ? w[m].y / q.y : 0.f);
       }
-      __syncthreads();  // row buffer reuse
-      r2c_store<E>(v, a, sc, i, tw, row, ok, srow);
-      return;
+      wave_sync();  // row buffer reuse
+      r2c_store<E>(v, M, P, sc, i, tw, row, ok, srow);
     } else {  // XM_UPDATE
       float2* ur = reinterpret_cast<float2*>(a.u + rix * (2LL * M));
       double acc = 0.0;
 #pragma unroll
       for (int m = 0; m < E; ++m) {
-        const float2 uo = ok ? ur[i + P * m] : make_float2(0.f, 0.f);
         const float2 c = v[m];
-        // clamp c < 0 to 0; a NaN passes through (as max(c, 0) does in the oracle) so that
-        // non-finite inputs reach the flux check instead of being silently zeroed
-        const float2 un = make_float2(uo.x * (c.x < 0.f ? 0.f : c.x), uo.y * (c.y < 0.f ? 0.f : c.y));
+        // clamp c < 0 to 0; a NaN passes through (as max(c, 0) does in the oracle) so
+        // that non-finite inputs reach the flux check instead of being silently zeroed
+        const float2 un = make_float2(w[m].x * (c.x < 0.f ? 0.f : c.x),
+                                      w[m].y * (c.y < 0.f ? 0.f : c.y));
         if (ok) ur[i + P * m] = un;
         acc += (double)un.x + (double)un.y;
         v[m] = un;
       }
       if (a.do_fwd) {
-        __syncthreads();
-        r2c_store<E>(v, a, sc, i, tw, row, ok, srow);
+        wave_sync();
+        r2c_store<E>(v, M, P, sc, i, tw, row, ok, srow);
       }
-      // deterministic work-group sum: wavefront butterfly, then waves in order
+      // work-group partial of the flux: wavefront butterfly, then the waves in order
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-      __shared__ double wsum[16];
-      __shared__ bool last_block;
-      __syncthreads();
-      if ((tid & 63) == 0) wsum[tid >> 6] = acc;
+      __shared__ double wsum[kXMaxThreads / 64];
+      if (lane == 0) wsum[wave] = acc;
       __syncthreads();
       if (tid == 0) {
         double t = 0.0;
-        const int nw = (blockDim.x + 63) >> 6;
-        for (int w = 0; w < nw; ++w) t += wsum[w];
-        a.partials[blockIdx.x] = t;
-        __threadfence();
-        const unsigned done = atomicAdd(a.counter, 1u);
-        last_block = (done == gridDim.x - 1);
-      }
-      __syncthreads();
-      if (last_block) {
-        __threadfence();
-        const unsigned long long* pp = reinterpret_cast<const unsigned long long*>(a.partials);
-        double t = 0.0;
-        for (unsigned g = tid; g < gridDim.x; g += blockDim.x)
-          t += __longlong_as_double((long long)__hip_atomic_load(
-              pp + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-        __syncthreads();
-        if ((tid & 63) == 0) wsum[tid >> 6] = t;
-        __syncthreads();
-        if (tid == 0) {
-          double s = 0.0;
-          const int nw = (blockDim.x + 63) >> 6;
-          for (int w = 0; w < nw; ++w) s += wsum[w];
-          a.flux[a.iter] = s;
-          __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        const int nw = blockDim.x >> 6;
+        for (int q = 0; q < nw; ++q) t += wsum[q];
+        a.partials[(long long)a.iter * gridDim.x + blockIdx.x] = t;
       }
     }
   }
+}
+
+// flux[it] = sum of the work-group partials of iteration it, in a fixed order.
+__global__ void __launch_bounds__(256) k_flux_reduce(const double* __restrict__ partials, int groups,
+                                                     double* __restrict__ flux) {
+  const int it = blockIdx.x, tid = threadIdx.x;
+  const double* p = partials + (long long)it * groups;
+  double t = 0.0;
+  for (int g = tid; g < groups; g += blockDim.x) t += p[g];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+  __shared__ double ws[4];
+  if ((tid & 63) == 0) ws[tid >> 6] = t;
+  __syncthreads();
+  if (tid == 0) flux[it] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
 }
 
 // ---------------------------------------------------------------------------
@@ -546,6 +575,12 @@ hipError_t launch_xrow(int mode, int E, dim3 grid, dim3 block, size_t lds, hipSt
     case XM_UPDATE: return xrow_e<XM_UPDATE>(E, grid, block, lds, s, a, sc, tw);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_flux_reduce(const double* partials, int groups, int n_iter, double* flux,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_flux_reduce, dim3(n_iter), dim3(256), 0, s, partials, groups, flux);
+  return hipGetLastError();
 }
 
 hipError_t launch_twiddles(float2* tab, int n, hipStream_t s) {
