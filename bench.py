@@ -141,6 +141,24 @@ def run_workload(torch, rl, synth, cfg: int, steps: int, warmup: int, workload: 
                 bytes_per_vi=round(model_bytes / (nvox * n_iter), 2))
 
 
+def copy_probe(torch, rl, nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Plain streaming copy kernel of the library: read + write bytes per second (GB/s)."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    stream = int(torch.cuda.current_stream().cuda_stream)
+    rl.rl_probe_copy(src.data_ptr(), dst.data_ptr(), nbytes, stream)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        rl.rl_probe_copy(src.data_ptr(), dst.data_ptr(), nbytes, stream)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(synth, n_iter_sample: int = 4):
     """The FP64 oracle on the host cores, bounded sample of the headline workload."""
     import oracle
@@ -178,6 +196,8 @@ def main():
     import torch
     from paper_2510_14143_amd import rl, synth
 
+    copy_gbs = copy_probe(torch, rl)
+    log(f"copy probe: {copy_gbs:.1f} GB/s (read + write)")
     log("workload: config 1 (128x256x256, 100 it)")
     main_run = run_workload(torch, rl, synth, 1, args.steps, args.warmup, "cfg1")
     log(json.dumps({"cfg1_per_kind": main_run["per_kind"]}))
@@ -217,6 +237,7 @@ def main():
         "bytes_per_vi": main_run["bytes_per_vi"],
         "flux_drift": main_run["flux_drift"],
         "large": large,
+        "copy_probe_gbs": round(copy_gbs, 1),
     }
     if rank == 0:
         print(json.dumps(out), flush=True)

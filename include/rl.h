@@ -67,7 +67,13 @@ typedef enum {
 typedef struct {
   int precision;  /* rl_precision */
   void* stream;   /* hipStream_t to enqueue on; NULL = null stream */
-  int tile_x;     /* columns per work-group in the Y/Z passes; 0 = library default */
+  int tile_x;     /* work-group width of the Y/Z passes in complex elements: 1..16 =
+                     columns of one 16-column tile, 32/64 = 2/4 whole tile rows (Z
+                     pass only); 0 = library default; out of range = RL_E_INVALID */
+  int x_elems;    /* elements per thread of the X-pass transforms (length nx/2); 0 =
+                     default; must divide nx/2 leaving a power-of-two thread count
+                     <= 64, and hold every factor 3 of nx/2 (else RL_E_INVALID) */
+  int yz_elems;   /* the same for the Y and Z transforms (lengths ny and nz) */
 } rl_options;
 
 /*
@@ -118,7 +124,8 @@ rl_status rl_plan_set_stream(rl_plan p, void* hip_stream);
  */
 rl_status rl_plan_get_flux(rl_plan p, double* flux, int cap, int* n_written);
 
-/* Shape {nz, ny, nx} and the half-spectrum row pitch (complex elements) of a plan. */
+/* Shape {nz, ny, nx} and the number of complex columns the plan stores per
+ * half-spectrum row (nx/2 + 1 rounded up to whole 16-column tiles). */
 rl_status rl_plan_get_info(rl_plan p, int64_t shape[3], int64_t* spectrum_pitch);
 
 /*

@@ -27,7 +27,8 @@ constexpr uint64_t kMagic = 0x31504c4d494c52ull;  // live plan
 constexpr uint64_t kDead = 0xdeadbeefdeadbeefull;
 constexpr int64_t kMaxNx = 2048;
 constexpr int64_t kMaxNyz = 1024;
-constexpr size_t kMaxLds = 65536;
+constexpr size_t kMaxLds = 65536;        // X pass work-group LDS budget
+constexpr size_t kMaxPencilLds = 163840;  // gfx950: 160 KB per work-group
 constexpr int kStatBlocks = 256;
 
 thread_local std::string g_err;
@@ -74,10 +75,44 @@ bool length_ok(int64_t L) {
   return is_pow2(L);
 }
 
+int64_t pow2_part(int64_t v) { return v & -v; }
+
+// A caller-chosen E for length L: divides L into a power-of-two thread count
+// <= max_p, carries every factor 3 of L, and leaves radices the schedule can use.
+bool e_ok(int64_t L, int E, int64_t max_p) {
+  static const int kE[] = {1, 2, 3, 4, 6, 8, 12, 16, 24};
+  bool known = false;
+  for (int k : kE) known = known || (k == E);
+  if (!known || L % E != 0) return false;
+  const int64_t P = L / E;
+  if (!is_pow2(P) || P > max_p) return false;
+  if (L % 3 == 0 && E % 3 != 0) return false;
+  if (E % 3 == 0 && L % 3 != 0) return false;
+  const int64_t l2 = pow2_part(L);
+  return l2 == 1 || pow2_part(E) >= 2;
+}
+
 int pick_e(int64_t L) {
   if (L == 1) return 1;
   if (is_pow2(L)) return (int)(L < 16 ? L : 16);
   return (int)(L < 24 ? L : 24);  // 3 * 2^a
+}
+
+// X pass: few elements per thread so that one row fills (up to) a wavefront;
+// the many short-lived waves hide the latency of the fused two-transform pass.
+int pick_e_x(int64_t M) {
+  if (is_pow2(M)) {
+    if (M <= 4) return (int)M;
+    return (int)(M / 4 <= 64 ? 4 : M / 64);
+  }
+  if (M <= 12) return (int)M;           // 3, 6, 12
+  return (int)(M / 12 <= 64 ? 12 : 24);  // 3 * 2^a
+}
+
+// Y pass: 8 elements per thread for power-of-two lengths up to 512.
+int pick_e_y(int64_t L) {
+  if (is_pow2(L) && L >= 8 && L <= 512) return 8;
+  return pick_e(L);
 }
 
 // Radix schedule: the largest power-of-two radix dividing E first, then the
@@ -125,7 +160,6 @@ struct Axis {
 
 struct Pencil {
   Axis ax;
-  int TX = 16, TXP = 16;
   size_t lds = 0;
   dim3 grid, block;
   PencilArgs args{};
@@ -143,7 +177,7 @@ struct rl_plan_s {
   int device = 0;
   hipStream_t stream = nullptr;
   int64_t nz = 0, ny = 0, nx = 0;
-  int64_t M = 0, ncols = 0, pitch = 0, nvox = 0, nrows = 0;
+  int64_t M = 0, ncols = 0, xt = 0, nvox = 0, nrows = 0;
   size_t spec_elems = 0;
   float2* spec = nullptr;
   float2* otf = nullptr;
@@ -249,33 +283,81 @@ void release(rl_plan p) {
   delete p;
 }
 
-Pencil make_pencil(int64_t L, int64_t ncols, int64_t estride, int64_t ostride, int64_t outer,
-                   int tile_x) {
-  Pencil pc;
-  pc.ax.L = L;
-  pc.ax.E = pick_e(L);
-  pc.ax.P = (int)(L / pc.ax.E);
-  pc.ax.sc = make_sched(L, pc.ax.E, 1);
-  int want = tile_x > 0 ? tile_x : 16;
-  int tx = 1;
-  while (tx < want) tx <<= 1;
-  int cap = 1;
-  while (cap < ncols) cap <<= 1;
-  if (tx > cap) tx = cap;
-  while (tx > 1 && ((int64_t)tx * pc.ax.P > rlmi::kPencilMaxThreads || (size_t)L * tx * sizeof(float2) > kMaxLds))
-    tx >>= 1;
-  pc.TX = tx;
-  pc.TXP = tx;
-  pc.lds = (pc.ax.sc.ns > 1) ? (size_t)L * pc.TXP * sizeof(float2) : 0;
-  pc.block = dim3((unsigned)(tx * pc.ax.P));
-  pc.grid = dim3((unsigned)((ncols + tx - 1) / tx), (unsigned)outer);
-  pc.args.L = (int)L;
+int max_threads_for(int E) { return (E == 8 || E == 16) ? 1024 : rlmi::kPencilMaxThreads; }
+
+Axis make_axis(int64_t L, int e = 0) {
+  Axis ax;
+  ax.L = L;
+  ax.E = e > 0 ? e : pick_e(L);
+  ax.P = (int)(L / ax.E);
+  ax.sc = make_sched(L, ax.E, 1);
+  return ax;
+}
+
+void finish_pencil(Pencil& pc, int txb) {
+  pc.args.L = (int)pc.ax.L;
   pc.args.P = pc.ax.P;
-  pc.args.TX = pc.TX;
-  pc.args.TXP = pc.TXP;
+  pc.args.TXB = txb;
+  pc.args.TXP = txb;
+  pc.lds = (pc.ax.sc.ns > 1) ? (size_t)pc.ax.L * txb * sizeof(float2) : 0;
+  pc.block = dim3((unsigned)(txb * pc.ax.P));
+}
+
+// Y pass: one work-group per (tile column, z); lanes = up to 16 columns of the tile.
+Pencil make_pencil_y(int64_t ny, int64_t nz, int64_t xt, int64_t ncols, int tile_x, int e) {
+  Pencil pc;
+  pc.ax = make_axis(ny, e);
+  int txb = rlmi::kTile;
+  if (tile_x > 0 && tile_x < txb) {
+    txb = 1;
+    while (txb * 2 <= tile_x) txb *= 2;
+  }
+  while (txb > 1 && ((int64_t)txb * pc.ax.P > max_threads_for(pc.ax.E) ||
+                     (size_t)ny * txb * sizeof(float2) > kMaxPencilLds))
+    txb >>= 1;
+  finish_pencil(pc, txb);
+  pc.args.xsplit = rlmi::kTile / txb;
   pc.args.ncols = (int)ncols;
-  pc.args.estride = estride;
-  pc.args.ostride = ostride;
+  pc.args.xstride = ny * rlmi::kTile;
+  pc.args.ostride = xt * ny * rlmi::kTile;
+  pc.args.estride = rlmi::kTile;
+  pc.grid = dim3((unsigned)(xt * pc.args.xsplit), (unsigned)nz);
+  return pc;
+}
+
+// Z pass: one work-group per (tile column, group of ty rows); lanes = 16 * ty
+// consecutive elements (ty whole tile rows), so each z step reads 128 * ty bytes.
+Pencil make_pencil_z(int64_t nz, int64_t ny, int64_t xt, int64_t ncols, int tile_x, int e) {
+  Pencil pc;
+  pc.ax = make_axis(nz, e);
+  const int maxt = max_threads_for(pc.ax.E);
+  auto fits = [&](int txb) {
+    return (int64_t)txb * pc.ax.P <= maxt && (size_t)nz * txb * sizeof(float2) <= kMaxPencilLds;
+  };
+  int txb;
+  if (tile_x > 0 && tile_x < rlmi::kTile) {
+    txb = 1;
+    while (txb * 2 <= tile_x) txb *= 2;
+  } else {
+    int ty = tile_x >= rlmi::kTile ? tile_x / rlmi::kTile : 2;
+    while (ty > 1 && (ny % ty != 0 || !fits(ty * rlmi::kTile))) ty >>= 1;
+    txb = ty * rlmi::kTile;
+  }
+  while (txb > 1 && !fits(txb)) txb >>= 1;
+  finish_pencil(pc, txb);
+  pc.args.ncols = (int)ncols;
+  pc.args.xstride = ny * rlmi::kTile;
+  pc.args.estride = xt * ny * rlmi::kTile;
+  if (txb >= rlmi::kTile) {
+    const int ty = txb / rlmi::kTile;
+    pc.args.xsplit = 1;
+    pc.args.ostride = (int64_t)ty * rlmi::kTile;
+    pc.grid = dim3((unsigned)xt, (unsigned)(ny / ty));
+  } else {
+    pc.args.xsplit = rlmi::kTile / txb;
+    pc.args.ostride = rlmi::kTile;
+    pc.grid = dim3((unsigned)(xt * pc.args.xsplit), (unsigned)ny);
+  }
   return pc;
 }
 
@@ -317,7 +399,9 @@ XArgs base_xargs(rl_plan p, float2* spec) {
   XArgs a;
   std::memset(&a, 0, sizeof(a));
   a.spec = spec;
-  a.pitch = p->pitch;
+  a.zstride = p->xt * p->ny * rlmi::kTile;
+  a.tstride = p->ny * rlmi::kTile;
+  a.ny = (int)p->ny;
   a.M = (int)p->M;
   a.P = p->axx.P;
   a.RPW = p->x_rpw;
@@ -360,6 +444,11 @@ rl_status create_impl(const int64_t shape[3], const float* psf, int boundary,
     return fail(RL_E_UNSUPPORTED, "only FP32 precision is implemented");
   if (opt && (opt->tile_x < 0 || opt->tile_x > 64))
     return fail(RL_E_INVALID, "tile_x must be in [0, 64]");
+  if (opt && opt->x_elems != 0 && !e_ok(shape[2] / 2, opt->x_elems, 64))
+    return fail(RL_E_INVALID, "x_elems does not fit nx/2");
+  if (opt && opt->yz_elems != 0 &&
+      (!e_ok(shape[1], opt->yz_elems, 1024) || !e_ok(shape[0], opt->yz_elems, 1024)))
+    return fail(RL_E_INVALID, "yz_elems does not fit ny and nz");
   if (!psf) return fail(RL_E_INVALID, "psf is NULL");
   if (reinterpret_cast<uintptr_t>(psf) % 16 != 0)
     return fail(RL_E_INVALID, "psf is not 16-byte aligned");
@@ -383,14 +472,14 @@ rl_status create_impl(const int64_t shape[3], const float* psf, int boundary,
   p->nx = nx;
   p->M = nx / 2;
   p->ncols = p->M + 1;
-  p->pitch = (p->ncols + 15) / 16 * 16;  // 128-byte aligned rows
+  p->xt = (p->ncols + rlmi::kTile - 1) / rlmi::kTile;  // 16-column tiles per row
   p->nvox = nvox;
   p->nrows = nz * ny;
-  p->spec_elems = (size_t)p->nrows * p->pitch;
+  p->spec_elems = (size_t)nz * p->xt * ny * rlmi::kTile;
 
   // X pass shape
   p->axx.L = p->M;
-  p->axx.E = pick_e(p->M);
+  p->axx.E = (opt && opt->x_elems) ? opt->x_elems : pick_e_x(p->M);
   p->axx.P = (int)(p->M / p->axx.E);
   p->axx.sc = make_sched(p->M, p->axx.E, 2);
   // each wavefront owns 64 / P whole rows; up to kXMaxThreads / 64 waves per work-group
@@ -407,9 +496,12 @@ rl_status create_impl(const int64_t shape[3], const float* psf, int boundary,
   p->x_grid = dim3((unsigned)((p->nrows + p->x_rpw - 1) / p->x_rpw));
   // Y: pencils along Y, outer = z; Z: pencils along Z, outer = y
   const int tile_x = opt ? opt->tile_x : 0;
-  p->py = make_pencil(ny, p->ncols, p->pitch, ny * p->pitch, nz, tile_x);
-  p->pz = make_pencil(nz, p->ncols, ny * p->pitch, p->pitch, ny, tile_x);
-  if (p->x_lds > kMaxLds || p->py.lds > kMaxLds || p->pz.lds > kMaxLds) {
+  const int yz_e = opt ? opt->yz_elems : 0;
+  p->py = make_pencil_y(ny, nz, p->xt, p->ncols, tile_x, yz_e ? yz_e : pick_e_y(ny));
+  p->pz = make_pencil_z(nz, ny, p->xt, p->ncols, tile_x, yz_e);
+  if (p->x_lds > kMaxLds || p->py.lds > kMaxPencilLds || p->pz.lds > kMaxPencilLds ||
+      (int)p->py.block.x > max_threads_for(p->py.ax.E) ||
+      (int)p->pz.block.x > max_threads_for(p->pz.ax.E)) {
     delete p;
     return fail(RL_E_UNSUPPORTED, "shape needs more LDS than a work-group may use");
   }
@@ -465,14 +557,14 @@ rl_status create_impl(const int64_t shape[3], const float* psf, int boundary,
     release(p);
     return fail(RL_E_INVALID, "psf must have a positive finite sum");
   }
-  // OTF / N: scaled, centred PSF written as padded real rows into the OTF
-  // buffer, then transformed in place along X, Y and Z.
+  // OTF / N: scaled, centred PSF written as dense real rows into the spectrum
+  // workspace, transformed along X into the OTF buffer, then along Y and Z.
   const double scale = 1.0 / (stats[0] * (double)nvox);
-  RL_TRY(rlmi::launch_psf_prep(psf, reinterpret_cast<float*>(p->otf), (int)nz, (int)ny, (int)nx,
-                               2 * p->pitch, scale, p->stream));
+  RL_TRY(rlmi::launch_psf_prep(psf, reinterpret_cast<float*>(p->spec), (int)nz, (int)ny, (int)nx,
+                               nx, scale, p->stream));
   XArgs a = base_xargs(p, p->otf);
-  a.rin = reinterpret_cast<const float*>(p->otf);
-  a.rin_stride = 2 * p->pitch;
+  a.rin = reinterpret_cast<const float*>(p->spec);
+  a.rin_stride = nx;
   if ((st = run_x(p, rlmi::XM_R2C, a, RL_KERNEL_OTHER)) != RL_OK) {
     release(p);
     return st;
@@ -654,7 +746,7 @@ rl_status rl_plan_get_info(rl_plan p, int64_t shape[3], int64_t* spectrum_pitch)
     shape[1] = p->ny;
     shape[2] = p->nx;
   }
-  if (spectrum_pitch) *spectrum_pitch = p->pitch;
+  if (spectrum_pitch) *spectrum_pitch = p->xt * rlmi::kTile;
   return RL_OK;
 }
 

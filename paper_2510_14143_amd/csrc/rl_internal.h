@@ -24,17 +24,28 @@ struct Sched {
   int tm[kMaxStages];
 };
 
-// Geometry of a strided pencil pass (Y or Z axis) over the half spectrum.
-// Element e of the pencil for (outer o, column x) sits at
-//   o * ostride + e * estride + x   (complex elements).
+// Half-spectrum layout ("x-tile major"): complex element (z, y, kx) of a volume
+// with ny rows and XT = ceil((nx/2 + 1) / 16) column tiles lives at
+//   ((z * XT + kx / 16) * ny + y) * 16 + kx % 16.
+// A tile column (fixed z and kx / 16) is ny * 128 contiguous bytes.
+constexpr int kTile = 16;
+
+// Geometry of a strided pencil pass (Y or Z axis).  A work-group covers TXB
+// consecutive complex elements ("lanes") of a tile row group and all L elements
+// of each of those pencils:
+//   lane c of block (bx, by): xb = bx / xsplit, c = (bx % xsplit) * TXB + lane,
+//   element e at xb * xstride + by * ostride + c + e * estride,
+//   valid when xb * 16 + (c % 16) < ncols.
 struct PencilArgs {
   int L;       // transform length
   int P;       // threads per pencil (L / E)
-  int TX;      // columns per work-group (power of two)
-  int TXP;     // LDS row stride in complex elements (>= TX)
+  int TXB;     // lanes per work-group (power of two)
+  int TXP;     // LDS stride per pencil element, in complex elements (>= TXB)
+  int xsplit;  // work-groups per 16-column tile (16 / TXB when TXB < 16, else 1)
   int ncols;   // valid columns (nx/2 + 1)
-  long long estride;
+  long long xstride;
   long long ostride;
+  long long estride;
 };
 
 enum PencilMode { PM_FWD = 0, PM_INV = 1, PM_FKI = 2, PM_FCKI = 3 };
@@ -42,8 +53,10 @@ enum XMode { XM_R2C = 0, XM_C2R = 1, XM_RATIO = 2, XM_UPDATE = 3 };
 
 // Arguments of an X-row pass (contiguous axis, real <-> half spectrum).
 struct XArgs {
-  float2* spec;          // half-spectrum rows, `pitch` complex apart
-  long long pitch;
+  float2* spec;          // half spectrum, x-tile-major layout (see kTile)
+  long long zstride;     // complex elements per z plane (XT * ny * 16)
+  long long tstride;     // complex elements per tile column (ny * 16)
+  int ny;
   const float* rin;      // XM_R2C: real input rows, `rin_stride` floats apart
   long long rin_stride;
   float* rout;           // XM_C2R: real output rows, `rout_stride` floats apart
@@ -60,6 +73,8 @@ struct XArgs {
   int nrows;             // nz * ny
 };
 
+// Pencil kernels exist for work-groups of up to 512 threads (all E) and up to
+// 1024 threads (E = 8 and 16 only).
 hipError_t launch_pencil(int mode, int E, dim3 grid, dim3 block, size_t lds, hipStream_t s,
                          float2* data, const float2* otf, const float2* tw,
                          const PencilArgs& a, const Sched& sc);

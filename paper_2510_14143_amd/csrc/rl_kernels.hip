@@ -13,10 +13,13 @@
 // natural order in the same registers, so global loads and stores of a pass
 // are always "element i + P*m".
 //
-// The half-spectrum layout is [Z][Y][pitch] complex64 with nx/2 + 1 valid
-// columns per row.  Real rows are transformed as complex rows of half length
-// (even samples in the real part, odd in the imaginary part) followed by the
-// usual split into even and odd spectra.
+// The half spectrum (nx/2 + 1 complex columns per row) is stored x-tile major:
+// [Z][column tile][Y][16], so a tile column is one contiguous run of ny * 128
+// bytes.  The Y pass reads whole tile columns, the Z pass reads 128 * ty bytes
+// per z step, and the X pass reads 128-byte row pieces of 16-row bands.  Real
+// rows are transformed as complex rows of half length (even samples in the real
+// part, odd in the imaginary part) followed by the split into even and odd
+// spectra.
 #include "rl_internal.h"
 
 namespace rlmi {
@@ -224,28 +227,30 @@ __device__ __forceinline__ void fft(float2 (&v)[E], const Sched& sc, int i, int 
 // ---------------------------------------------------------------------------
 // Y / Z pencil pass
 // ---------------------------------------------------------------------------
-// Work-group = TX columns x P threads; lanes run along the contiguous column
-// index so that each global access of a wavefront covers TX consecutive
-// complex elements of 64/TX pencil rows.
-template <int E, int MODE>
-__global__ void __launch_bounds__(kPencilMaxThreads) k_pencil(float2* __restrict__ data,
+// Work-group = TXB lanes x P threads; lanes run along contiguous complex
+// elements of the tiled layout, so a wavefront access covers TXB consecutive
+// elements of 64/TXB pencil positions (for the Y pass the whole work-group
+// reads one contiguous tile column).
+template <int E, int MODE, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_pencil(float2* __restrict__ data,
                                                  const float2* __restrict__ otf,
                                                  const float2* __restrict__ tw, PencilArgs a,
                                                  Sched sc) {
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
-  const int xl = tid & (a.TX - 1);
-  const int i = tid / a.TX;
-  const int x = blockIdx.x * a.TX + xl;
-  const bool ok = x < a.ncols;
-  const long long base = (long long)blockIdx.y * a.ostride + x;
+  const int lane = tid & (a.TXB - 1);
+  const int i = tid / a.TXB;
+  const int xb = blockIdx.x / a.xsplit;
+  const int c = (blockIdx.x - xb * a.xsplit) * a.TXB + lane;
+  const bool ok = xb * kTile + (c & (kTile - 1)) < a.ncols;
+  const long long base = (long long)xb * a.xstride + (long long)blockIdx.y * a.ostride + c;
 
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m)
     v[m] = ok ? data[base + (long long)(i + a.P * m) * a.estride] : make_float2(0.f, 0.f);
 
-  if constexpr (MODE != PM_INV) fft<E, -1>(v, sc, i, a.P, tw, lds, a.TXP, xl);
+  if constexpr (MODE != PM_INV) fft<E, -1>(v, sc, i, a.P, tw, lds, a.TXP, lane);
   if constexpr (MODE == PM_FKI || MODE == PM_FCKI) {
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -253,7 +258,7 @@ __global__ void __launch_bounds__(kPencilMaxThreads) k_pencil(float2* __restrict
       v[m] = (MODE == PM_FKI) ? cmul(v[m], k) : cmulc(v[m], k);
     }
   }
-  if constexpr (MODE != PM_FWD) fft<E, +1>(v, sc, i, a.P, tw, lds, a.TXP, xl);
+  if constexpr (MODE != PM_FWD) fft<E, +1>(v, sc, i, a.P, tw, lds, a.TXP, lane);
 
   if (ok) {
 #pragma unroll
@@ -271,10 +276,15 @@ __global__ void __launch_bounds__(kPencilMaxThreads) k_pencil(float2* __restrict
 
 // Forward: complex row z (registers, natural order) -> FFT -> split into the
 // half spectrum X[0..M] and store.  `row` is this row's wave-private LDS.
+// Offset of column kx inside a row of the tiled half spectrum.
+__device__ __forceinline__ long long col_off(int kx, long long tstride) {
+  return (long long)(kx >> 4) * tstride + (kx & (kTile - 1));
+}
+
 template <int E>
 __device__ __forceinline__ void r2c_store(float2 (&v)[E], int M, int P, const Sched& sc, int i,
                                           const float2* tw, float2* row, bool ok,
-                                          float2* __restrict__ out) {
+                                          float2* __restrict__ out, long long ts) {
   fft<E, -1, true>(v, sc, i, P, tw, row, 1, 0);
 #pragma unroll
   for (int m = 0; m < E; ++m) row[i + P * m] = v[m];
@@ -288,9 +298,9 @@ __device__ __forceinline__ void r2c_store(float2 (&v)[E], int M, int P, const Sc
     const float2 dd = csub(A, B);
     const float2 od = make_float2(0.5f * dd.y, -0.5f * dd.x);  // -i/2 * (A - B)
     const float2 X = cadd(ev, cmul(tw[k], od));
-    if (ok) out[k] = X;
+    if (ok) out[col_off(k, ts)] = X;
   }
-  if (ok && i == 0) out[M] = make_float2(v[0].x - v[0].y, 0.f);
+  if (ok && i == 0) out[col_off(M, ts)] = make_float2(v[0].x - v[0].y, 0.f);
 }
 
 // Pairs X[k] with X[M-k] and forms z[k] = A + iB, the half-length complex
@@ -329,7 +339,9 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
   const bool ok = rowi < a.nrows;
   const long long rix = ok ? rowi : 0;
   float2* row = lds + 2 * M + lrow * a.RS;
-  float2* srow = a.spec + rix * a.pitch;
+  const int zz = (int)(rix / a.ny), yy = (int)(rix - (long long)zz * a.ny);
+  float2* srow = a.spec + (long long)zz * a.zstride + yy * kTile;
+  const long long ts = a.tstride;
 
   float2 v[E];
   if constexpr (MODE == XM_R2C) {
@@ -337,13 +349,13 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = ok ? in[i + P * m] : make_float2(0.f, 0.f);
     __syncthreads();  // twiddles in LDS
-    r2c_store<E>(v, M, P, sc, i, tw, row, ok, srow);
+    r2c_store<E>(v, M, P, sc, i, tw, row, ok, srow, ts);
   } else {
     // issue every global load of the row first
     float2 w[(MODE == XM_RATIO || MODE == XM_UPDATE) ? E : 1];
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = ok ? srow[i + P * m] : make_float2(0.f, 0.f);
-    const float2 nyq = (ok && i == 0) ? srow[M] : make_float2(0.f, 0.f);
+    for (int m = 0; m < E; ++m) v[m] = ok ? srow[col_off(i + P * m, ts)] : make_float2(0.f, 0.f);
+    const float2 nyq = (ok && i == 0) ? srow[col_off(M, ts)] : make_float2(0.f, 0.f);
     if constexpr (MODE == XM_RATIO) {
       const float2* dr = reinterpret_cast<const float2*>(a.d + rix * (2LL * M));
 #pragma unroll
@@ -370,7 +382,7 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
         v[m] = make_float2(q.x > 1e-12f ? w[m].x / q.x : 0.f, q.y > 1e-12f ? w[m].y / q.y : 0.f);
       }
       wave_sync();  // row buffer reuse
-      r2c_store<E>(v, M, P, sc, i, tw, row, ok, srow);
+      r2c_store<E>(v, M, P, sc, i, tw, row, ok, srow, ts);
     } else {  // XM_UPDATE
       float2* ur = reinterpret_cast<float2*>(a.u + rix * (2LL * M));
       double acc = 0.0;
@@ -387,7 +399,7 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
       }
       if (a.do_fwd) {
         wave_sync();
-        r2c_store<E>(v, M, P, sc, i, tw, row, ok, srow);
+        r2c_store<E>(v, M, P, sc, i, tw, row, ok, srow, ts);
       }
       // work-group partial of the flux: wavefront butterfly, then the waves in order
 #pragma unroll
@@ -519,22 +531,44 @@ __global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ src,
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+template <int MODE, int MAXT, int EV>
+static hipError_t pencil_one(dim3 g, dim3 b, size_t lds, hipStream_t s, float2* data,
+                             const float2* otf, const float2* tw, const PencilArgs& a,
+                             const Sched& sc) {
+  if (lds > 65536) {
+    static bool attr_done = false;  // once per instantiation
+    if (!attr_done) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pencil<EV, MODE, MAXT>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+      if (e != hipSuccess) return e;
+      attr_done = true;
+    }
+  }
+  hipLaunchKernelGGL((k_pencil<EV, MODE, MAXT>), g, b, lds, s, data, otf, tw, a, sc);
+  return hipGetLastError();
+}
+
 template <int MODE>
 static hipError_t pencil_e(int E, dim3 g, dim3 b, size_t lds, hipStream_t s, float2* data,
                            const float2* otf, const float2* tw, const PencilArgs& a,
                            const Sched& sc) {
+  if (b.x > 1024) return hipErrorInvalidValue;
+  if (b.x > 512) {
+    switch (E) {
+      case 8: return pencil_one<MODE, 1024, 8>(g, b, lds, s, data, otf, tw, a, sc);
+      case 16: return pencil_one<MODE, 1024, 16>(g, b, lds, s, data, otf, tw, a, sc);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (E) {
-#define RL_CASE(EV)                                                             \
-  case EV:                                                                      \
-    hipLaunchKernelGGL((k_pencil<EV, MODE>), g, b, lds, s, data, otf, tw, a, sc); \
-    break;
+#define RL_CASE(EV) \
+  case EV: return pencil_one<MODE, 512, EV>(g, b, lds, s, data, otf, tw, a, sc);
     RL_CASE(1) RL_CASE(2) RL_CASE(3) RL_CASE(4) RL_CASE(6) RL_CASE(8) RL_CASE(12) RL_CASE(16)
     RL_CASE(24)
 #undef RL_CASE
     default:
       return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_pencil(int mode, int E, dim3 grid, dim3 block, size_t lds, hipStream_t s,

@@ -40,7 +40,8 @@ _STATUS_NAMES = {0: "RL_OK", 1: "RL_E_INVALID", 2: "RL_E_UNSUPPORTED", 3: "RL_E_
 
 
 class _Options(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int), ("stream", ctypes.c_void_p), ("tile_x", ctypes.c_int)]
+    _fields_ = [("precision", ctypes.c_int), ("stream", ctypes.c_void_p), ("tile_x", ctypes.c_int),
+                ("x_elems", ctypes.c_int), ("yz_elems", ctypes.c_int)]
 
 
 _lib = None
@@ -112,9 +113,11 @@ def rl_plan_create(shape, psf_ptr: int, boundary: int = RL_BOUNDARY_PERIODIC) ->
 
 
 def rl_plan_create_ex(shape, psf_ptr: int, boundary: int = RL_BOUNDARY_PERIODIC,
-                      precision: int = RL_PRECISION_FP32, stream: int = 0, tile_x: int = 0) -> int:
+                      precision: int = RL_PRECISION_FP32, stream: int = 0, tile_x: int = 0,
+                      x_elems: int = 0, yz_elems: int = 0) -> int:
     out = ctypes.c_void_p()
-    opt = _Options(int(precision), ctypes.c_void_p(stream or None), int(tile_x))
+    opt = _Options(int(precision), ctypes.c_void_p(stream or None), int(tile_x), int(x_elems),
+                   int(yz_elems))
     _check(lib().rl_plan_create_ex(_shape(shape), ctypes.c_void_p(psf_ptr), int(boundary),
                                    ctypes.byref(opt), ctypes.byref(out)))
     return out.value
@@ -205,7 +208,8 @@ def _check_volume(t, shape, device, name):
 class Plan:
     """Richardson-Lucy plan for one volume shape and PSF (a float32 CUDA tensor [Z][Y][X])."""
 
-    def __init__(self, psf, boundary: str = "periodic", tile_x: int = 0):
+    def __init__(self, psf, boundary: str = "periodic", tile_x: int = 0, x_elems: int = 0,
+                 yz_elems: int = 0):
         bmap = {"periodic": RL_BOUNDARY_PERIODIC, "zero": RL_BOUNDARY_ZERO}
         if boundary not in bmap:
             raise ValueError("boundary must be 'periodic' or 'zero'")
@@ -215,7 +219,8 @@ class Plan:
         self.shape = tuple(int(s) for s in psf.shape)
         self.device = psf.device
         self.handle = rl_plan_create_ex(self.shape, psf.data_ptr(), bmap[boundary],
-                                        stream=_stream_of(self.device), tile_x=tile_x)
+                                        stream=_stream_of(self.device), tile_x=tile_x,
+                                        x_elems=x_elems, yz_elems=yz_elems)
 
     def _bind_stream(self):
         rl_plan_set_stream(self.handle, _stream_of(self.device))

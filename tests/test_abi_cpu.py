@@ -104,3 +104,13 @@ def test_python_errors_carry_status():
     with pytest.raises(rl.RLError) as ei:
         rl.rl_iterate(0x1234560, 0, 0, 1)
     assert ei.value.status == rl.RL_E_INVALID
+
+
+def test_elems_options_validated_before_device_work():
+    L = rl.lib()
+    sh = (ctypes.c_int64 * 3)(8, 16, 32)
+    out = ctypes.c_void_p()
+    for xe, yze in ((5, 0), (3, 0), (32, 0), (0, 3), (0, 7), (1, 0)):
+        opt = rl._Options(0, None, 0, xe, yze)
+        st = L.rl_plan_create_ex(sh, ctypes.c_void_p(4096), 0, ctypes.byref(opt), ctypes.byref(out))
+        assert st == rl.RL_E_INVALID, (xe, yze, rl.rl_last_error())

@@ -88,6 +88,28 @@ def test_conv_tile_widths(torch, tile_x):
     assert oracle.rel_l2(got, oracle.conv3d(x, psf)) <= CONV_TOL
 
 
+@pytest.mark.parametrize("x_elems,yz_elems", [(8, 8), (4, 4), (2, 8), (16, 4)])
+def test_conv_elems_options(torch, x_elems, yz_elems):
+    shape = (16, 32, 64)
+    say("conv elems", x_elems, yz_elems)
+    x = synth.uniform_volume(shape, 103)
+    psf = rand_psf(shape, 14)
+    got = gpu_conv(torch, x, psf, x_elems=x_elems, yz_elems=yz_elems)
+    assert oracle.rel_l2(got, oracle.conv3d(x, psf)) <= CONV_TOL
+
+
+def test_rl_elems_options(torch):
+    shape = (12, 48, 96)
+    say("rl elems 24/12")
+    c = synth.small_case(shape, seed=8)
+    ref, _, _ = oracle.rl(c["d"], c["psf"], c["u0"], 8)
+    with rl.Plan(dev(torch, c["psf"]), x_elems=24, yz_elems=12) as p:
+        u = dev(torch, c["u0"])
+        p.iterate(dev(torch, c["d"]), u, 8)
+        got = u.cpu().numpy()
+    assert oracle.rel_l2(got, ref) <= RL_TOL
+
+
 def test_conv_in_place(torch):
     shape = (8, 16, 32)
     say("conv in place")
