@@ -299,7 +299,9 @@ void finish_pencil(Pencil& pc, int txb) {
   pc.args.P = pc.ax.P;
   pc.args.TXB = txb;
   pc.args.TXP = txb;
-  pc.lds = (pc.ax.sc.ns > 1) ? (size_t)pc.ax.L * txb * sizeof(float2) : 0;
+  // exchange buffer (L x TXP) followed by the twiddle table (L); the kernel
+  // places the table at offset L * TXP whether or not the exchange is used
+  pc.lds = (size_t)pc.ax.L * (txb + 1) * sizeof(float2);
   pc.block = dim3((unsigned)(txb * pc.ax.P));
 }
 
@@ -313,7 +315,7 @@ Pencil make_pencil_y(int64_t ny, int64_t nz, int64_t xt, int64_t ncols, int tile
     while (txb * 2 <= tile_x) txb *= 2;
   }
   while (txb > 1 && ((int64_t)txb * pc.ax.P > max_threads_for(pc.ax.E) ||
-                     (size_t)ny * txb * sizeof(float2) > kMaxPencilLds))
+                     (size_t)ny * (txb + 1) * sizeof(float2) > kMaxPencilLds))
     txb >>= 1;
   finish_pencil(pc, txb);
   pc.args.xsplit = rlmi::kTile / txb;
@@ -332,7 +334,8 @@ Pencil make_pencil_z(int64_t nz, int64_t ny, int64_t xt, int64_t ncols, int tile
   pc.ax = make_axis(nz, e);
   const int maxt = max_threads_for(pc.ax.E);
   auto fits = [&](int txb) {
-    return (int64_t)txb * pc.ax.P <= maxt && (size_t)nz * txb * sizeof(float2) <= kMaxPencilLds;
+    return (int64_t)txb * pc.ax.P <= maxt &&
+           (size_t)nz * (txb + 1) * sizeof(float2) <= kMaxPencilLds;
   };
   int txb;
   if (tile_x > 0 && tile_x < rlmi::kTile) {
@@ -485,7 +488,7 @@ rl_status create_impl(const int64_t shape[3], const float* psf, int boundary,
   // each wavefront owns 64 / P whole rows; up to kXMaxThreads / 64 waves per work-group
   const int rows_per_wave = 64 / p->axx.P;
   int waves = rlmi::kXMaxThreads / 64;
-  p->x_rs = (int)(p->M + 1);
+  p->x_rs = (int)(p->M + 1 + ((p->M + 1) >> rlmi::kXPad) + 1);  // padded row
   auto x_lds_for = [&](int w) {
     return (size_t)(2 * p->M + (int64_t)w * rows_per_wave * p->x_rs) * sizeof(float2);
   };

@@ -12,6 +12,8 @@ constexpr int kMaxStages = 8;
 // Work-group size limits the kernels are compiled for (register budget).
 constexpr int kPencilMaxThreads = 512;
 constexpr int kXMaxThreads = 256;
+// X-pass LDS rows: one spare slot after every 4 elements (radix-4 stages).
+constexpr int kXPad = 2;
 
 // Radix schedule of one axis transform of length L, executed in this order.
 // Stage s has radix r[s], input span p[s] (product of earlier radices) and

@@ -142,7 +142,15 @@ struct Dft {
 // ---------------------------------------------------------------------------
 // tw: table of exp(-2 pi i m / T) (forward sign); inverse transforms conjugate it.
 // lds element n of this thread's pencil lives at lds[n * ls + lo].
-template <int E, int R, int S>
+// LDS slot of pencil element n: with PAD > 0 one spare slot follows every 2^PAD
+// elements, which spreads power-of-two strides over the banks.
+template <int PAD>
+__device__ __forceinline__ int lslot(int n) {
+  if constexpr (PAD > 0) return n + (n >> PAD);
+  else return n;
+}
+
+template <int E, int R, int S, int PAD>
 __device__ __forceinline__ void stage(float2 (&v)[E], int i, int P, int p, int tm, bool last,
                                       const float2* __restrict__ tw, float2* lds, int ls, int lo) {
   constexpr int V = E / R;
@@ -167,7 +175,7 @@ __device__ __forceinline__ void stage(float2 (&v)[E], int i, int P, int p, int t
     } else {
       const int base = (b - k) * R + k;
 #pragma unroll
-      for (int j = 0; j < R; ++j) lds[(base + j * p) * ls + lo] = y[j];
+      for (int j = 0; j < R; ++j) lds[lslot<PAD>(base + j * p) * ls + lo] = y[j];
     }
   }
 }
@@ -190,7 +198,7 @@ __device__ __forceinline__ void exch_sync() {
 // Full 1-D transform of this thread's pencil; natural order in and out.
 // WAVE = false: the pencil spans the work-group and every thread must call this
 // (it contains barriers).  WAVE = true: the pencil lives inside one wavefront.
-template <int E, int S, bool WAVE = false>
+template <int E, int S, bool WAVE = false, int PAD = 0>
 __device__ __forceinline__ void fft(float2 (&v)[E], const Sched& sc, int i, int P,
                                     const float2* __restrict__ tw, float2* lds, int ls, int lo) {
   for (int s = 0; s < sc.ns; ++s) {
@@ -198,19 +206,19 @@ __device__ __forceinline__ void fft(float2 (&v)[E], const Sched& sc, int i, int 
     const int r = sc.r[s], p = sc.p[s], tm = sc.tm[s];
     switch (r) {
       case 16:
-        if constexpr (E % 16 == 0) stage<E, 16, S>(v, i, P, p, tm, last, tw, lds, ls, lo);
+        if constexpr (E % 16 == 0) stage<E, 16, S, PAD>(v, i, P, p, tm, last, tw, lds, ls, lo);
         break;
       case 8:
-        if constexpr (E % 8 == 0) stage<E, 8, S>(v, i, P, p, tm, last, tw, lds, ls, lo);
+        if constexpr (E % 8 == 0) stage<E, 8, S, PAD>(v, i, P, p, tm, last, tw, lds, ls, lo);
         break;
       case 4:
-        if constexpr (E % 4 == 0) stage<E, 4, S>(v, i, P, p, tm, last, tw, lds, ls, lo);
+        if constexpr (E % 4 == 0) stage<E, 4, S, PAD>(v, i, P, p, tm, last, tw, lds, ls, lo);
         break;
       case 2:
-        if constexpr (E % 2 == 0) stage<E, 2, S>(v, i, P, p, tm, last, tw, lds, ls, lo);
+        if constexpr (E % 2 == 0) stage<E, 2, S, PAD>(v, i, P, p, tm, last, tw, lds, ls, lo);
         break;
       case 3:
-        if constexpr (E % 3 == 0) stage<E, 3, S>(v, i, P, p, tm, last, tw, lds, ls, lo);
+        if constexpr (E % 3 == 0) stage<E, 3, S, PAD>(v, i, P, p, tm, last, tw, lds, ls, lo);
         break;
       default:
         break;
@@ -218,7 +226,7 @@ __device__ __forceinline__ void fft(float2 (&v)[E], const Sched& sc, int i, int 
     if (!last) {
       exch_sync<WAVE>();
 #pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = lds[(i + P * m) * ls + lo];
+      for (int m = 0; m < E; ++m) v[m] = lds[lslot<PAD>(i + P * m) * ls + lo];
       exch_sync<WAVE>();
     }
   }
@@ -231,13 +239,17 @@ __device__ __forceinline__ void fft(float2 (&v)[E], const Sched& sc, int i, int 
 // elements of the tiled layout, so a wavefront access covers TXB consecutive
 // elements of 64/TXB pencil positions (for the Y pass the whole work-group
 // reads one contiguous tile column).
+// 1024-thread work-groups of E = 8 are held to 64 VGPRs (8 waves per SIMD), so
+// that two of them share a CU.
 template <int E, int MODE, int MAXT>
-__global__ void __launch_bounds__(MAXT) k_pencil(float2* __restrict__ data,
-                                                 const float2* __restrict__ otf,
-                                                 const float2* __restrict__ tw, PencilArgs a,
-                                                 Sched sc) {
+__global__ void __launch_bounds__(MAXT, (MAXT == 1024 && E == 8) ? 8 : 1)
+    k_pencil(float2* __restrict__ data, const float2* __restrict__ otf,
+             const float2* __restrict__ twg, PencilArgs a, Sched sc) {
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
+  // twiddle table (L entries) after the exchange buffer
+  float2* tw = lds + (size_t)a.L * a.TXP;
+  for (int t = tid; t < a.L; t += blockDim.x) tw[t] = twg[t];
   const int lane = tid & (a.TXB - 1);
   const int i = tid / a.TXB;
   const int xb = blockIdx.x / a.xsplit;
@@ -249,6 +261,7 @@ __global__ void __launch_bounds__(MAXT) k_pencil(float2* __restrict__ data,
 #pragma unroll
   for (int m = 0; m < E; ++m)
     v[m] = ok ? data[base + (long long)(i + a.P * m) * a.estride] : make_float2(0.f, 0.f);
+  __syncthreads();  // twiddles in LDS
 
   if constexpr (MODE != PM_INV) fft<E, -1>(v, sc, i, a.P, tw, lds, a.TXP, lane);
   if constexpr (MODE == PM_FKI || MODE == PM_FCKI) {
@@ -285,15 +298,15 @@ template <int E>
 __device__ __forceinline__ void r2c_store(float2 (&v)[E], int M, int P, const Sched& sc, int i,
                                           const float2* tw, float2* row, bool ok,
                                           float2* __restrict__ out, long long ts) {
-  fft<E, -1, true>(v, sc, i, P, tw, row, 1, 0);
+  fft<E, -1, true, kXPad>(v, sc, i, P, tw, row, 1, 0);
 #pragma unroll
-  for (int m = 0; m < E; ++m) row[i + P * m] = v[m];
+  for (int m = 0; m < E; ++m) row[lslot<kXPad>(i + P * m)] = v[m];
   wave_sync();
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int k = i + P * m;
     const float2 A = v[m];
-    const float2 B = conjf2(row[k == 0 ? 0 : M - k]);
+    const float2 B = conjf2(row[lslot<kXPad>(k == 0 ? 0 : M - k)]);
     const float2 ev = make_float2(0.5f * (A.x + B.x), 0.5f * (A.y + B.y));
     const float2 dd = csub(A, B);
     const float2 od = make_float2(0.5f * dd.y, -0.5f * dd.x);  // -i/2 * (A - B)
@@ -309,14 +322,14 @@ template <int E>
 __device__ __forceinline__ void c2r_prepare(float2 (&v)[E], float2 nyq, int M, int P, int i,
                                             const float2* tw, float2* row) {
 #pragma unroll
-  for (int m = 0; m < E; ++m) row[i + P * m] = v[m];
-  if (i == 0) row[M] = nyq;
+  for (int m = 0; m < E; ++m) row[lslot<kXPad>(i + P * m)] = v[m];
+  if (i == 0) row[lslot<kXPad>(M)] = nyq;
   wave_sync();
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int k = i + P * m;
     const float2 X = v[m];
-    const float2 Y = conjf2(row[M - k]);
+    const float2 Y = conjf2(row[lslot<kXPad>(M - k)]);
     const float2 A = cadd(X, Y);
     const float2 B = cmulc(csub(X, Y), tw[k]);  // (X - conj X[M-k]) * exp(+2 pi i k / 2M)
     v[m] = make_float2(A.x - B.y, A.y + B.x);   // A + i B
@@ -367,7 +380,7 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
     }
     __syncthreads();  // twiddles in LDS
     c2r_prepare<E>(v, nyq, M, P, i, tw, row);
-    fft<E, +1, true>(v, sc, i, P, tw, row, 1, 0);
+    fft<E, +1, true, kXPad>(v, sc, i, P, tw, row, 1, 0);
     // v[m] holds (x[2n], x[2n+1]) for n = i + P*m (unnormalised; the 1/N is in the OTF)
     if constexpr (MODE == XM_C2R) {
       if (ok) {
