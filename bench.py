@@ -141,6 +141,60 @@ def run_workload(torch, rl, synth, cfg: int, steps: int, warmup: int, workload: 
                 bytes_per_vi=round(model_bytes / (nvox * n_iter), 2))
 
 
+def run_batched(torch, rl, synth, steps: int, warmup: int, count: int = 96, n_iter: int = 50):
+    """Batched form: `count` uneven volumes with their own PSFs, one graph launch per
+    iteration, against the same volumes run one plain plan at a time."""
+    vols = synth.make_batch(count)
+    dev = torch.device("cuda:0")
+    psfs = [torch.from_numpy(v["psf"]).to(dev) for v in vols]
+    d = [torch.from_numpy(v["d"]).to(dev) for v in vols]
+    u0 = [torch.from_numpy(v["u0"]).to(dev) for v in vols]
+    u = [t.clone() for t in u0]
+    nvox = sum(int(np.prod(v["shape"])) for v in vols)
+    bp = rl.BatchPlan(psfs)
+
+    def step_batched():
+        for a, b in zip(u, u0):
+            a.copy_(b)
+        bp.iterate(d, u, n_iter)
+
+    plans = [rl.Plan(h) for h in psfs]
+
+    def step_plain():
+        for a, b in zip(u, u0):
+            a.copy_(b)
+        for p, dd, uu in zip(plans, d, u):
+            p.iterate(dd, uu, n_iter)
+
+    out = {}
+    for name, fn in (("batched", step_batched), ("plain", step_plain)):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        out[name] = a.elapsed_time(b) / steps
+    flux = bp.flux()
+    totals = np.array([float(v["d"].sum(dtype=np.float64)) for v in vols])
+    drift = float(np.max(np.abs(flux - totals[:, None]) / totals[:, None]))
+    for p in plans:
+        p.close()
+    bp.close()
+    classes = {}
+    for v in vols:
+        classes[str(v["shape"])] = classes.get(str(v["shape"]), 0) + 1
+    return {"workload": f"rl_fp32_batch{count}_uneven_{n_iter}it", "volumes": count,
+            "voxels": nvox, "shape_classes": classes,
+            "value": round(nvox * n_iter / (out["batched"] * 1e-3) / 1e9, 3),
+            "unit": "Gvoxel-iter/s", "ms_per_step": round(out["batched"], 3),
+            "plain_one_plan_per_volume_ms": round(out["plain"], 3),
+            "speedup_vs_plain": round(out["plain"] / out["batched"], 3), "flux_drift": drift}
+
+
 def copy_probe(torch, rl, nbytes: int = 1 << 30, reps: int = 5) -> float:
     """Plain streaming copy kernel of the library: read + write bytes per second (GB/s)."""
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
@@ -186,6 +240,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-large", action="store_true", help="skip the 256x512x512 workload")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 96-volume workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the batched and single-volume paths "
@@ -210,6 +265,11 @@ def main():
                  "unit": "Gvoxel-iter/s", "ms_per_step": round(lr["ms"], 3),
                  "roofline": lr["roofline"], "all_kernels_gbs": lr["all_kernels_gbs"],
                  "bytes_per_vi": lr["bytes_per_vi"], "flux_drift": lr["flux_drift"]}
+    batched = None
+    if not args.no_batch:
+        log("workload: batched, 96 uneven volumes, 50 it")
+        batched = run_batched(torch, rl, synth, max(1, args.steps // 5), 1)
+        log(json.dumps({"batched": batched}))
     cpu = None
     if rank == 0 and not args.no_cpu:
         log("cpu baseline (oracle)")
@@ -237,6 +297,7 @@ def main():
         "bytes_per_vi": main_run["bytes_per_vi"],
         "flux_drift": main_run["flux_drift"],
         "large": large,
+        "batched": batched,
         "copy_probe_gbs": round(copy_gbs, 1),
     }
     if rank == 0:

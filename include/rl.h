@@ -60,7 +60,13 @@ typedef enum {
 } rl_boundary;
 
 typedef enum {
-  RL_PRECISION_FP32 = 0 /* FP32 transforms, FP64 twiddle generation and sums */
+  RL_PRECISION_FP32 = 0,       /* FP32 transforms, FP64 twiddle generation and sums */
+  RL_PRECISION_SPLIT_BF16 = 1, /* radix-16 butterflies as 32x32 real DFT matrices on MFMA,
+                                  operands split into BF16 hi + lo, three products
+                                  accumulated in FP32; other stages, twiddles, the
+                                  elementwise steps and all sums as in FP32 mode */
+  RL_PRECISION_SPLIT_FP16 = 2  /* the same with FP16 hi + lo and a power-of-two scale
+                                  per 16-point DFT */
 } rl_precision;
 
 /* Options for rl_plan_create_ex.  Zero-initialise, then set fields. */
@@ -74,6 +80,12 @@ typedef struct {
                      default; must divide nx/2 leaving a power-of-two thread count
                      <= 64, and hold every factor 3 of nx/2 (else RL_E_INVALID) */
   int yz_elems;   /* the same for the Y and Z transforms (lengths ny and nz) */
+  int autotune;   /* 1: at plan creation, time candidate elements-per-thread and
+                     work-group widths for each pass on this GPU and keep the
+                     fastest (adds tens of ms; needs 8 bytes per voxel of
+                     temporary device memory).  With RLMI_TUNE_CACHE naming a
+                     text file, results are read from / appended to it, keyed
+                     by GPU architecture, HIP runtime version and shape. */
 } rl_options;
 
 /*
@@ -110,6 +122,30 @@ rl_status rl_iterate(rl_plan p, const float* observed, float* estimate, int n_it
  */
 rl_status conv3d_fft(rl_plan p, const float* x, float* out);
 
+/*
+ * Batched form: `count` independent volumes, volume v of shape
+ * {shapes[3v], shapes[3v+1], shapes[3v+2]} with its own PSF psfs[v] (device
+ * pointers, each the shape of its volume), deconvolved together.  Volumes of
+ * equal shape form one class; each class keeps its spectra and transfer
+ * functions back to back.  Constraints per volume as for rl_plan_create;
+ * opt->tile_x must be 0; opt->autotune tunes each shape once.  Synchronous.
+ * The plan's stream (opt->stream) orders calls; the library forks private
+ * streams, one per class, from it and joins them back.
+ */
+rl_status rl_plan_create_batch(int count, const int64_t* shapes, const float* const* psfs,
+                               int boundary, const rl_options* opt, rl_plan* out);
+
+/*
+ * n_iter iterations of every volume of a batch plan: observed[v] and
+ * estimate[v] are device pointers (host arrays of `count` pointers, read
+ * during the call).  One iteration of all volumes is one hipGraph launch
+ * (captured on the first call, replayed afterwards); the graph holds one
+ * branch per shape class.  rl_plan_get_flux then returns count * n_iter values,
+ * volume-major (flux[v * n_iter + t]).  Asynchronous like rl_iterate.
+ */
+rl_status rl_iterate_batch(rl_plan p, const float* const* observed, float* const* estimate,
+                           int n_iter);
+
 /* Release the plan and its device memory (waits for its pending work). NULL is a no-op. */
 void rl_plan_destroy(rl_plan p);
 
@@ -127,6 +163,11 @@ rl_status rl_plan_get_flux(rl_plan p, double* flux, int cap, int* n_written);
 /* Shape {nz, ny, nx} and the number of complex columns the plan stores per
  * half-spectrum row (nx/2 + 1 rounded up to whole 16-column tiles). */
 rl_status rl_plan_get_info(rl_plan p, int64_t shape[3], int64_t* spectrum_pitch);
+
+/* Launch configuration in use: out = {X elements per thread, Y elements per
+ * thread, Y work-group lanes, Z elements per thread, Z work-group lanes,
+ * 1 if chosen by the autotuner else 0}. */
+rl_status rl_plan_get_launch(rl_plan p, int out[6]);
 
 /*
  * Per-kernel timing with HIP events (measurement support).  When enabled,
@@ -146,7 +187,7 @@ enum {
   RL_KERNEL_OTHER = 7,    /* twiddles, PSF reduction and preparation */
   RL_KERNEL_KINDS = 8
 };
-rl_status rl_plan_set_timing(rl_plan p, int enable);
+rl_status rl_plan_set_timing(rl_plan p, int enable); /* RL_E_UNSUPPORTED for batch plans */
 rl_status rl_plan_get_timing(rl_plan p, int count[RL_KERNEL_KINDS], double ms[RL_KERNEL_KINDS]);
 
 /*

@@ -4,4 +4,4 @@
 draws seeded synthetic input volumes.
 """
 from . import rl  # noqa: F401
-from .rl import Plan, RLError  # noqa: F401
+from .rl import BatchPlan, Plan, RLError  # noqa: F401

@@ -6,10 +6,15 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <mutex>
+#include <sstream>
 #include <new>
 #include <string>
 #include <unordered_set>
@@ -109,6 +114,12 @@ int pick_e_x(int64_t M) {
   return (int)(M / 12 <= 64 ? 12 : 24);  // 3 * 2^a
 }
 
+// Split precision: 16 elements per thread (radix-16 stages) when the length is a
+// power of two >= 16 with at most max_p threads per transform; else 0 (default).
+int split_e(int64_t L, int64_t max_p) {
+  return (is_pow2(L) && L >= 16 && L / 16 <= max_p) ? 16 : 0;
+}
+
 // Y pass: 8 elements per thread for power-of-two lengths up to 512.
 int pick_e_y(int64_t L) {
   if (is_pow2(L) && L >= 8 && L <= 512) return 8;
@@ -198,6 +209,24 @@ struct rl_plan_s {
   dim3 x_grid, x_block;
   // Y and Z passes
   Pencil py, pz;
+  int precision = RL_PRECISION_FP32;
+  // batched volumes of this shape (a class of a batch plan); 1 for a single plan
+  int count = 1;
+  const float** d_tab = nullptr;  // device tables of per-volume pointers (count each)
+  float** u_tab = nullptr;
+  int* iter_dev = nullptr;        // device iteration index for graph replays
+  // batch container (is_batch): classes of equal shape, input-order mapping
+  bool is_batch = false;
+  std::vector<rl_plan> classes;
+  std::vector<int> vol_class, vol_index;
+  std::vector<hipStream_t> cls_streams;
+  std::vector<hipEvent_t> cls_events;
+  hipEvent_t fork_event = nullptr;
+  hipGraphExec_t graph_full = nullptr, graph_last = nullptr;
+  int batch_n = 0;                // iterations of the last rl_iterate_batch call
+  // applied launch choice (elements per thread and work-group widths)
+  int ch_x_e = 0, ch_y_e = 0, ch_y_txb = 0, ch_z_e = 0, ch_z_txb = 0;
+  bool tuned = false;
   // timing
   bool timing = false;
   std::vector<TimedLaunch> events;
@@ -279,6 +308,15 @@ void release(rl_plan p) {
   (void)hipFree(p->counter);
   (void)hipFree(p->stats);
   (void)hipFree(p->flux);
+  (void)hipFree(p->iter_dev);
+  (void)hipFree(p->d_tab);
+  (void)hipFree(p->u_tab);
+  for (rl_plan c : p->classes) release(c);
+  if (p->graph_full) (void)hipGraphExecDestroy(p->graph_full);
+  if (p->graph_last) (void)hipGraphExecDestroy(p->graph_last);
+  for (hipEvent_t ev : p->cls_events) (void)hipEventDestroy(ev);
+  if (p->fork_event) (void)hipEventDestroy(p->fork_event);
+  for (hipStream_t cs : p->cls_streams) (void)hipStreamDestroy(cs);
   p->magic = kDead;
   delete p;
 }
@@ -305,16 +343,25 @@ void finish_pencil(Pencil& pc, int txb) {
   pc.block = dim3((unsigned)(txb * pc.ax.P));
 }
 
-// Y pass: one work-group per (tile column, z); lanes = up to 16 columns of the tile.
-Pencil make_pencil_y(int64_t ny, int64_t nz, int64_t xt, int64_t ncols, int tile_x, int e) {
+int pow2_floor(int v) {
+  int r = 1;
+  while (r * 2 <= v) r *= 2;
+  return r;
+}
+
+bool pencil_fits(const Pencil& pc) {
+  return (int)pc.block.x <= max_threads_for(pc.ax.E) && pc.lds <= kMaxPencilLds;
+}
+
+// Y pass: one work-group per (tile column, z); lanes = `req` (a power of two
+// <= 16; 0 = 16) columns of the tile, halved until the work-group fits.
+Pencil make_pencil_y(int64_t ny, int64_t nz, int64_t xt, int64_t ncols, int req, int e,
+                     int maxt_cap = 1024) {
   Pencil pc;
   pc.ax = make_axis(ny, e);
-  int txb = rlmi::kTile;
-  if (tile_x > 0 && tile_x < txb) {
-    txb = 1;
-    while (txb * 2 <= tile_x) txb *= 2;
-  }
-  while (txb > 1 && ((int64_t)txb * pc.ax.P > max_threads_for(pc.ax.E) ||
+  const int maxt = std::min(max_threads_for(pc.ax.E), maxt_cap);
+  int txb = req > 0 ? pow2_floor(req < rlmi::kTile ? req : rlmi::kTile) : rlmi::kTile;
+  while (txb > 1 && ((int64_t)txb * pc.ax.P > maxt ||
                      (size_t)ny * (txb + 1) * sizeof(float2) > kMaxPencilLds))
     txb >>= 1;
   finish_pencil(pc, txb);
@@ -328,24 +375,20 @@ Pencil make_pencil_y(int64_t ny, int64_t nz, int64_t xt, int64_t ncols, int tile
 }
 
 // Z pass: one work-group per (tile column, group of ty rows); lanes = 16 * ty
-// consecutive elements (ty whole tile rows), so each z step reads 128 * ty bytes.
-Pencil make_pencil_z(int64_t nz, int64_t ny, int64_t xt, int64_t ncols, int tile_x, int e) {
+// consecutive elements (ty whole tile rows), so each z step reads 128 * ty
+// bytes.  `req` = requested lanes (a power of two <= 64; 0 = 32); ty must divide
+// ny; the width is halved until the work-group fits.
+Pencil make_pencil_z(int64_t nz, int64_t ny, int64_t xt, int64_t ncols, int req, int e,
+                     int maxt_cap = 1024) {
   Pencil pc;
   pc.ax = make_axis(nz, e);
-  const int maxt = max_threads_for(pc.ax.E);
+  const int maxt = std::min(max_threads_for(pc.ax.E), maxt_cap);
   auto fits = [&](int txb) {
+    if (txb >= rlmi::kTile && ny % (txb / rlmi::kTile) != 0) return false;
     return (int64_t)txb * pc.ax.P <= maxt &&
            (size_t)nz * (txb + 1) * sizeof(float2) <= kMaxPencilLds;
   };
-  int txb;
-  if (tile_x > 0 && tile_x < rlmi::kTile) {
-    txb = 1;
-    while (txb * 2 <= tile_x) txb *= 2;
-  } else {
-    int ty = tile_x >= rlmi::kTile ? tile_x / rlmi::kTile : 2;
-    while (ty > 1 && (ny % ty != 0 || !fits(ty * rlmi::kTile))) ty >>= 1;
-    txb = ty * rlmi::kTile;
-  }
+  int txb = req > 0 ? pow2_floor(req < 4 * rlmi::kTile ? req : 4 * rlmi::kTile) : 2 * rlmi::kTile;
   while (txb > 1 && !fits(txb)) txb >>= 1;
   finish_pencil(pc, txb);
   pc.args.ncols = (int)ncols;
@@ -386,14 +429,20 @@ rl_status timed_end(rl_plan p, size_t slot) {
   return e == hipSuccess ? RL_OK : hip_fail(e, "hipEventRecord");
 }
 
+// One pencil pass over `nvol` consecutive volumes starting at `data` (and at
+// the plan's OTF for the filtered modes); nvol = 0 means all of the plan's.
 rl_status run_pencil(rl_plan p, const Pencil& pc, int mode, float2* data, const float2* tw,
-                     int kind) {
+                     int kind, int nvol = 0) {
   if (pc.ax.L == 1 && (mode == rlmi::PM_FWD || mode == rlmi::PM_INV)) return RL_OK;  // identity
   size_t slot = 0;
   rl_status st = timed_begin(p, kind, &slot);
   if (st != RL_OK) return st;
-  hipError_t e = rlmi::launch_pencil(mode, pc.ax.E, pc.grid, pc.block, pc.lds, p->stream, data,
-                                     p->otf, tw, pc.args, pc.ax.sc);
+  dim3 grid = pc.grid;
+  grid.z = (unsigned)(nvol > 0 ? nvol : p->count);
+  PencilArgs args = pc.args;
+  args.vstride = (long long)p->spec_elems;
+  hipError_t e = rlmi::launch_pencil(mode, pc.ax.E, p->precision, grid, pc.block, pc.lds,
+                                     p->stream, data, p->otf, tw, args, pc.ax.sc);
   if (e != hipSuccess) return hip_fail(e, "pencil pass launch");
   return timed_end(p, slot);
 }
@@ -410,6 +459,8 @@ XArgs base_xargs(rl_plan p, float2* spec) {
   a.RPW = p->x_rpw;
   a.RS = p->x_rs;
   a.nrows = (int)p->nrows;
+  a.nvol = p->count;
+  a.vstride = (long long)p->spec_elems;
   return a;
 }
 
@@ -417,8 +468,10 @@ rl_status run_x(rl_plan p, int mode, const XArgs& a, int kind) {
   size_t slot = 0;
   rl_status st = timed_begin(p, kind, &slot);
   if (st != RL_OK) return st;
-  hipError_t e = rlmi::launch_xrow(mode, p->axx.E, p->x_grid, p->x_block, p->x_lds, p->stream, a,
-                                   p->axx.sc, p->tw_x);
+  dim3 grid = p->x_grid;
+  grid.y = (unsigned)a.nvol;
+  hipError_t e = rlmi::launch_xrow(mode, p->axx.E, p->precision, grid, p->x_block, p->x_lds,
+                                   p->stream, a, p->axx.sc, p->tw_x);
   if (e != hipSuccess) return hip_fail(e, "X pass launch");
   return timed_end(p, slot);
 }
@@ -434,42 +487,270 @@ rl_status run_yz_filter(rl_plan p, bool adjoint) {
   return run_pencil(p, p->py, rlmi::PM_INV, p->spec, p->tw_y, RL_KERNEL_Y);
 }
 
-rl_status create_impl(const int64_t shape[3], const float* psf, int boundary,
-                      const rl_options* opt, rl_plan* out) {
-  if (!out) return fail(RL_E_INVALID, "out is NULL");
-  *out = nullptr;
-  rl_status st = check_shape(shape);
+// Launch choice: elements per thread and lane widths per pass (0 = default).
+struct Choice {
+  int x_e = 0, y_e = 0, y_txb = 0, z_e = 0, z_txb = 0;
+};
+
+// X pass shape for E = x_e: each wavefront owns 64 / P whole rows, up to
+// kXMaxThreads / 64 waves per work-group.
+bool configure_x(rl_plan p, int x_e) {
+  Axis ax = make_axis(p->M, x_e > 0 ? x_e : pick_e_x(p->M));
+  ax.sc = make_sched(p->M, ax.E, 2);
+  if (ax.P > 64 || 64 % ax.P != 0) return false;
+  const int rows_per_wave = 64 / ax.P;
+  const int rs = (int)(p->M + 1 + ((p->M + 1) >> rlmi::kXPad) + 1);  // padded row
+  auto lds_for = [&](int w) {
+    return (size_t)(2 * p->M + (int64_t)w * rows_per_wave * rs) * sizeof(float2);
+  };
+  int waves = rlmi::kXMaxThreads / 64;
+  while (waves > 1 && lds_for(waves) > kMaxLds) waves >>= 1;
+  if (lds_for(waves) > kMaxLds) return false;
+  p->axx = ax;
+  p->x_rs = rs;
+  p->x_rpw = waves * rows_per_wave;
+  p->x_lds = lds_for(waves);
+  p->x_block = dim3((unsigned)(64 * waves));
+  p->x_grid = dim3((unsigned)((p->nrows + p->x_rpw - 1) / p->x_rpw));
+  p->ch_x_e = ax.E;
+  return true;
+}
+
+// Split-precision work-groups stay at <= 512 threads (their register budget).
+int pencil_thread_cap(rl_plan p) { return p->precision == RL_PRECISION_FP32 ? 1024 : 512; }
+
+bool configure_y(rl_plan p, int y_e, int y_txb) {
+  Pencil pc = make_pencil_y(p->ny, p->nz, p->xt, p->ncols, y_txb,
+                            y_e > 0 ? y_e : pick_e_y(p->ny), pencil_thread_cap(p));
+  if (!pencil_fits(pc) || (int)pc.block.x > pencil_thread_cap(p)) return false;
+  p->py = pc;
+  p->ch_y_e = pc.ax.E;
+  p->ch_y_txb = pc.args.TXB;
+  return true;
+}
+
+bool configure_z(rl_plan p, int z_e, int z_txb) {
+  Pencil pc = make_pencil_z(p->nz, p->ny, p->xt, p->ncols, z_txb, z_e, pencil_thread_cap(p));
+  if (!pencil_fits(pc) || (int)pc.block.x > pencil_thread_cap(p)) return false;
+  p->pz = pc;
+  p->ch_z_e = pc.ax.E;
+  p->ch_z_txb = pc.args.TXB;
+  return true;
+}
+
+bool configure(rl_plan p, const Choice& c) {
+  return configure_x(p, c.x_e) && configure_y(p, c.y_e, c.y_txb) && configure_z(p, c.z_e, c.z_txb);
+}
+
+// --- autotuner ---------------------------------------------------------------
+// Times candidate elements-per-thread and lane widths for each pass on the
+// plan's own buffers (HIP events, median of a few launches) and keeps the
+// fastest per pass; ties keep the earlier (default-first) candidate.  Results
+// can be cached in the text file named by RLMI_TUNE_CACHE, keyed by GPU
+// architecture, runtime version and shape.
+
+std::string tune_key(rl_plan p) {
+  hipDeviceProp_t prop;
+  std::memset(&prop, 0, sizeof(prop));
+  (void)hipGetDeviceProperties(&prop, p->device);
+  int rt = 0;
+  (void)hipRuntimeGetVersion(&rt);
+  std::ostringstream k;
+  k << prop.gcnArchName << "/hip" << rt << "/" << p->nz << "x" << p->ny << "x" << p->nx;
+  std::string s = k.str();
+  for (char& ch : s)
+    if (ch == ' ') ch = '_';
+  return s;
+}
+
+bool cache_lookup(const std::string& key, Choice* c) {
+  const char* path = std::getenv("RLMI_TUNE_CACHE");
+  if (!path || !*path) return false;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    std::istringstream ls(line);
+    std::string k;
+    Choice t;
+    if ((ls >> k >> t.x_e >> t.y_e >> t.y_txb >> t.z_e >> t.z_txb) && k == key) {
+      *c = t;
+      return true;
+    }
+  }
+  return false;
+}
+
+void cache_store(const std::string& key, const Choice& c) {
+  const char* path = std::getenv("RLMI_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::ofstream f(path, std::ios::app);
+  f << key << " " << c.x_e << " " << c.y_e << " " << c.y_txb << " " << c.z_e << " " << c.z_txb
+    << "\n";
+}
+
+
+// Median time (ms) of `reps` runs of `fn` on the plan's stream.
+template <typename F>
+rl_status time_ms(rl_plan p, F fn, float* ms) {
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventCreate");
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return hip_fail(hipGetLastError(), "hipEventCreate");
+  }
+  rl_status st = fn();  // warm-up
+  float t[3] = {0, 0, 0};
+  for (int r = 0; r < 3 && st == RL_OK; ++r) {
+    (void)hipEventRecord(a, p->stream);
+    st = fn();
+    (void)hipEventRecord(b, p->stream);
+    if (hipEventSynchronize(b) != hipSuccess) st = hip_fail(hipGetLastError(), "tuning run");
+    else (void)hipEventElapsedTime(&t[r], a, b);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  std::sort(t, t + 3);
+  *ms = t[1];
+  return st;
+}
+
+std::vector<int> e_candidates(int64_t L, int64_t max_p, int precision) {
+  std::vector<int> out;
+  if (precision != RL_PRECISION_FP32 && split_e(L, max_p) == 16) return {16};
+  for (int e : {4, 8, 16, 2, 6, 12, 24, 3})
+    if (e_ok(L, e, max_p)) out.push_back(e);
+  return out;
+}
+
+rl_status autotune(rl_plan p, Choice* best) {
+  float* dbuf = nullptr;
+  float* ubuf = nullptr;
+  const size_t bytes = (size_t)p->nvox * sizeof(float);
+  hipError_t e;
+  if ((e = hipMalloc(&dbuf, bytes)) != hipSuccess) return hip_fail(e, "hipMalloc(tuning)");
+  if ((e = hipMalloc(&ubuf, bytes)) != hipSuccess) {
+    (void)hipFree(dbuf);
+    return hip_fail(e, "hipMalloc(tuning)");
+  }
+  rl_status st = RL_OK;
+  // benign contents: d = u = 1.0, spectrum = 0
+  if ((e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(dbuf), 0x3f800000u, p->nvox,
+                             p->stream)) != hipSuccess ||
+      (e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(ubuf), 0x3f800000u, p->nvox,
+                             p->stream)) != hipSuccess ||
+      (e = hipMemsetAsync(p->spec, 0, p->spec_elems * sizeof(float2), p->stream)) != hipSuccess)
+    st = hip_fail(e, "tuning buffers");
+  Choice c = *best;
+  // X: fused ratio + update
+  float bt = 1e30f;
+  for (int xe : e_candidates(p->M, 64, p->precision)) {
+    if (st != RL_OK) break;
+    if (!configure_x(p, xe)) continue;
+    float ms = 0.f;
+    st = time_ms(p, [&]() {
+      XArgs r = base_xargs(p, p->spec);
+      r.d = dbuf;
+      rl_status s2 = run_x(p, rlmi::XM_RATIO, r, RL_KERNEL_OTHER);
+      if (s2 != RL_OK) return s2;
+      XArgs u = base_xargs(p, p->spec);
+      u.u = ubuf;
+      u.partials = p->partials;
+      u.iter = 0;
+      u.do_fwd = 1;
+      return run_x(p, rlmi::XM_UPDATE, u, RL_KERNEL_OTHER);
+    }, &ms);
+    if (st == RL_OK && ms < bt) {
+      bt = ms;
+      c.x_e = xe;
+    }
+  }
+  // Y: forward + inverse
+  bt = 1e30f;
+  if (p->ny > 1) {
+    for (int ye : e_candidates(p->ny, 1024, p->precision))
+      for (int w : {16, 8}) {
+        if (st != RL_OK || !configure_y(p, ye, w) || p->py.args.TXB != w) continue;
+        float ms = 0.f;
+        st = time_ms(p, [&]() {
+          rl_status s2 = run_pencil(p, p->py, rlmi::PM_FWD, p->spec, p->tw_y, RL_KERNEL_OTHER);
+          return s2 != RL_OK ? s2 : run_pencil(p, p->py, rlmi::PM_INV, p->spec, p->tw_y,
+                                               RL_KERNEL_OTHER);
+        }, &ms);
+        if (st == RL_OK && ms < bt) {
+          bt = ms;
+          c.y_e = ye;
+          c.y_txb = w;
+        }
+      }
+  }
+  // Z: forward * K * inverse
+  bt = 1e30f;
+  for (int ze : e_candidates(p->nz, 1024, p->precision))
+    for (int w : {32, 16, 64}) {
+      if (st != RL_OK || !configure_z(p, ze, w) || p->pz.args.TXB != w) continue;
+      float ms = 0.f;
+      st = time_ms(p, [&]() {
+        return run_pencil(p, p->pz, rlmi::PM_FKI, p->spec, p->tw_z, RL_KERNEL_OTHER);
+      }, &ms);
+      if (st == RL_OK && ms < bt) {
+        bt = ms;
+        c.z_e = ze;
+        c.z_txb = w;
+      }
+    }
+  (void)hipStreamSynchronize(p->stream);
+  (void)hipFree(dbuf);
+  (void)hipFree(ubuf);
   if (st != RL_OK) return st;
+  *best = c;
+  return RL_OK;
+}
+
+rl_status check_options(const int64_t shape[3], const rl_options* opt) {
+  if (!opt) return RL_OK;
+  if (opt->precision != RL_PRECISION_FP32 && opt->precision != RL_PRECISION_SPLIT_BF16 &&
+      opt->precision != RL_PRECISION_SPLIT_FP16)
+    return fail(RL_E_INVALID, "unknown precision");
+  if (opt->tile_x < 0 || opt->tile_x > 64) return fail(RL_E_INVALID, "tile_x must be in [0, 64]");
+  if (opt->x_elems != 0 && !e_ok(shape[2] / 2, opt->x_elems, 64))
+    return fail(RL_E_INVALID, "x_elems does not fit nx/2");
+  if (opt->yz_elems != 0 &&
+      (!e_ok(shape[1], opt->yz_elems, 1024) || !e_ok(shape[0], opt->yz_elems, 1024)))
+    return fail(RL_E_INVALID, "yz_elems does not fit ny and nz");
+  if (opt->autotune != 0 && opt->autotune != 1) return fail(RL_E_INVALID, "autotune must be 0 or 1");
+  return RL_OK;
+}
+
+rl_status check_boundary(int boundary) {
   if (boundary == RL_BOUNDARY_ZERO)
     return fail(RL_E_UNSUPPORTED, "only the periodic boundary is implemented");
   if (boundary != RL_BOUNDARY_PERIODIC) return fail(RL_E_INVALID, "unknown boundary");
-  if (opt && opt->precision != RL_PRECISION_FP32)
-    return fail(RL_E_UNSUPPORTED, "only FP32 precision is implemented");
-  if (opt && (opt->tile_x < 0 || opt->tile_x > 64))
-    return fail(RL_E_INVALID, "tile_x must be in [0, 64]");
-  if (opt && opt->x_elems != 0 && !e_ok(shape[2] / 2, opt->x_elems, 64))
-    return fail(RL_E_INVALID, "x_elems does not fit nx/2");
-  if (opt && opt->yz_elems != 0 &&
-      (!e_ok(shape[1], opt->yz_elems, 1024) || !e_ok(shape[0], opt->yz_elems, 1024)))
-    return fail(RL_E_INVALID, "yz_elems does not fit ny and nz");
-  if (!psf) return fail(RL_E_INVALID, "psf is NULL");
-  if (reinterpret_cast<uintptr_t>(psf) % 16 != 0)
-    return fail(RL_E_INVALID, "psf is not 16-byte aligned");
+  return RL_OK;
+}
+
+rl_status check_device_present() {
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
   if (e != hipSuccess || ndev < 1) {
     (void)hipGetLastError();
     return fail(RL_E_DEVICE, "no HIP device available");
   }
+  return RL_OK;
+}
+
+// Build the plan of `count` volumes of one (validated) shape on `device`;
+// psfs[i] is volume i's PSF (validated device pointers).  Synchronous.
+rl_status build_class(const int64_t shape[3], int count, const float* const* psfs, int device,
+                      const rl_options* opt, hipStream_t stream, rl_plan* out) {
+  rl_status st;
+  hipError_t e;
   const int64_t nz = shape[0], ny = shape[1], nx = shape[2];
   const int64_t nvox = nz * ny * nx;
-  int device = -1;
-  if ((st = check_dev_ptr(psf, (size_t)nvox * sizeof(float), &device, "psf")) != RL_OK) return st;
-
   rl_plan p = new (std::nothrow) rl_plan_s();
   if (!p) return fail(RL_E_NOMEM, "host allocation failed");
   p->device = device;
-  p->stream = opt ? reinterpret_cast<hipStream_t>(opt->stream) : nullptr;
+  p->stream = stream;
+  p->count = count;
   p->nz = nz;
   p->ny = ny;
   p->nx = nx;
@@ -480,43 +761,37 @@ rl_status create_impl(const int64_t shape[3], const float* psf, int boundary,
   p->nrows = nz * ny;
   p->spec_elems = (size_t)nz * p->xt * ny * rlmi::kTile;
 
-  // X pass shape
-  p->axx.L = p->M;
-  p->axx.E = (opt && opt->x_elems) ? opt->x_elems : pick_e_x(p->M);
-  p->axx.P = (int)(p->M / p->axx.E);
-  p->axx.sc = make_sched(p->M, p->axx.E, 2);
-  // each wavefront owns 64 / P whole rows; up to kXMaxThreads / 64 waves per work-group
-  const int rows_per_wave = 64 / p->axx.P;
-  int waves = rlmi::kXMaxThreads / 64;
-  p->x_rs = (int)(p->M + 1 + ((p->M + 1) >> rlmi::kXPad) + 1);  // padded row
-  auto x_lds_for = [&](int w) {
-    return (size_t)(2 * p->M + (int64_t)w * rows_per_wave * p->x_rs) * sizeof(float2);
-  };
-  while (waves > 1 && x_lds_for(waves) > kMaxLds) waves >>= 1;
-  p->x_rpw = waves * rows_per_wave;
-  p->x_lds = x_lds_for(waves);
-  p->x_block = dim3((unsigned)(64 * waves));
-  p->x_grid = dim3((unsigned)((p->nrows + p->x_rpw - 1) / p->x_rpw));
-  // Y: pencils along Y, outer = z; Z: pencils along Z, outer = y
-  const int tile_x = opt ? opt->tile_x : 0;
-  const int yz_e = opt ? opt->yz_elems : 0;
-  p->py = make_pencil_y(ny, nz, p->xt, p->ncols, tile_x, yz_e ? yz_e : pick_e_y(ny));
-  p->pz = make_pencil_z(nz, ny, p->xt, p->ncols, tile_x, yz_e);
-  if (p->x_lds > kMaxLds || p->py.lds > kMaxPencilLds || p->pz.lds > kMaxPencilLds ||
-      (int)p->py.block.x > max_threads_for(p->py.ax.E) ||
-      (int)p->pz.block.x > max_threads_for(p->pz.ax.E)) {
-    delete p;
-    return fail(RL_E_UNSUPPORTED, "shape needs more LDS than a work-group may use");
+  // launch choice: options first, defaults for the rest
+  p->precision = opt ? opt->precision : RL_PRECISION_FP32;
+  Choice choice;
+  if (p->precision != RL_PRECISION_FP32) {
+    // split precision runs radix-16 stages on MFMA: 16 elements per thread
+    // wherever the length has radix-16 stages (other lengths stay FP32)
+    choice.x_e = split_e(p->M, 64);
+    choice.y_e = split_e(ny, 1024);
+    choice.z_e = split_e(nz, 1024);
   }
-
+  if (opt) {
+    const int tx = opt->tile_x > 0 ? pow2_floor(opt->tile_x) : 0;
+    if (opt->x_elems) choice.x_e = opt->x_elems;
+    if (opt->yz_elems) choice.y_e = choice.z_e = opt->yz_elems;
+    choice.y_txb = tx > rlmi::kTile ? rlmi::kTile : tx;
+    choice.z_txb = tx;
+  }
+  const bool want_tune = opt && opt->autotune;
+  if (!configure(p, choice)) {
+    delete p;
+    return fail(RL_E_UNSUPPORTED, "shape needs more LDS or threads than a work-group may use");
+  }
   if ((e = hipSetDevice(device)) != hipSuccess) {
     delete p;
     return hip_fail(e, "hipSetDevice");
   }
   p->flux_cap = 128;
-  p->n_partials = (size_t)p->x_grid.x * p->flux_cap;
+  // >= any X grid times the iteration capacity times the volumes
+  p->n_partials = (size_t)p->nrows * p->flux_cap * count;
   if (p->n_partials < 3 * (size_t)kStatBlocks) p->n_partials = 3 * kStatBlocks;
-  const size_t spec_bytes = p->spec_elems * sizeof(float2);
+  const size_t spec_bytes = p->spec_elems * sizeof(float2) * (size_t)count;
   if ((e = hipMalloc(&p->spec, spec_bytes)) != hipSuccess ||
       (e = hipMalloc(&p->otf, spec_bytes)) != hipSuccess ||
       (e = hipMalloc(&p->tw_x, (size_t)nx * sizeof(float2))) != hipSuccess ||
@@ -525,7 +800,10 @@ rl_status create_impl(const int64_t shape[3], const float* psf, int boundary,
       (e = hipMalloc(&p->partials, p->n_partials * sizeof(double))) != hipSuccess ||
       (e = hipMalloc(&p->counter, 4 * sizeof(unsigned))) != hipSuccess ||
       (e = hipMalloc(&p->stats, 4 * sizeof(double))) != hipSuccess ||
-      (e = hipMalloc(&p->flux, (size_t)p->flux_cap * sizeof(double))) != hipSuccess) {
+      (e = hipMalloc(&p->flux, (size_t)p->flux_cap * count * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&p->iter_dev, sizeof(int))) != hipSuccess ||
+      (e = hipMalloc(&p->d_tab, (size_t)count * sizeof(float*))) != hipSuccess ||
+      (e = hipMalloc(&p->u_tab, (size_t)count * sizeof(float*))) != hipSuccess) {
     st = hip_fail(e, "hipMalloc");
     release(p);
     return st;
@@ -543,50 +821,168 @@ rl_status create_impl(const int64_t shape[3], const float* psf, int boundary,
   RL_TRY(rlmi::launch_twiddles(p->tw_x, (int)nx, p->stream));
   RL_TRY(rlmi::launch_twiddles(p->tw_y, (int)ny, p->stream));
   RL_TRY(rlmi::launch_twiddles(p->tw_z, (int)nz, p->stream));
-  RL_TRY(rlmi::launch_psf_stats(psf, nvox, p->partials, kStatBlocks, p->counter, p->stats,
-                                p->stream));
-  double stats[3] = {0, 0, 0};
-  RL_TRY(hipMemcpyAsync(stats, p->stats, 3 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
-  RL_TRY(hipStreamSynchronize(p->stream));
-  if (stats[2] != 0.0) {
-    release(p);
-    return fail(RL_E_INVALID, "psf has non-finite entries");
-  }
-  if (stats[1] < 0.0) {
-    release(p);
-    return fail(RL_E_INVALID, "psf has negative entries");
-  }
-  if (!(stats[0] > 0.0) || !std::isfinite(stats[0])) {
-    release(p);
-    return fail(RL_E_INVALID, "psf must have a positive finite sum");
-  }
-  // OTF / N: scaled, centred PSF written as dense real rows into the spectrum
-  // workspace, transformed along X into the OTF buffer, then along Y and Z.
-  const double scale = 1.0 / (stats[0] * (double)nvox);
-  RL_TRY(rlmi::launch_psf_prep(psf, reinterpret_cast<float*>(p->spec), (int)nz, (int)ny, (int)nx,
-                               nx, scale, p->stream));
-  XArgs a = base_xargs(p, p->otf);
-  a.rin = reinterpret_cast<const float*>(p->spec);
-  a.rin_stride = nx;
-  if ((st = run_x(p, rlmi::XM_R2C, a, RL_KERNEL_OTHER)) != RL_OK) {
-    release(p);
-    return st;
-  }
-  if ((st = run_pencil(p, p->py, rlmi::PM_FWD, p->otf, p->tw_y, RL_KERNEL_OTHER)) != RL_OK ||
-      (st = run_pencil(p, p->pz, rlmi::PM_FWD, p->otf, p->tw_z, RL_KERNEL_OTHER)) != RL_OK) {
-    release(p);
-    return st;
+  for (int v = 0; v < count; ++v) {
+    const float* psf = psfs[v];
+    RL_TRY(rlmi::launch_psf_stats(psf, nvox, p->partials, kStatBlocks, p->counter, p->stats,
+                                  p->stream));
+    double stats[3] = {0, 0, 0};
+    RL_TRY(hipMemcpyAsync(stats, p->stats, 3 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    RL_TRY(hipStreamSynchronize(p->stream));
+    const std::string which = count > 1 ? " (volume " + std::to_string(v) + " of its shape)" : "";
+    if (stats[2] != 0.0) {
+      release(p);
+      return fail(RL_E_INVALID, "psf has non-finite entries" + which);
+    }
+    if (stats[1] < 0.0) {
+      release(p);
+      return fail(RL_E_INVALID, "psf has negative entries" + which);
+    }
+    if (!(stats[0] > 0.0) || !std::isfinite(stats[0])) {
+      release(p);
+      return fail(RL_E_INVALID, "psf must have a positive finite sum" + which);
+    }
+    // OTF / N: scaled, centred PSF written as dense real rows into the spectrum
+    // workspace, transformed along X into the volume's OTF slot, then along Y and Z.
+    float2* otf_v = p->otf + (size_t)v * p->spec_elems;
+    const double scale = 1.0 / (stats[0] * (double)nvox);
+    RL_TRY(rlmi::launch_psf_prep(psf, reinterpret_cast<float*>(p->spec), (int)nz, (int)ny,
+                                 (int)nx, nx, scale, p->stream));
+    XArgs a = base_xargs(p, otf_v);
+    a.rin = reinterpret_cast<const float*>(p->spec);
+    a.rin_stride = nx;
+    a.nvol = 1;
+    if ((st = run_x(p, rlmi::XM_R2C, a, RL_KERNEL_OTHER)) != RL_OK ||
+        (st = run_pencil(p, p->py, rlmi::PM_FWD, otf_v, p->tw_y, RL_KERNEL_OTHER, 1)) != RL_OK ||
+        (st = run_pencil(p, p->pz, rlmi::PM_FWD, otf_v, p->tw_z, RL_KERNEL_OTHER, 1)) != RL_OK) {
+      release(p);
+      return st;
+    }
   }
   RL_TRY(hipStreamSynchronize(p->stream));
 #undef RL_TRY
+  if (want_tune) {
+    const std::string key = tune_key(p);
+    Choice tuned = choice;
+    if (!cache_lookup(key, &tuned)) {
+      if ((st = autotune(p, &tuned)) != RL_OK) {
+        release(p);
+        return st;
+      }
+      cache_store(key, tuned);
+    }
+    if (!configure(p, tuned)) {
+      release(p);
+      return fail(RL_E_INTERNAL, "tuned configuration does not apply");
+    }
+    p->tuned = true;
+  }
+  *out = p;
+  return RL_OK;
+}
+
+rl_status create_impl(const int64_t shape[3], const float* psf, int boundary,
+                      const rl_options* opt, rl_plan* out) {
+  if (!out) return fail(RL_E_INVALID, "out is NULL");
+  *out = nullptr;
+  rl_status st = check_shape(shape);
+  if (st != RL_OK) return st;
+  if ((st = check_boundary(boundary)) != RL_OK) return st;
+  if ((st = check_options(shape, opt)) != RL_OK) return st;
+  if (!psf) return fail(RL_E_INVALID, "psf is NULL");
+  if (reinterpret_cast<uintptr_t>(psf) % 16 != 0)
+    return fail(RL_E_INVALID, "psf is not 16-byte aligned");
+  if ((st = check_device_present()) != RL_OK) return st;
+  const int64_t nvox = shape[0] * shape[1] * shape[2];
+  int device = -1;
+  if ((st = check_dev_ptr(psf, (size_t)nvox * sizeof(float), &device, "psf")) != RL_OK) return st;
+  rl_plan p = nullptr;
+  const float* psfs[1] = {psf};
+  hipStream_t stream = opt ? reinterpret_cast<hipStream_t>(opt->stream) : nullptr;
+  if ((st = build_class(shape, 1, psfs, device, opt, stream, &p)) != RL_OK) return st;
   plan_register(p);
   *out = p;
   return RL_OK;
 }
 
+// Grow the per-iteration flux array and the [iteration][volume][work-group]
+// partial table of a (class) plan to hold n_iter iterations.
+rl_status ensure_flux_capacity(rl_plan p, int n_iter, bool* grew) {
+  if (grew) *grew = false;
+  if (n_iter <= p->flux_cap) return RL_OK;
+  double* nf = nullptr;
+  double* np = nullptr;
+  const size_t nparts = (size_t)n_iter * p->nrows * p->count;
+  hipError_t e;
+  if ((e = hipMalloc(&nf, (size_t)n_iter * p->count * sizeof(double))) != hipSuccess)
+    return hip_fail(e, "hipMalloc(flux)");
+  if ((e = hipMalloc(&np, nparts * sizeof(double))) != hipSuccess) {
+    (void)hipFree(nf);
+    return hip_fail(e, "hipMalloc(flux partials)");
+  }
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  else (void)hipDeviceSynchronize();
+  (void)hipFree(p->flux);
+  (void)hipFree(p->partials);
+  p->flux = nf;
+  p->partials = np;
+  p->n_partials = nparts;
+  p->flux_cap = n_iter;
+  if (grew) *grew = true;
+  return RL_OK;
+}
+
+// Spectrum of H u (transformed back along Z and Y) for every volume of the plan.
+// u == nullptr: per-volume estimates from the plan's device table.
+rl_status enqueue_prologue(rl_plan p, const float* u) {
+  XArgs a = base_xargs(p, p->spec);
+  a.rin = u;
+  a.rin_tab = u ? nullptr : p->u_tab;
+  a.rin_stride = p->nx;
+  rl_status st = run_x(p, rlmi::XM_R2C, a, RL_KERNEL_X_R2C);
+  return st != RL_OK ? st : run_yz_filter(p, false);
+}
+
+// One RL iteration for every volume of the plan (d/u == nullptr: device tables).
+// The iteration index for the flux partials is `it`, or *iter_ptr if non-null.
+rl_status enqueue_iteration(rl_plan p, const float* d, float* u, int it, const int* iter_ptr,
+                            bool do_fwd) {
+  rl_status st;
+  XArgs r = base_xargs(p, p->spec);
+  r.d = d;
+  r.d_tab = d ? nullptr : p->d_tab;
+  if ((st = run_x(p, rlmi::XM_RATIO, r, RL_KERNEL_X_RATIO)) != RL_OK) return st;
+  if ((st = run_yz_filter(p, true)) != RL_OK) return st;
+  XArgs w = base_xargs(p, p->spec);
+  w.u = u;
+  w.u_tab = u ? nullptr : p->u_tab;
+  w.partials = p->partials;
+  w.iter = it;
+  w.iter_ptr = iter_ptr;
+  w.do_fwd = do_fwd ? 1 : 0;
+  if ((st = run_x(p, rlmi::XM_UPDATE, w, RL_KERNEL_X_UPDATE)) != RL_OK) return st;
+  if (do_fwd && (st = run_yz_filter(p, false)) != RL_OK) return st;
+  return RL_OK;
+}
+
+// flux[it * count + v] for it < n_iter, on `stream`.
+rl_status enqueue_flux_reduce(rl_plan p, int n_iter, hipStream_t stream) {
+  hipStream_t keep = p->stream;
+  p->stream = stream;
+  size_t slot = 0;
+  rl_status st = timed_begin(p, RL_KERNEL_OTHER, &slot);
+  if (st == RL_OK) {
+    hipError_t e = rlmi::launch_flux_reduce(p->partials, (int)p->x_grid.x, n_iter * p->count,
+                                            p->flux, stream);
+    st = (e == hipSuccess) ? timed_end(p, slot) : hip_fail(e, "flux reduction launch");
+  }
+  p->stream = keep;
+  return st;
+}
+
 rl_status iterate_impl(rl_plan p, const float* observed, float* estimate, int n_iter) {
   rl_status st = check_plan(p);
   if (st != RL_OK) return st;
+  if (p->is_batch) return fail(RL_E_INVALID, "batch plans iterate with rl_iterate_batch");
   if (n_iter < 0) return fail(RL_E_INVALID, "n_iter must be >= 0");
   const size_t bytes = (size_t)p->nvox * sizeof(float);
   int dev = p->device;
@@ -595,58 +991,222 @@ rl_status iterate_impl(rl_plan p, const float* observed, float* estimate, int n_
   if (n_iter == 0) return RL_OK;
   hipError_t e = hipSetDevice(p->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-  if (n_iter > p->flux_cap) {
-    // grow the flux array and the [iteration][work-group] partial table
-    double* nf = nullptr;
-    double* np = nullptr;
-    const size_t nparts = (size_t)n_iter * p->x_grid.x;
-    if ((e = hipMalloc(&nf, (size_t)n_iter * sizeof(double))) != hipSuccess)
-      return hip_fail(e, "hipMalloc(flux)");
-    if ((e = hipMalloc(&np, nparts * sizeof(double))) != hipSuccess) {
-      (void)hipFree(nf);
-      return hip_fail(e, "hipMalloc(flux partials)");
-    }
-    if (p->stream) (void)hipStreamSynchronize(p->stream);
-    else (void)hipDeviceSynchronize();
-    (void)hipFree(p->flux);
-    (void)hipFree(p->partials);
-    p->flux = nf;
-    p->partials = np;
-    p->n_partials = nparts;
-    p->flux_cap = n_iter;
-  }
+  if ((st = ensure_flux_capacity(p, n_iter, nullptr)) != RL_OK) return st;
   p->flux_count = n_iter;
+  if ((st = enqueue_prologue(p, estimate)) != RL_OK) return st;
+  for (int it = 0; it < n_iter; ++it)
+    if ((st = enqueue_iteration(p, observed, estimate, it, nullptr, it + 1 < n_iter)) != RL_OK)
+      return st;
+  return enqueue_flux_reduce(p, n_iter, p->stream);
+}
 
-  // prologue: spectrum of H u0, transformed back along Z and Y
-  XArgs a = base_xargs(p, p->spec);
-  a.rin = estimate;
-  a.rin_stride = p->nx;
-  if ((st = run_x(p, rlmi::XM_R2C, a, RL_KERNEL_X_R2C)) != RL_OK) return st;
-  if ((st = run_yz_filter(p, false)) != RL_OK) return st;
-  for (int it = 0; it < n_iter; ++it) {
-    XArgs r = base_xargs(p, p->spec);
-    r.d = observed;
-    if ((st = run_x(p, rlmi::XM_RATIO, r, RL_KERNEL_X_RATIO)) != RL_OK) return st;
-    if ((st = run_yz_filter(p, true)) != RL_OK) return st;
-    XArgs u = base_xargs(p, p->spec);
-    u.u = estimate;
-    u.partials = p->partials;
-    u.iter = it;
-    u.do_fwd = (it + 1 < n_iter) ? 1 : 0;
-    if ((st = run_x(p, rlmi::XM_UPDATE, u, RL_KERNEL_X_UPDATE)) != RL_OK) return st;
-    if (u.do_fwd && (st = run_yz_filter(p, false)) != RL_OK) return st;
+// --- batched volumes -----------------------------------------------------------
+
+rl_status create_batch_impl(int count, const int64_t* shapes, const float* const* psfs,
+                            int boundary, const rl_options* opt, rl_plan* out) {
+  if (!out) return fail(RL_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (count < 1 || count > 65535) return fail(RL_E_INVALID, "count must be in [1, 65535]");
+  if (!shapes || !psfs) return fail(RL_E_INVALID, "shapes or psfs is NULL");
+  rl_status st;
+  for (int v = 0; v < count; ++v) {
+    if ((st = check_shape(shapes + 3 * v)) != RL_OK)
+      return fail(st, "volume " + std::to_string(v) + ": " + g_err);
+    if ((st = check_options(shapes + 3 * v, opt)) != RL_OK)
+      return fail(st, "volume " + std::to_string(v) + ": " + g_err);
+    if (!psfs[v]) return fail(RL_E_INVALID, "psf of volume " + std::to_string(v) + " is NULL");
+    if (reinterpret_cast<uintptr_t>(psfs[v]) % 16 != 0)
+      return fail(RL_E_INVALID, "psf of volume " + std::to_string(v) + " is not 16-byte aligned");
   }
-  size_t slot = 0;
-  if ((st = timed_begin(p, RL_KERNEL_OTHER, &slot)) != RL_OK) return st;
-  if ((e = rlmi::launch_flux_reduce(p->partials, (int)p->x_grid.x, n_iter, p->flux, p->stream)) !=
-      hipSuccess)
-    return hip_fail(e, "flux reduction launch");
-  return timed_end(p, slot);
+  if ((st = check_boundary(boundary)) != RL_OK) return st;
+  if (opt && opt->tile_x != 0)
+    return fail(RL_E_INVALID, "batch plans choose work-group widths per shape (tile_x must be 0)");
+  if ((st = check_device_present()) != RL_OK) return st;
+  int device = -1;
+  for (int v = 0; v < count; ++v) {
+    const int64_t nvox = shapes[3 * v] * shapes[3 * v + 1] * shapes[3 * v + 2];
+    if ((st = check_dev_ptr(psfs[v], (size_t)nvox * sizeof(float), &device,
+                            "psf of a volume")) != RL_OK)
+      return st;
+  }
+  rl_plan b = new (std::nothrow) rl_plan_s();
+  if (!b) return fail(RL_E_NOMEM, "host allocation failed");
+  b->is_batch = true;
+  b->device = device;
+  b->stream = opt ? reinterpret_cast<hipStream_t>(opt->stream) : nullptr;
+  b->count = count;
+  b->nz = shapes[0];
+  b->ny = shapes[1];
+  b->nx = shapes[2];
+  b->vol_class.assign(count, -1);
+  b->vol_index.assign(count, -1);
+  hipError_t e;
+  if ((e = hipSetDevice(device)) != hipSuccess) {
+    delete b;
+    return hip_fail(e, "hipSetDevice");
+  }
+  if ((e = hipMalloc(&b->iter_dev, sizeof(int))) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&b->fork_event, hipEventDisableTiming)) != hipSuccess) {
+    st = hip_fail(e, "batch setup");
+    release(b);
+    return st;
+  }
+  // classes: volumes of equal shape, in order of first appearance
+  for (int v = 0; v < count; ++v) {
+    if (b->vol_class[v] >= 0) continue;
+    const int64_t* sh = shapes + 3 * v;
+    std::vector<int> members;
+    for (int w = v; w < count; ++w)
+      if (shapes[3 * w] == sh[0] && shapes[3 * w + 1] == sh[1] && shapes[3 * w + 2] == sh[2])
+        members.push_back(w);
+    hipStream_t cs = nullptr;
+    hipEvent_t ce = nullptr;
+    if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) {
+      st = hip_fail(e, "hipStreamCreate");
+      release(b);
+      return st;
+    }
+    b->cls_streams.push_back(cs);
+    if ((e = hipEventCreateWithFlags(&ce, hipEventDisableTiming)) != hipSuccess) {
+      st = hip_fail(e, "hipEventCreate");
+      release(b);
+      return st;
+    }
+    b->cls_events.push_back(ce);
+    std::vector<const float*> cpsf;
+    for (int w : members) cpsf.push_back(psfs[w]);
+    rl_plan c = nullptr;
+    if ((st = build_class(sh, (int)members.size(), cpsf.data(), device, opt, cs, &c)) != RL_OK) {
+      const std::string msg = g_err;
+      release(b);
+      return fail(st, msg);
+    }
+    const int ci = (int)b->classes.size();
+    b->classes.push_back(c);
+    for (size_t k = 0; k < members.size(); ++k) {
+      b->vol_class[members[k]] = ci;
+      b->vol_index[members[k]] = (int)k;
+    }
+  }
+  plan_register(b);
+  *out = b;
+  return RL_OK;
+}
+
+// One iteration of every class, forked from and joined back into b->stream
+// (captured into a graph by the caller).
+rl_status enqueue_batch_iteration(rl_plan b, bool do_fwd) {
+  hipError_t e;
+  rl_status st;
+  if ((e = hipEventRecord(b->fork_event, b->stream)) != hipSuccess)
+    return hip_fail(e, "hipEventRecord");
+  for (size_t c = 0; c < b->classes.size(); ++c) {
+    rl_plan cl = b->classes[c];
+    if ((e = hipStreamWaitEvent(cl->stream, b->fork_event, 0)) != hipSuccess)
+      return hip_fail(e, "hipStreamWaitEvent");
+    if ((st = enqueue_iteration(cl, nullptr, nullptr, 0, b->iter_dev, do_fwd)) != RL_OK) return st;
+    if ((e = hipEventRecord(b->cls_events[c], cl->stream)) != hipSuccess)
+      return hip_fail(e, "hipEventRecord");
+    if ((e = hipStreamWaitEvent(b->stream, b->cls_events[c], 0)) != hipSuccess)
+      return hip_fail(e, "hipStreamWaitEvent");
+  }
+  if ((e = rlmi::launch_advance(b->iter_dev, b->stream)) != hipSuccess)
+    return hip_fail(e, "iteration counter launch");
+  return RL_OK;
+}
+
+rl_status capture_graph(rl_plan b, bool do_fwd, hipGraphExec_t* exec) {
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  rl_status st = enqueue_batch_iteration(b, do_fwd);
+  e = hipStreamEndCapture(b->stream, &g);
+  if (st != RL_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return e == hipSuccess ? RL_OK : hip_fail(e, "hipGraphInstantiate");
+}
+
+rl_status iterate_batch_impl(rl_plan b, const float* const* observed, float* const* estimate,
+                             int n_iter) {
+  rl_status st = check_plan(b);
+  if (st != RL_OK) return st;
+  if (!b->is_batch) return fail(RL_E_INVALID, "not a batch plan (use rl_iterate)");
+  if (n_iter < 0) return fail(RL_E_INVALID, "n_iter must be >= 0");
+  if (!observed || !estimate) return fail(RL_E_INVALID, "observed or estimate is NULL");
+  for (int v = 0; v < b->count; ++v) {
+    const rl_plan c = b->classes[b->vol_class[v]];
+    const size_t bytes = (size_t)c->nvox * sizeof(float);
+    int dev = b->device;
+    if ((st = check_dev_ptr(observed[v], bytes, &dev, "observed volume")) != RL_OK ||
+        (st = check_dev_ptr(estimate[v], bytes, &dev, "estimate volume")) != RL_OK)
+      return fail(st, "volume " + std::to_string(v) + ": " + g_err);
+  }
+  if (n_iter == 0) return RL_OK;
+  hipError_t e = hipSetDevice(b->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  bool rebuild = false;
+  for (rl_plan c : b->classes) {
+    bool grew = false;
+    if ((st = ensure_flux_capacity(c, n_iter, &grew)) != RL_OK) return st;
+    rebuild = rebuild || grew;
+    c->flux_count = n_iter;
+  }
+  if (rebuild) {  // partial tables moved: captured kernel arguments are stale
+    if (b->graph_full) (void)hipGraphExecDestroy(b->graph_full);
+    if (b->graph_last) (void)hipGraphExecDestroy(b->graph_last);
+    b->graph_full = b->graph_last = nullptr;
+  }
+  // per-volume pointer tables (ordered after earlier work on b->stream)
+  for (size_t ci = 0; ci < b->classes.size(); ++ci) {
+    rl_plan c = b->classes[ci];
+    std::vector<const float*> dt(c->count);
+    std::vector<float*> ut(c->count);
+    for (int v = 0; v < b->count; ++v)
+      if (b->vol_class[v] == (int)ci) {
+        dt[b->vol_index[v]] = observed[v];
+        ut[b->vol_index[v]] = estimate[v];
+      }
+    if ((e = hipMemcpyAsync(c->d_tab, dt.data(), dt.size() * sizeof(float*),
+                            hipMemcpyHostToDevice, b->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(c->u_tab, ut.data(), ut.size() * sizeof(float*),
+                            hipMemcpyHostToDevice, b->stream)) != hipSuccess)
+      return hip_fail(e, "pointer tables");
+  }
+  if ((e = rlmi::launch_set_counter(b->iter_dev, 0, b->stream)) != hipSuccess)
+    return hip_fail(e, "iteration counter launch");
+  // prologue per class, forked from and joined back into b->stream
+  if ((e = hipEventRecord(b->fork_event, b->stream)) != hipSuccess)
+    return hip_fail(e, "hipEventRecord");
+  for (size_t ci = 0; ci < b->classes.size(); ++ci) {
+    rl_plan c = b->classes[ci];
+    if ((e = hipStreamWaitEvent(c->stream, b->fork_event, 0)) != hipSuccess)
+      return hip_fail(e, "hipStreamWaitEvent");
+    if ((st = enqueue_prologue(c, nullptr)) != RL_OK) return st;
+    if ((e = hipEventRecord(b->cls_events[ci], c->stream)) != hipSuccess ||
+        (e = hipStreamWaitEvent(b->stream, b->cls_events[ci], 0)) != hipSuccess)
+      return hip_fail(e, "prologue join");
+  }
+  if (!b->graph_full && (st = capture_graph(b, true, &b->graph_full)) != RL_OK) return st;
+  if (!b->graph_last && (st = capture_graph(b, false, &b->graph_last)) != RL_OK) return st;
+  for (int it = 0; it < n_iter; ++it)
+    if ((e = hipGraphLaunch(it + 1 < n_iter ? b->graph_full : b->graph_last, b->stream)) !=
+        hipSuccess)
+      return hip_fail(e, "hipGraphLaunch");
+  for (rl_plan c : b->classes)
+    if ((st = enqueue_flux_reduce(c, n_iter, b->stream)) != RL_OK) return st;
+  b->batch_n = n_iter;
+  return RL_OK;
 }
 
 rl_status conv_impl(rl_plan p, const float* x, float* out) {
   rl_status st = check_plan(p);
   if (st != RL_OK) return st;
+  if (p->is_batch) return fail(RL_E_UNSUPPORTED, "conv3d_fft takes a single-volume plan");
   const size_t bytes = (size_t)p->nvox * sizeof(float);
   int dev = p->device;
   if ((st = check_dev_ptr(x, bytes, &dev, "x")) != RL_OK) return st;
@@ -689,6 +1249,26 @@ rl_status rl_plan_create_ex(const int64_t shape[3], const float* psf, int bounda
   }
 }
 
+rl_status rl_plan_create_batch(int count, const int64_t* shapes, const float* const* psfs,
+                               int boundary, const rl_options* opt, rl_plan* out) {
+  try {
+    return create_batch_impl(count, shapes, psfs, boundary, opt, out);
+  } catch (const std::bad_alloc&) {
+    return fail(RL_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(RL_E_INTERNAL, "unexpected exception in rl_plan_create_batch");
+  }
+}
+
+rl_status rl_iterate_batch(rl_plan p, const float* const* observed, float* const* estimate,
+                           int n_iter) {
+  try {
+    return iterate_batch_impl(p, observed, estimate, n_iter);
+  } catch (...) {
+    return fail(RL_E_INTERNAL, "unexpected exception in rl_iterate_batch");
+  }
+}
+
 rl_status rl_iterate(rl_plan p, const float* observed, float* estimate, int n_iter) {
   try {
     return iterate_impl(p, observed, estimate, n_iter);
@@ -728,16 +1308,35 @@ rl_status rl_plan_get_flux(rl_plan p, double* flux, int cap, int* n_written) {
   hipError_t e = hipSetDevice(p->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return hip_fail(e, "execution");
-  const int n = p->flux_count;
-  std::vector<double> h((size_t)n);
-  if (n > 0 && (e = hipMemcpy(h.data(), p->flux, (size_t)n * sizeof(double),
-                              hipMemcpyDeviceToHost)) != hipSuccess)
-    return hip_fail(e, "hipMemcpy(flux)");
+  std::vector<double> h;
+  if (!p->is_batch) {
+    const int n = p->flux_count;
+    h.resize((size_t)n);
+    if (n > 0 && (e = hipMemcpy(h.data(), p->flux, (size_t)n * sizeof(double),
+                                hipMemcpyDeviceToHost)) != hipSuccess)
+      return hip_fail(e, "hipMemcpy(flux)");
+  } else {
+    // volume-major: flux[v * n + it]
+    const int n = p->batch_n;
+    h.assign((size_t)n * p->count, 0.0);
+    for (size_t ci = 0; ci < p->classes.size() && n > 0; ++ci) {
+      rl_plan c = p->classes[ci];
+      std::vector<double> cf((size_t)n * c->count);
+      if ((e = hipMemcpy(cf.data(), c->flux, cf.size() * sizeof(double),
+                         hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy(flux)");
+      for (int v = 0; v < p->count; ++v)
+        if (p->vol_class[v] == (int)ci)
+          for (int it = 0; it < n; ++it)
+            h[(size_t)v * n + it] = cf[(size_t)it * c->count + p->vol_index[v]];
+    }
+  }
+  const int n = (int)h.size();
   *n_written = n;
   for (int i = 0; i < n && i < cap; ++i) flux[i] = h[(size_t)i];
   for (int i = 0; i < n; ++i)
     if (!std::isfinite(h[(size_t)i]))
-      return fail(RL_E_NUMERIC, "non-finite flux at iteration " + std::to_string(i));
+      return fail(RL_E_NUMERIC, "non-finite flux at entry " + std::to_string(i));
   return RL_OK;
 }
 
@@ -753,9 +1352,24 @@ rl_status rl_plan_get_info(rl_plan p, int64_t shape[3], int64_t* spectrum_pitch)
   return RL_OK;
 }
 
+rl_status rl_plan_get_launch(rl_plan p, int out[6]) {
+  rl_status st = check_plan(p);
+  if (st != RL_OK) return st;
+  if (!out) return fail(RL_E_INVALID, "out is NULL");
+  if (p->is_batch) p = p->classes[0];  // configuration of the first volume's shape
+  out[0] = p->ch_x_e;
+  out[1] = p->ch_y_e;
+  out[2] = p->ch_y_txb;
+  out[3] = p->ch_z_e;
+  out[4] = p->ch_z_txb;
+  out[5] = p->tuned ? 1 : 0;
+  return RL_OK;
+}
+
 rl_status rl_plan_set_timing(rl_plan p, int enable) {
   rl_status st = check_plan(p);
   if (st != RL_OK) return st;
+  if (p->is_batch) return fail(RL_E_UNSUPPORTED, "batch plans replay graphs; time them whole");
   p->timing = enable != 0;
   p->n_events = 0;
   return RL_OK;

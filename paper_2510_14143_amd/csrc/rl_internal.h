@@ -48,6 +48,7 @@ struct PencilArgs {
   long long xstride;
   long long ostride;
   long long estride;
+  long long vstride;  // complex elements between volumes (work-group z index = volume)
 };
 
 enum PencilMode { PM_FWD = 0, PM_INV = 1, PM_FKI = 2, PM_FCKI = 3 };
@@ -65,8 +66,17 @@ struct XArgs {
   long long rout_stride;
   const float* d;        // XM_RATIO: observed rows (dense, nx floats apart)
   float* u;              // XM_UPDATE: estimate rows (dense), updated in place
-  double* partials;      // XM_UPDATE: FP64 partial flux, [iter][work-group]
+  // Batched volumes (work-group y index = volume): when a table is non-null the
+  // volume's pointer is taken from it instead of rin / rout / d / u above.
+  const float* const* rin_tab;
+  float* const* rout_tab;
+  const float* const* d_tab;
+  float* const* u_tab;
+  long long vstride;     // complex elements between the volumes' spectra
+  double* partials;      // XM_UPDATE: FP64 partial flux, [iter][volume][work-group]
   int iter;
+  const int* iter_ptr;   // XM_UPDATE: if non-null, the iteration index is *iter_ptr
+  int nvol;              // volumes in this launch (>= 1)
   int do_fwd;            // XM_UPDATE: also transform the new estimate forward
   int M;                 // complex row length nx/2
   int P;                 // threads per row (M / E)
@@ -77,15 +87,22 @@ struct XArgs {
 
 // Pencil kernels exist for work-groups of up to 512 threads (all E) and up to
 // 1024 threads (E = 8 and 16 only).
-hipError_t launch_pencil(int mode, int E, dim3 grid, dim3 block, size_t lds, hipStream_t s,
-                         float2* data, const float2* otf, const float2* tw,
+// prec: 0 = FP32 butterflies; 1 / 2 = radix-16 stages of E = 16 transforms on
+// MFMA with BF16 / FP16 hi-lo split operands (other stages stay FP32).
+hipError_t launch_pencil(int mode, int E, int prec, dim3 grid, dim3 block, size_t lds,
+                         hipStream_t s, float2* data, const float2* otf, const float2* tw,
                          const PencilArgs& a, const Sched& sc);
-hipError_t launch_xrow(int mode, int E, dim3 grid, dim3 block, size_t lds, hipStream_t s,
-                       const XArgs& a, const Sched& sc, const float2* tw);
+hipError_t launch_xrow(int mode, int E, int prec, dim3 grid, dim3 block, size_t lds,
+                       hipStream_t s, const XArgs& a, const Sched& sc, const float2* tw);
 hipError_t launch_twiddles(float2* tab, int n, hipStream_t s);
-// flux[it] = sum_g partials[it * groups + g] for it < n_iter, summed in a fixed order.
-hipError_t launch_flux_reduce(const double* partials, int groups, int n_iter, double* flux,
+// flux[r] = sum_g partials[r * groups + g] for r < rows (a row is one
+// (iteration, volume) pair), summed in a fixed order.
+hipError_t launch_flux_reduce(const double* partials, int groups, int rows, double* flux,
                               hipStream_t s);
+// *counter += 1 (one thread); used to advance a device-side iteration index.
+hipError_t launch_advance(int* counter, hipStream_t s);
+// *counter = value (one thread).
+hipError_t launch_set_counter(int* counter, int value, hipStream_t s);
 // out[0] = sum(h), out[1] = min(h), out[2] = number of non-finite entries (FP64).
 hipError_t launch_psf_stats(const float* h, long long n, double* partials, int nblk,
                             unsigned* counter, double* out, hipStream_t s);

@@ -43,6 +43,21 @@ __device__ __forceinline__ float2 mul_si(float2 a) {
   return S > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
 }
 
+// Ordering point for LDS traffic that stays inside one wavefront: the lanes of
+// a wave execute in lock step and a wave's LDS operations complete in issue
+// order, so only the compiler must be kept from moving accesses across it.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool WAVE>
+__device__ __forceinline__ void exch_sync() {
+  if constexpr (WAVE) wave_sync();
+  else __syncthreads();
+}
+
 // cos(2 pi k / 16), k = 0..15
 __device__ constexpr float kCos16[16] = {
     1.0f,  0.92387953251128674f,  0.70710678118654752f,  0.38268343236508977f,
@@ -138,6 +153,128 @@ struct Dft {
 };
 
 // ---------------------------------------------------------------------------
+// Split-precision 16-point DFT on MFMA
+// ---------------------------------------------------------------------------
+// A 16-point complex DFT is the 32x32 real matrix [[Fr, -S Fi], [S Fi, Fr]]
+// applied to (re_0..15, im_0..15).  A wavefront computes its 64 threads' DFTs
+// as 4 groups of 16 columns with v_mfma_f32_16x16x32_{bf16,f16}: operands are
+// split x = hi + lo (hi = RNE(x), lo = RNE(x - hi)) and the three products
+// Fhi*Xhi + Fhi*Xlo + Flo*Xhi accumulate in FP32.  FP16 inputs are scaled per
+// DFT by a power of two (largest magnitude below 2^14); the scale is undone on
+// the FP32 result.  Operand lane layout (16x16x32): lane l holds A row l%16 and
+// B column l%16 over K = 8*(l/16) .. +7; D rows 4*(l/16) .. +3 of column l%16.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int PREC>
+struct SplitT;
+
+template <>
+struct SplitT<1> {  // BF16 hi/lo
+  typedef __bf16 T;
+  typedef __bf16 V8 __attribute__((ext_vector_type(8)));
+  static constexpr bool kScale = false;
+  __device__ __forceinline__ static f32x4 mma(V8 a, V8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct SplitT<2> {  // FP16 hi/lo with a power-of-two scale per DFT
+  typedef _Float16 T;
+  typedef _Float16 V8 __attribute__((ext_vector_type(8)));
+  static constexpr bool kScale = true;
+  __device__ __forceinline__ static f32x4 mma(V8 a, V8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+// y[0..15] of every thread of the wavefront <- its 16-point DFT (sign S).
+// `stg` is a wave-private LDS area of 64 * 32 floats; all 64 lanes must call.
+template <int PREC, int S>
+__device__ __forceinline__ void dft16_mfma(float2 (&y)[16], float* stg) {
+  typedef SplitT<PREC> ST;
+  typedef typename ST::T T;
+  typedef typename ST::V8 V8;
+  const int l = threadIdx.x & 63;
+  const int n = l & 15, g = l >> 4;
+  // A operands: row m = n of the re-output and im-output blocks, K = 8g .. 8g+7
+  V8 are_hi, are_lo, aim_hi, aim_lo;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int kk = 8 * g + q, k = kk & 15, t = (n * k) & 15;
+    const float c = kCos16[t], sn = kCos16[(t + 12) & 15];
+    const float ar = kk < 16 ? c : -S * sn;
+    const float ai = kk < 16 ? S * sn : c;
+    const T arh = (T)ar, aih = (T)ai;
+    are_hi[q] = arh;
+    are_lo[q] = (T)(ar - (float)arh);
+    aim_hi[q] = aih;
+    aim_lo[q] = (T)(ai - (float)aih);
+  }
+  // stage the inputs: thread t's (re_0..15, im_0..15) at stg[32 t ..]
+  float* mine = stg + 32 * l;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    mine[j] = y[j].x;
+    mine[16 + j] = y[j].y;
+  }
+  wave_sync();
+  f32x4 dr[4], di[4];
+  float inv[4];
+#pragma unroll
+  for (int grp = 0; grp < 4; ++grp) {
+    const float* src = stg + 32 * (16 * grp + n) + 8 * g;
+    float x[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) x[q] = src[q];
+    float sc = 1.f;
+    inv[grp] = 1.f;
+    if constexpr (ST::kScale) {
+      float mx = 0.f;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) mx = fmaxf(mx, fabsf(x[q]));
+      mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+      mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+      if (mx > 0.f && isfinite(mx)) {
+        int e;
+        (void)frexpf(mx, &e);  // mx < 2^e
+        sc = ldexpf(1.f, 14 - e);
+        inv[grp] = ldexpf(1.f, e - 14);
+      }
+    }
+    V8 bh, bl;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const float xs = x[q] * sc;
+      const T h = (T)xs;
+      bh[q] = h;
+      bl[q] = (T)(xs - (float)h);
+    }
+    f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    f32x4 r = ST::mma(are_hi, bh, z);
+    r = ST::mma(are_hi, bl, r);
+    dr[grp] = ST::mma(are_lo, bh, r);
+    f32x4 im = ST::mma(aim_hi, bh, z);
+    im = ST::mma(aim_hi, bl, im);
+    di[grp] = ST::mma(aim_lo, bh, im);
+  }
+  wave_sync();  // every lane has read its operands
+#pragma unroll
+  for (int grp = 0; grp < 4; ++grp) {
+    float* dst = stg + 32 * (16 * grp + n);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      dst[4 * g + q] = dr[grp][q] * inv[grp];
+      dst[16 + 4 * g + q] = di[grp][q] * inv[grp];
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < 16; ++j) y[j] = make_float2(mine[j], mine[16 + j]);
+  wave_sync();
+}
+
+// ---------------------------------------------------------------------------
 // Stockham stages
 // ---------------------------------------------------------------------------
 // tw: table of exp(-2 pi i m / T) (forward sign); inverse transforms conjugate it.
@@ -150,9 +287,13 @@ __device__ __forceinline__ int lslot(int n) {
   else return n;
 }
 
-template <int E, int R, int S, int PAD>
+// PREC > 0 with R = E = 16: the butterfly runs on MFMA (dft16_mfma) using the
+// wave's staging area `stg`; a barrier (WAVE: wavefront, else work-group)
+// separates that from the stage's LDS output writes.
+template <int E, int R, int S, int PAD, int PREC = 0, bool WAVE = false>
 __device__ __forceinline__ void stage(float2 (&v)[E], int i, int P, int p, int tm, bool last,
-                                      const float2* __restrict__ tw, float2* lds, int ls, int lo) {
+                                      const float2* __restrict__ tw, float2* lds, int ls, int lo,
+                                      float* stg = nullptr) {
   constexpr int V = E / R;
 #pragma unroll
   for (int q = 0; q < V; ++q) {
@@ -168,7 +309,12 @@ __device__ __forceinline__ void stage(float2 (&v)[E], int i, int P, int p, int t
         y[j] = (S < 0) ? cmul(y[j], w) : cmulc(y[j], w);
       }
     }
-    Dft<R, S>::run(y);
+    if constexpr (PREC > 0 && R == 16 && E == 16) {
+      dft16_mfma<PREC, S>(y, stg);
+      exch_sync<WAVE>();  // all staging areas are free before outputs land in LDS
+    } else {
+      Dft<R, S>::run(y);
+    }
     if (last) {
 #pragma unroll
       for (int j = 0; j < R; ++j) v[q + j * V] = y[j];
@@ -180,33 +326,20 @@ __device__ __forceinline__ void stage(float2 (&v)[E], int i, int P, int p, int t
   }
 }
 
-// Ordering point for LDS traffic that stays inside one wavefront: the lanes of
-// a wave execute in lock step and a wave's LDS operations complete in issue
-// order, so only the compiler must be kept from moving accesses across it.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <bool WAVE>
-__device__ __forceinline__ void exch_sync() {
-  if constexpr (WAVE) wave_sync();
-  else __syncthreads();
-}
-
 // Full 1-D transform of this thread's pencil; natural order in and out.
 // WAVE = false: the pencil spans the work-group and every thread must call this
 // (it contains barriers).  WAVE = true: the pencil lives inside one wavefront.
-template <int E, int S, bool WAVE = false, int PAD = 0>
+template <int E, int S, bool WAVE = false, int PAD = 0, int PREC = 0>
 __device__ __forceinline__ void fft(float2 (&v)[E], const Sched& sc, int i, int P,
-                                    const float2* __restrict__ tw, float2* lds, int ls, int lo) {
+                                    const float2* __restrict__ tw, float2* lds, int ls, int lo,
+                                    float* stg = nullptr) {
   for (int s = 0; s < sc.ns; ++s) {
     const bool last = (s == sc.ns - 1);
     const int r = sc.r[s], p = sc.p[s], tm = sc.tm[s];
     switch (r) {
       case 16:
-        if constexpr (E % 16 == 0) stage<E, 16, S, PAD>(v, i, P, p, tm, last, tw, lds, ls, lo);
+        if constexpr (E % 16 == 0)
+          stage<E, 16, S, PAD, PREC, WAVE>(v, i, P, p, tm, last, tw, lds, ls, lo, stg);
         break;
       case 8:
         if constexpr (E % 8 == 0) stage<E, 8, S, PAD>(v, i, P, p, tm, last, tw, lds, ls, lo);
@@ -241,7 +374,7 @@ __device__ __forceinline__ void fft(float2 (&v)[E], const Sched& sc, int i, int 
 // reads one contiguous tile column).
 // 1024-thread work-groups of E = 8 are held to 64 VGPRs (8 waves per SIMD), so
 // that two of them share a CU.
-template <int E, int MODE, int MAXT>
+template <int E, int MODE, int MAXT, int PREC = 0>
 __global__ void __launch_bounds__(MAXT, (MAXT == 1024 && E == 8) ? 8 : 1)
     k_pencil(float2* __restrict__ data, const float2* __restrict__ otf,
              const float2* __restrict__ twg, PencilArgs a, Sched sc) {
@@ -255,7 +388,8 @@ __global__ void __launch_bounds__(MAXT, (MAXT == 1024 && E == 8) ? 8 : 1)
   const int xb = blockIdx.x / a.xsplit;
   const int c = (blockIdx.x - xb * a.xsplit) * a.TXB + lane;
   const bool ok = xb * kTile + (c & (kTile - 1)) < a.ncols;
-  const long long base = (long long)xb * a.xstride + (long long)blockIdx.y * a.ostride + c;
+  const long long base = (long long)blockIdx.z * a.vstride + (long long)xb * a.xstride +
+                         (long long)blockIdx.y * a.ostride + c;
 
   float2 v[E];
 #pragma unroll
@@ -263,7 +397,9 @@ __global__ void __launch_bounds__(MAXT, (MAXT == 1024 && E == 8) ? 8 : 1)
     v[m] = ok ? data[base + (long long)(i + a.P * m) * a.estride] : make_float2(0.f, 0.f);
   __syncthreads();  // twiddles in LDS
 
-  if constexpr (MODE != PM_INV) fft<E, -1>(v, sc, i, a.P, tw, lds, a.TXP, lane);
+  // split-precision stages stage their operands in this wave's slice of the exchange buffer
+  float* stg = reinterpret_cast<float*>(lds) + (tid >> 6) * (64 * 32);
+  if constexpr (MODE != PM_INV) fft<E, -1, false, 0, PREC>(v, sc, i, a.P, tw, lds, a.TXP, lane, stg);
   if constexpr (MODE == PM_FKI || MODE == PM_FCKI) {
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -271,7 +407,7 @@ __global__ void __launch_bounds__(MAXT, (MAXT == 1024 && E == 8) ? 8 : 1)
       v[m] = (MODE == PM_FKI) ? cmul(v[m], k) : cmulc(v[m], k);
     }
   }
-  if constexpr (MODE != PM_FWD) fft<E, +1>(v, sc, i, a.P, tw, lds, a.TXP, lane);
+  if constexpr (MODE != PM_FWD) fft<E, +1, false, 0, PREC>(v, sc, i, a.P, tw, lds, a.TXP, lane, stg);
 
   if (ok) {
 #pragma unroll
@@ -294,11 +430,11 @@ __device__ __forceinline__ long long col_off(int kx, long long tstride) {
   return (long long)(kx >> 4) * tstride + (kx & (kTile - 1));
 }
 
-template <int E>
+template <int E, int PREC>
 __device__ __forceinline__ void r2c_store(float2 (&v)[E], int M, int P, const Sched& sc, int i,
                                           const float2* tw, float2* row, bool ok,
-                                          float2* __restrict__ out, long long ts) {
-  fft<E, -1, true, kXPad>(v, sc, i, P, tw, row, 1, 0);
+                                          float2* __restrict__ out, long long ts, float* stg) {
+  fft<E, -1, true, kXPad, PREC>(v, sc, i, P, tw, row, 1, 0, stg);
 #pragma unroll
   for (int m = 0; m < E; ++m) row[lslot<kXPad>(i + P * m)] = v[m];
   wave_sync();
@@ -337,7 +473,7 @@ __device__ __forceinline__ void c2r_prepare(float2 (&v)[E], float2 nyq, int M, i
   wave_sync();
 }
 
-template <int E, int MODE>
+template <int E, int MODE, int PREC = 0>
 __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const float2* __restrict__ twg) {
   extern __shared__ float2 lds[];
   const int M = a.M, P = a.P;
@@ -352,17 +488,21 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
   const bool ok = rowi < a.nrows;
   const long long rix = ok ? rowi : 0;
   float2* row = lds + 2 * M + lrow * a.RS;
+  // split-precision stages: the wave's rows double as its staging area (>= 64 * 32 floats)
+  float* stg = reinterpret_cast<float*>(lds + 2 * M + wave * rpw * a.RS);
+  const int vol = blockIdx.y;
   const int zz = (int)(rix / a.ny), yy = (int)(rix - (long long)zz * a.ny);
-  float2* srow = a.spec + (long long)zz * a.zstride + yy * kTile;
+  float2* srow = a.spec + (long long)vol * a.vstride + (long long)zz * a.zstride + yy * kTile;
   const long long ts = a.tstride;
 
   float2 v[E];
   if constexpr (MODE == XM_R2C) {
-    const float2* in = reinterpret_cast<const float2*>(a.rin + rix * a.rin_stride);
+    const float* rin = a.rin_tab ? a.rin_tab[vol] : a.rin;
+    const float2* in = reinterpret_cast<const float2*>(rin + rix * a.rin_stride);
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = ok ? in[i + P * m] : make_float2(0.f, 0.f);
     __syncthreads();  // twiddles in LDS
-    r2c_store<E>(v, M, P, sc, i, tw, row, ok, srow, ts);
+    r2c_store<E, PREC>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
   } else {
     // issue every global load of the row first
     float2 w[(MODE == XM_RATIO || MODE == XM_UPDATE) ? E : 1];
@@ -370,21 +510,24 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
     for (int m = 0; m < E; ++m) v[m] = ok ? srow[col_off(i + P * m, ts)] : make_float2(0.f, 0.f);
     const float2 nyq = (ok && i == 0) ? srow[col_off(M, ts)] : make_float2(0.f, 0.f);
     if constexpr (MODE == XM_RATIO) {
-      const float2* dr = reinterpret_cast<const float2*>(a.d + rix * (2LL * M));
+      const float* dbase = a.d_tab ? a.d_tab[vol] : a.d;
+      const float2* dr = reinterpret_cast<const float2*>(dbase + rix * (2LL * M));
 #pragma unroll
       for (int m = 0; m < E; ++m) w[m] = ok ? dr[i + P * m] : make_float2(0.f, 0.f);
     } else if constexpr (MODE == XM_UPDATE) {
-      const float2* ur = reinterpret_cast<const float2*>(a.u + rix * (2LL * M));
+      const float* ubase = a.u_tab ? a.u_tab[vol] : a.u;
+      const float2* ur = reinterpret_cast<const float2*>(ubase + rix * (2LL * M));
 #pragma unroll
       for (int m = 0; m < E; ++m) w[m] = ok ? ur[i + P * m] : make_float2(0.f, 0.f);
     }
     __syncthreads();  // twiddles in LDS
     c2r_prepare<E>(v, nyq, M, P, i, tw, row);
-    fft<E, +1, true, kXPad>(v, sc, i, P, tw, row, 1, 0);
+    fft<E, +1, true, kXPad, PREC>(v, sc, i, P, tw, row, 1, 0, stg);
     // v[m] holds (x[2n], x[2n+1]) for n = i + P*m (unnormalised; the 1/N is in the OTF)
     if constexpr (MODE == XM_C2R) {
       if (ok) {
-        float2* out = reinterpret_cast<float2*>(a.rout + rix * a.rout_stride);
+        float* rout = a.rout_tab ? a.rout_tab[vol] : a.rout;
+        float2* out = reinterpret_cast<float2*>(rout + rix * a.rout_stride);
 #pragma unroll
         for (int m = 0; m < E; ++m) out[i + P * m] = v[m];
       }
@@ -395,9 +538,9 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
         v[m] = make_float2(q.x > 1e-12f ? w[m].x / q.x : 0.f, q.y > 1e-12f ? w[m].y / q.y : 0.f);
       }
       wave_sync();  // row buffer reuse
-      r2c_store<E>(v, M, P, sc, i, tw, row, ok, srow, ts);
+      r2c_store<E, PREC>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
     } else {  // XM_UPDATE
-      float2* ur = reinterpret_cast<float2*>(a.u + rix * (2LL * M));
+      float2* ur = reinterpret_cast<float2*>((a.u_tab ? a.u_tab[vol] : a.u) + rix * (2LL * M));
       double acc = 0.0;
 #pragma unroll
       for (int m = 0; m < E; ++m) {
@@ -412,7 +555,7 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
       }
       if (a.do_fwd) {
         wave_sync();
-        r2c_store<E>(v, M, P, sc, i, tw, row, ok, srow, ts);
+        r2c_store<E, PREC>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
       }
       // work-group partial of the flux: wavefront butterfly, then the waves in order
 #pragma unroll
@@ -424,13 +567,15 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
         double t = 0.0;
         const int nw = blockDim.x >> 6;
         for (int q = 0; q < nw; ++q) t += wsum[q];
-        a.partials[(long long)a.iter * gridDim.x + blockIdx.x] = t;
+        const int it = a.iter_ptr ? *a.iter_ptr : a.iter;
+        a.partials[((long long)it * a.nvol + vol) * gridDim.x + blockIdx.x] = t;
       }
     }
   }
 }
 
-// flux[it] = sum of the work-group partials of iteration it, in a fixed order.
+// flux[r] = sum of the work-group partials of row r (one iteration of one
+// volume), in a fixed order.
 __global__ void __launch_bounds__(256) k_flux_reduce(const double* __restrict__ partials, int groups,
                                                      double* __restrict__ flux) {
   const int it = blockIdx.x, tid = threadIdx.x;
@@ -544,28 +689,38 @@ __global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ src,
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <int MODE, int MAXT, int EV>
+template <int MODE, int MAXT, int EV, int PREC = 0>
 static hipError_t pencil_one(dim3 g, dim3 b, size_t lds, hipStream_t s, float2* data,
                              const float2* otf, const float2* tw, const PencilArgs& a,
                              const Sched& sc) {
   if (lds > 65536) {
     static bool attr_done = false;  // once per instantiation
     if (!attr_done) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pencil<EV, MODE, MAXT>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+      hipError_t e =
+          hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pencil<EV, MODE, MAXT, PREC>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
       if (e != hipSuccess) return e;
       attr_done = true;
     }
   }
-  hipLaunchKernelGGL((k_pencil<EV, MODE, MAXT>), g, b, lds, s, data, otf, tw, a, sc);
+  hipLaunchKernelGGL((k_pencil<EV, MODE, MAXT, PREC>), g, b, lds, s, data, otf, tw, a, sc);
   return hipGetLastError();
 }
 
 template <int MODE>
-static hipError_t pencil_e(int E, dim3 g, dim3 b, size_t lds, hipStream_t s, float2* data,
-                           const float2* otf, const float2* tw, const PencilArgs& a,
+static hipError_t pencil_e(int E, int prec, dim3 g, dim3 b, size_t lds, hipStream_t s,
+                           float2* data, const float2* otf, const float2* tw, const PencilArgs& a,
                            const Sched& sc) {
   if (b.x > 1024) return hipErrorInvalidValue;
+  if (b.x % 64 != 0) prec = 0;  // MFMA stages need whole wavefronts
+  if (E == 16 && prec == 1) {
+    return b.x > 512 ? pencil_one<MODE, 1024, 16, 1>(g, b, lds, s, data, otf, tw, a, sc)
+                     : pencil_one<MODE, 512, 16, 1>(g, b, lds, s, data, otf, tw, a, sc);
+  }
+  if (E == 16 && prec == 2) {
+    return b.x > 512 ? pencil_one<MODE, 1024, 16, 2>(g, b, lds, s, data, otf, tw, a, sc)
+                     : pencil_one<MODE, 512, 16, 2>(g, b, lds, s, data, otf, tw, a, sc);
+  }
   if (b.x > 512) {
     switch (E) {
       case 8: return pencil_one<MODE, 1024, 8>(g, b, lds, s, data, otf, tw, a, sc);
@@ -584,21 +739,29 @@ static hipError_t pencil_e(int E, dim3 g, dim3 b, size_t lds, hipStream_t s, flo
   }
 }
 
-hipError_t launch_pencil(int mode, int E, dim3 grid, dim3 block, size_t lds, hipStream_t s,
-                         float2* data, const float2* otf, const float2* tw,
+hipError_t launch_pencil(int mode, int E, int prec, dim3 grid, dim3 block, size_t lds,
+                         hipStream_t s, float2* data, const float2* otf, const float2* tw,
                          const PencilArgs& a, const Sched& sc) {
   switch (mode) {
-    case PM_FWD: return pencil_e<PM_FWD>(E, grid, block, lds, s, data, otf, tw, a, sc);
-    case PM_INV: return pencil_e<PM_INV>(E, grid, block, lds, s, data, otf, tw, a, sc);
-    case PM_FKI: return pencil_e<PM_FKI>(E, grid, block, lds, s, data, otf, tw, a, sc);
-    case PM_FCKI: return pencil_e<PM_FCKI>(E, grid, block, lds, s, data, otf, tw, a, sc);
+    case PM_FWD: return pencil_e<PM_FWD>(E, prec, grid, block, lds, s, data, otf, tw, a, sc);
+    case PM_INV: return pencil_e<PM_INV>(E, prec, grid, block, lds, s, data, otf, tw, a, sc);
+    case PM_FKI: return pencil_e<PM_FKI>(E, prec, grid, block, lds, s, data, otf, tw, a, sc);
+    case PM_FCKI: return pencil_e<PM_FCKI>(E, prec, grid, block, lds, s, data, otf, tw, a, sc);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int MODE>
-static hipError_t xrow_e(int E, dim3 g, dim3 b, size_t lds, hipStream_t s, const XArgs& a,
-                         const Sched& sc, const float2* tw) {
+static hipError_t xrow_e(int E, int prec, dim3 g, dim3 b, size_t lds, hipStream_t s,
+                         const XArgs& a, const Sched& sc, const float2* tw) {
+  if (E == 16 && prec == 1) {
+    hipLaunchKernelGGL((k_xrow<16, MODE, 1>), g, b, lds, s, a, sc, tw);
+    return hipGetLastError();
+  }
+  if (E == 16 && prec == 2) {
+    hipLaunchKernelGGL((k_xrow<16, MODE, 2>), g, b, lds, s, a, sc, tw);
+    return hipGetLastError();
+  }
   switch (E) {
 #define RL_CASE(EV)                                                      \
   case EV:                                                               \
@@ -613,20 +776,38 @@ static hipError_t xrow_e(int E, dim3 g, dim3 b, size_t lds, hipStream_t s, const
   return hipGetLastError();
 }
 
-hipError_t launch_xrow(int mode, int E, dim3 grid, dim3 block, size_t lds, hipStream_t s,
-                       const XArgs& a, const Sched& sc, const float2* tw) {
+hipError_t launch_xrow(int mode, int E, int prec, dim3 grid, dim3 block, size_t lds,
+                       hipStream_t s, const XArgs& a, const Sched& sc, const float2* tw) {
   switch (mode) {
-    case XM_R2C: return xrow_e<XM_R2C>(E, grid, block, lds, s, a, sc, tw);
-    case XM_C2R: return xrow_e<XM_C2R>(E, grid, block, lds, s, a, sc, tw);
-    case XM_RATIO: return xrow_e<XM_RATIO>(E, grid, block, lds, s, a, sc, tw);
-    case XM_UPDATE: return xrow_e<XM_UPDATE>(E, grid, block, lds, s, a, sc, tw);
+    case XM_R2C: return xrow_e<XM_R2C>(E, prec, grid, block, lds, s, a, sc, tw);
+    case XM_C2R: return xrow_e<XM_C2R>(E, prec, grid, block, lds, s, a, sc, tw);
+    case XM_RATIO: return xrow_e<XM_RATIO>(E, prec, grid, block, lds, s, a, sc, tw);
+    case XM_UPDATE: return xrow_e<XM_UPDATE>(E, prec, grid, block, lds, s, a, sc, tw);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_flux_reduce(const double* partials, int groups, int n_iter, double* flux,
+hipError_t launch_flux_reduce(const double* partials, int groups, int rows, double* flux,
                               hipStream_t s) {
-  hipLaunchKernelGGL(k_flux_reduce, dim3(n_iter), dim3(256), 0, s, partials, groups, flux);
+  hipLaunchKernelGGL(k_flux_reduce, dim3(rows), dim3(256), 0, s, partials, groups, flux);
+  return hipGetLastError();
+}
+
+__global__ void k_advance(int* counter) {
+  if (threadIdx.x == 0) counter[0] += 1;
+}
+
+__global__ void k_set_counter(int* counter, int value) {
+  if (threadIdx.x == 0) counter[0] = value;
+}
+
+hipError_t launch_advance(int* counter, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_counter(int* counter, int value, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(64), 0, s, counter, value);
   return hipGetLastError();
 }
 

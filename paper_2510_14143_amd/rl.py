@@ -23,7 +23,9 @@ HEADER_PATH = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__fil
 
 RL_OK, RL_E_INVALID, RL_E_UNSUPPORTED, RL_E_NOMEM, RL_E_DEVICE, RL_E_NUMERIC, RL_E_INTERNAL = range(7)
 RL_BOUNDARY_PERIODIC, RL_BOUNDARY_ZERO = 0, 1
-RL_PRECISION_FP32 = 0
+RL_PRECISION_FP32, RL_PRECISION_SPLIT_BF16, RL_PRECISION_SPLIT_FP16 = 0, 1, 2
+_PRECISIONS = {"fp32": RL_PRECISION_FP32, "split_bf16": RL_PRECISION_SPLIT_BF16,
+               "split_fp16": RL_PRECISION_SPLIT_FP16}
 KERNEL_KINDS = ("x_r2c", "x_c2r", "x_ratio", "x_update", "y", "z_otf", "z", "other")
 
 
@@ -41,7 +43,7 @@ _STATUS_NAMES = {0: "RL_OK", 1: "RL_E_INVALID", 2: "RL_E_UNSUPPORTED", 3: "RL_E_
 
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("stream", ctypes.c_void_p), ("tile_x", ctypes.c_int),
-                ("x_elems", ctypes.c_int), ("yz_elems", ctypes.c_int)]
+                ("x_elems", ctypes.c_int), ("yz_elems", ctypes.c_int), ("autotune", ctypes.c_int)]
 
 
 _lib = None
@@ -67,10 +69,15 @@ def lib() -> ctypes.CDLL:
         "rl_plan_get_flux": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                               ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "rl_plan_get_info": ([vp, i64p, i64p], ctypes.c_int),
+        "rl_plan_get_launch": ([vp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "rl_plan_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
         "rl_plan_get_timing": ([vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)],
                                ctypes.c_int),
         "rl_probe_copy": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
+        "rl_plan_create_batch": ([ctypes.c_int, i64p, ctypes.POINTER(vp), ctypes.c_int,
+                                  ctypes.POINTER(_Options), ctypes.POINTER(vp)], ctypes.c_int),
+        "rl_iterate_batch": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int],
+                             ctypes.c_int),
         "rl_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "rl_last_error": ([], ctypes.c_char_p),
     }
@@ -114,10 +121,10 @@ def rl_plan_create(shape, psf_ptr: int, boundary: int = RL_BOUNDARY_PERIODIC) ->
 
 def rl_plan_create_ex(shape, psf_ptr: int, boundary: int = RL_BOUNDARY_PERIODIC,
                       precision: int = RL_PRECISION_FP32, stream: int = 0, tile_x: int = 0,
-                      x_elems: int = 0, yz_elems: int = 0) -> int:
+                      x_elems: int = 0, yz_elems: int = 0, autotune: bool = False) -> int:
     out = ctypes.c_void_p()
     opt = _Options(int(precision), ctypes.c_void_p(stream or None), int(tile_x), int(x_elems),
-                   int(yz_elems))
+                   int(yz_elems), 1 if autotune else 0)
     _check(lib().rl_plan_create_ex(_shape(shape), ctypes.c_void_p(psf_ptr), int(boundary),
                                    ctypes.byref(opt), ctypes.byref(out)))
     return out.value
@@ -130,6 +137,29 @@ def rl_iterate(plan: int, observed_ptr: int, estimate_ptr: int, n_iter: int) -> 
 
 def conv3d_fft(plan: int, x_ptr: int, out_ptr: int) -> None:
     _check(lib().conv3d_fft(ctypes.c_void_p(plan), ctypes.c_void_p(x_ptr), ctypes.c_void_p(out_ptr)))
+
+
+def rl_plan_create_batch(shapes, psf_ptrs, boundary: int = RL_BOUNDARY_PERIODIC,
+                         stream: int = 0, x_elems: int = 0, yz_elems: int = 0,
+                         autotune: bool = False) -> int:
+    n = len(shapes)
+    if len(psf_ptrs) != n:
+        raise ValueError("one PSF per volume")
+    sh = (ctypes.c_int64 * (3 * n))(*[int(v) for s3 in shapes for v in s3])
+    ps = (ctypes.c_void_p * n)(*psf_ptrs)
+    out = ctypes.c_void_p()
+    opt = _Options(RL_PRECISION_FP32, ctypes.c_void_p(stream or None), 0, int(x_elems),
+                   int(yz_elems), 1 if autotune else 0)
+    _check(lib().rl_plan_create_batch(n, sh, ps, int(boundary), ctypes.byref(opt),
+                                      ctypes.byref(out)))
+    return out.value
+
+
+def rl_iterate_batch(plan: int, observed_ptrs, estimate_ptrs, n_iter: int) -> None:
+    n = len(observed_ptrs)
+    ob = (ctypes.c_void_p * n)(*observed_ptrs)
+    es = (ctypes.c_void_p * n)(*estimate_ptrs)
+    _check(lib().rl_iterate_batch(ctypes.c_void_p(plan), ob, es, int(n_iter)))
 
 
 def rl_plan_destroy(plan: int) -> None:
@@ -156,6 +186,13 @@ def rl_plan_get_info(plan: int):
     pitch = ctypes.c_int64(0)
     _check(lib().rl_plan_get_info(ctypes.c_void_p(plan), shape, ctypes.byref(pitch)))
     return tuple(shape), pitch.value
+
+
+def rl_plan_get_launch(plan: int) -> dict:
+    out = (ctypes.c_int * 6)()
+    _check(lib().rl_plan_get_launch(ctypes.c_void_p(plan), out))
+    return dict(x_elems=out[0], y_elems=out[1], y_lanes=out[2], z_elems=out[3], z_lanes=out[4],
+                tuned=bool(out[5]))
 
 
 def rl_plan_set_timing(plan: int, enable: bool) -> None:
@@ -209,7 +246,7 @@ class Plan:
     """Richardson-Lucy plan for one volume shape and PSF (a float32 CUDA tensor [Z][Y][X])."""
 
     def __init__(self, psf, boundary: str = "periodic", tile_x: int = 0, x_elems: int = 0,
-                 yz_elems: int = 0):
+                 yz_elems: int = 0, autotune: bool = False, precision: str = "fp32"):
         bmap = {"periodic": RL_BOUNDARY_PERIODIC, "zero": RL_BOUNDARY_ZERO}
         if boundary not in bmap:
             raise ValueError("boundary must be 'periodic' or 'zero'")
@@ -218,9 +255,12 @@ class Plan:
         _check_volume(psf, psf.shape, None, "psf")
         self.shape = tuple(int(s) for s in psf.shape)
         self.device = psf.device
+        if precision not in _PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(_PRECISIONS)}")
         self.handle = rl_plan_create_ex(self.shape, psf.data_ptr(), bmap[boundary],
+                                        precision=_PRECISIONS[precision],
                                         stream=_stream_of(self.device), tile_x=tile_x,
-                                        x_elems=x_elems, yz_elems=yz_elems)
+                                        x_elems=x_elems, yz_elems=yz_elems, autotune=autotune)
 
     def _bind_stream(self):
         rl_plan_set_stream(self.handle, _stream_of(self.device))
@@ -263,6 +303,73 @@ class Plan:
     def info(self):
         self._live()
         return rl_plan_get_info(self.handle)
+
+    def launch(self) -> dict:
+        """Elements per thread and work-group widths in use (and whether tuned)."""
+        self._live()
+        return rl_plan_get_launch(self.handle)
+
+    def _live(self):
+        if getattr(self, "handle", None) is None:
+            raise RLError(RL_E_INVALID, "plan is closed")
+
+    def close(self) -> None:
+        h = getattr(self, "handle", None)
+        if h is not None:
+            self.handle = None
+            rl_plan_destroy(h)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchPlan:
+    """Batched plan: volumes of uneven shape, each with its own PSF (float32 CUDA tensors)."""
+
+    def __init__(self, psfs, autotune: bool = False, x_elems: int = 0, yz_elems: int = 0):
+        if len(psfs) == 0:
+            raise ValueError("at least one volume")
+        for i, h in enumerate(psfs):
+            if h.dim() != 3:
+                raise ValueError(f"psf {i} must be 3-D")
+            _check_volume(h, h.shape, psfs[0].device, f"psf {i}")
+        self.shapes = [tuple(int(v) for v in h.shape) for h in psfs]
+        self.device = psfs[0].device
+        self.handle = rl_plan_create_batch(self.shapes, [h.data_ptr() for h in psfs],
+                                           stream=_stream_of(self.device), x_elems=x_elems,
+                                           yz_elems=yz_elems, autotune=autotune)
+
+    def iterate(self, observed, estimates, n_iter: int) -> None:
+        """n_iter iterations of every volume, in place on `estimates` (lists of tensors)."""
+        self._live()
+        if len(observed) != len(self.shapes) or len(estimates) != len(self.shapes):
+            raise ValueError("one observed and one estimate tensor per volume")
+        for i, shp in enumerate(self.shapes):
+            _check_volume(observed[i], shp, self.device, f"observed {i}")
+            _check_volume(estimates[i], shp, self.device, f"estimate {i}")
+        rl_plan_set_stream(self.handle, _stream_of(self.device))
+        rl_iterate_batch(self.handle, [t.data_ptr() for t in observed],
+                         [t.data_ptr() for t in estimates], n_iter)
+
+    def flux(self) -> np.ndarray:
+        """(volumes, iterations) FP64 flux of the last iterate() call (synchronises)."""
+        self._live()
+        rl_plan_set_stream(self.handle, _stream_of(self.device))
+        f = rl_plan_get_flux(self.handle)
+        return f.reshape(len(self.shapes), -1)
+
+    def launch(self) -> dict:
+        self._live()
+        return rl_plan_get_launch(self.handle)
 
     def _live(self):
         if getattr(self, "handle", None) is None:

@@ -1,0 +1,130 @@
+"""GPU checks of the batched form: uneven volumes with their own PSFs, one
+graph launch per iteration, against the FP64 oracle and against single-volume
+plans (same kernels, so equal bit for bit)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_14143_amd import rl, synth
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(12, 24, 24), (16, 32, 32), (12, 24, 24), (24, 48, 48), (16, 32, 32), (8, 16, 64)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to("cuda:0")
+
+
+def cases():
+    out = []
+    for i, shp in enumerate(SHAPES):
+        sig = (1.0 + 0.3 * i, 1.2 + 0.2 * i, 2.0 + 0.25 * i)
+        out.append(synth.small_case(shp, sigma_xyz=sig, seed=20 + i, density=4.0))
+    return out
+
+
+def test_batch_matches_oracle_and_single_plans(torch):
+    say("batch vs oracle and single plans")
+    cs = cases()
+    n_iter = 10
+    with rl.BatchPlan([dev(torch, c["psf"]) for c in cs]) as bp:
+        d = [dev(torch, c["d"]) for c in cs]
+        u = [dev(torch, c["u0"]) for c in cs]
+        bp.iterate(d, u, n_iter)
+        flux = bp.flux()
+    assert flux.shape == (len(cs), n_iter)
+    for i, c in enumerate(cs):
+        ref, ref_flux, _ = oracle.rl(c["d"], c["psf"], c["u0"], n_iter)
+        got = u[i].cpu().numpy()
+        err = oracle.rel_l2(got, ref)
+        say("  volume", i, c["shape"], "relL2", err)
+        assert err <= 1e-4
+        assert np.max(np.abs(flux[i] - ref_flux) / ref_flux) <= 1e-6
+        with rl.Plan(dev(torch, c["psf"])) as p:
+            us = dev(torch, c["u0"])
+            p.iterate(d[i], us, n_iter)
+            torch.cuda.synchronize()
+        assert torch.equal(us, u[i]), i
+
+
+def test_batch_graph_replays_and_resume(torch):
+    say("batch graph replays")
+    cs = cases()
+    with rl.BatchPlan([dev(torch, c["psf"]) for c in cs]) as bp:
+        d = [dev(torch, c["d"]) for c in cs]
+        a = [dev(torch, c["u0"]) for c in cs]
+        bp.iterate(d, a, 7)
+        b = [dev(torch, c["u0"]) for c in cs]
+        for k in (3, 1, 3):  # separate calls replay the same graphs
+            bp.iterate(d, b, k)
+            junk = torch.randn(1 << 20, device="cuda:0")  # eager work between replays
+            junk.mul_(2.0).sum().item()
+        torch.cuda.synchronize()
+        for i in range(len(cs)):
+            assert torch.equal(a[i], b[i]), i
+        # one iteration, then zero (no-op)
+        e = [dev(torch, c["u0"]) for c in cs]
+        bp.iterate(d, e, 1)
+        bp.iterate(d, e, 0)
+        torch.cuda.synchronize()
+        assert bp.flux().shape == (len(cs), 1)
+
+
+def test_batch_more_iterations_than_initial_capacity(torch):
+    # 130 > initial flux capacity: partial tables grow and the graphs are rebuilt
+    say("batch capacity growth")
+    cs = cases()[:2]
+    with rl.BatchPlan([dev(torch, c["psf"]) for c in cs]) as bp:
+        d = [dev(torch, c["d"]) for c in cs]
+        u = [dev(torch, c["u0"]) for c in cs]
+        bp.iterate(d, u, 3)
+        bp.iterate(d, u, 130)
+        f = bp.flux()
+    assert f.shape == (2, 130)
+    for i, c in enumerate(cs):
+        total = float(c["d"].sum(dtype=np.float64))
+        assert np.all(np.abs(f[i] - total) / total <= 1e-6)
+
+
+def test_batch_errors(torch):
+    say("batch errors")
+    cs = cases()[:2]
+    psfs = [dev(torch, c["psf"]) for c in cs]
+    with pytest.raises(rl.RLError):
+        rl.rl_plan_create_batch([], [])
+    bad = cs[0]["psf"].copy()
+    bad[0, 0, 0] = -1
+    with pytest.raises(rl.RLError) as ei:
+        rl.BatchPlan([psfs[0], dev(torch, bad)])
+    assert ei.value.status == rl.RL_E_INVALID
+    with rl.BatchPlan(psfs) as bp:
+        d = [dev(torch, c["d"]) for c in cs]
+        u = [dev(torch, c["u0"]) for c in cs]
+        host = np.ones(16, np.float32)
+        with pytest.raises(rl.RLError) as ei:  # a host pointer is refused
+            rl.rl_iterate_batch(bp.handle, [d[0].data_ptr(), host.ctypes.data],
+                                [u[0].data_ptr(), u[1].data_ptr()], 1)
+        assert ei.value.status == rl.RL_E_INVALID
+        with pytest.raises(rl.RLError):
+            rl.rl_iterate_batch(bp.handle, [d[0].data_ptr(), d[1].data_ptr()],
+                                [u[0].data_ptr(), u[1].data_ptr()], -1)
+        with pytest.raises(rl.RLError):
+            rl.rl_iterate(bp.handle, d[0].data_ptr(), u[0].data_ptr(), 1)
+        with pytest.raises(rl.RLError):
+            rl.conv3d_fft(bp.handle, d[0].data_ptr(), u[0].data_ptr())

@@ -110,6 +110,35 @@ def test_rl_elems_options(torch):
     assert oracle.rel_l2(got, ref) <= RL_TOL
 
 
+def test_autotuned_plan_matches_oracle(torch, tmp_path, monkeypatch):
+    shape = (24, 48, 96)
+    say("autotune")
+    monkeypatch.setenv("RLMI_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    c = synth.small_case(shape, seed=9)
+    ref, _, _ = oracle.rl(c["d"], c["psf"], c["u0"], 6)
+    for attempt in range(2):  # second plan reads the cache
+        with rl.Plan(dev(torch, c["psf"]), autotune=True) as p:
+            cfg = p.launch()
+            assert cfg["tuned"]
+            u = dev(torch, c["u0"])
+            p.iterate(dev(torch, c["d"]), u, 6)
+            got = u.cpu().numpy()
+        assert oracle.rel_l2(got, ref) <= RL_TOL, cfg
+    lines = (tmp_path / "tune.txt").read_text().splitlines()
+    assert len(lines) == 1 and "24x48x96" in lines[0]
+
+
+@pytest.mark.parametrize("tile_x", [3, 24, 48])
+def test_odd_tile_width_requests(torch, tile_x):
+    # non-power-of-two requests round down to a power of two
+    shape = (6, 24, 64)
+    say("tile_x", tile_x)
+    x = synth.uniform_volume(shape, 104)
+    psf = rand_psf(shape, 15)
+    got = gpu_conv(torch, x, psf, tile_x=tile_x)
+    assert oracle.rel_l2(got, oracle.conv3d(x, psf)) <= CONV_TOL
+
+
 def test_conv_in_place(torch):
     shape = (8, 16, 32)
     say("conv in place")
