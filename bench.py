@@ -195,6 +195,50 @@ def run_batched(torch, rl, synth, steps: int, warmup: int, count: int = 96, n_it
             "speedup_vs_plain": round(out["plain"] / out["batched"], 3), "flux_drift": drift}
 
 
+def run_split(torch, rl, synth, steps: int, cfg: int = 2):
+    """Split-precision forms on the organoid-scale volume: time per step against the
+    plain FP32 form, and relative L2 to the FP32 result after 10 and 50 iterations."""
+    c = synth.make_config(cfg)
+    n_iter = c["n_iter"]
+    dev = torch.device("cuda:0")
+    psf = torch.from_numpy(c["psf"]).to(dev)
+    d = torch.from_numpy(c["d"]).to(dev)
+    u0 = torch.from_numpy(c["u0"]).to(dev)
+    nvox = int(np.prod(c["shape"]))
+    res, ref = {}, {}
+    for prec in ("fp32", "split_bf16", "split_fp16"):
+        plan = rl.Plan(psf, precision=prec)
+        u = u0.clone()
+        plan.iterate(d, u, 10)
+        u10 = u.clone()
+        plan.iterate(d, u, n_iter - 10)
+        u50 = u.clone()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            u.copy_(u0)
+            plan.iterate(d, u, n_iter)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        plan.close()
+        if prec == "fp32":
+            ref = {10: u10.double(), 50: u50.double()}
+        entry = {"ms_per_step": round(ms, 3),
+                 "value": round(nvox * n_iter / (ms * 1e-3) / 1e9, 3)}
+        if prec != "fp32":
+            for k, uu in ((10, u10), (50, u50)):
+                entry[f"rel_l2_vs_fp32_at_{k}"] = float(
+                    (torch.linalg.vector_norm(uu.double() - ref[k]) /
+                     torch.linalg.vector_norm(ref[k])).item())
+        res[prec] = entry
+    for prec in ("split_bf16", "split_fp16"):
+        res[prec]["speedup_vs_fp32"] = round(res["fp32"]["ms_per_step"] /
+                                             res[prec]["ms_per_step"], 3)
+    return {"workload": "rl_split_256x512x512_50it", "unit": "Gvoxel-iter/s", **res}
+
+
 def copy_probe(torch, rl, nbytes: int = 1 << 30, reps: int = 5) -> float:
     """Plain streaming copy kernel of the library: read + write bytes per second (GB/s)."""
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
@@ -241,6 +285,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-large", action="store_true", help="skip the 256x512x512 workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 96-volume workload")
+    ap.add_argument("--no-split", action="store_true", help="skip the split-precision forms")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the batched and single-volume paths "
@@ -270,6 +315,11 @@ def main():
         log("workload: batched, 96 uneven volumes, 50 it")
         batched = run_batched(torch, rl, synth, max(1, args.steps // 5), 1)
         log(json.dumps({"batched": batched}))
+    split = None
+    if not args.no_split:
+        log("workload: split-precision forms, 256x512x512, 50 it")
+        split = run_split(torch, rl, synth, max(1, args.steps // 5))
+        log(json.dumps({"split": split}))
     cpu = None
     if rank == 0 and not args.no_cpu:
         log("cpu baseline (oracle)")
@@ -298,6 +348,7 @@ def main():
         "flux_drift": main_run["flux_drift"],
         "large": large,
         "batched": batched,
+        "split": split,
         "copy_probe_gbs": round(copy_gbs, 1),
     }
     if rank == 0:

@@ -222,6 +222,7 @@ struct rl_plan_s {
   std::vector<hipStream_t> cls_streams;
   std::vector<hipEvent_t> cls_events;
   hipEvent_t fork_event = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream the iteration graphs are captured on
   hipGraphExec_t graph_full = nullptr, graph_last = nullptr;
   int batch_n = 0;                // iterations of the last rl_iterate_batch call
   // applied launch choice (elements per thread and work-group widths)
@@ -317,6 +318,7 @@ void release(rl_plan p) {
   for (hipEvent_t ev : p->cls_events) (void)hipEventDestroy(ev);
   if (p->fork_event) (void)hipEventDestroy(p->fork_event);
   for (hipStream_t cs : p->cls_streams) (void)hipStreamDestroy(cs);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   p->magic = kDead;
   delete p;
 }
@@ -519,10 +521,22 @@ bool configure_x(rl_plan p, int x_e) {
 // Split-precision work-groups stay at <= 512 threads (their register budget).
 int pencil_thread_cap(rl_plan p) { return p->precision == RL_PRECISION_FP32 ? 1024 : 512; }
 
+// Work-groups above 64 KB of LDS need the kernel attribute set once; done here
+// (host side, outside any graph capture) for every mode the pass may launch.
+bool prepare_pencil(rl_plan p, const Pencil& pc) {
+  for (int mode : {rlmi::PM_FWD, rlmi::PM_INV, rlmi::PM_FKI, rlmi::PM_FCKI})
+    if (rlmi::prepare_pencil(mode, pc.ax.E, p->precision, pc.block, pc.lds) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+  return true;
+}
+
 bool configure_y(rl_plan p, int y_e, int y_txb) {
   Pencil pc = make_pencil_y(p->ny, p->nz, p->xt, p->ncols, y_txb,
                             y_e > 0 ? y_e : pick_e_y(p->ny), pencil_thread_cap(p));
-  if (!pencil_fits(pc) || (int)pc.block.x > pencil_thread_cap(p)) return false;
+  if (!pencil_fits(pc) || (int)pc.block.x > pencil_thread_cap(p) || !prepare_pencil(p, pc))
+    return false;
   p->py = pc;
   p->ch_y_e = pc.ax.E;
   p->ch_y_txb = pc.args.TXB;
@@ -531,7 +545,8 @@ bool configure_y(rl_plan p, int y_e, int y_txb) {
 
 bool configure_z(rl_plan p, int z_e, int z_txb) {
   Pencil pc = make_pencil_z(p->nz, p->ny, p->xt, p->ncols, z_txb, z_e, pencil_thread_cap(p));
-  if (!pencil_fits(pc) || (int)pc.block.x > pencil_thread_cap(p)) return false;
+  if (!pencil_fits(pc) || (int)pc.block.x > pencil_thread_cap(p) || !prepare_pencil(p, pc))
+    return false;
   p->pz = pc;
   p->ch_z_e = pc.ax.E;
   p->ch_z_txb = pc.args.TXB;
@@ -1046,7 +1061,8 @@ rl_status create_batch_impl(int count, const int64_t* shapes, const float* const
     return hip_fail(e, "hipSetDevice");
   }
   if ((e = hipMalloc(&b->iter_dev, sizeof(int))) != hipSuccess ||
-      (e = hipEventCreateWithFlags(&b->fork_event, hipEventDisableTiming)) != hipSuccess) {
+      (e = hipEventCreateWithFlags(&b->fork_event, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
     st = hip_fail(e, "batch setup");
     release(b);
     return st;
@@ -1093,12 +1109,12 @@ rl_status create_batch_impl(int count, const int64_t* shapes, const float* const
   return RL_OK;
 }
 
-// One iteration of every class, forked from and joined back into b->stream
+// One iteration of every class, forked from and joined back into `origin`
 // (captured into a graph by the caller).
-rl_status enqueue_batch_iteration(rl_plan b, bool do_fwd) {
+rl_status enqueue_batch_iteration(rl_plan b, bool do_fwd, hipStream_t origin) {
   hipError_t e;
   rl_status st;
-  if ((e = hipEventRecord(b->fork_event, b->stream)) != hipSuccess)
+  if ((e = hipEventRecord(b->fork_event, origin)) != hipSuccess)
     return hip_fail(e, "hipEventRecord");
   for (size_t c = 0; c < b->classes.size(); ++c) {
     rl_plan cl = b->classes[c];
@@ -1107,20 +1123,22 @@ rl_status enqueue_batch_iteration(rl_plan b, bool do_fwd) {
     if ((st = enqueue_iteration(cl, nullptr, nullptr, 0, b->iter_dev, do_fwd)) != RL_OK) return st;
     if ((e = hipEventRecord(b->cls_events[c], cl->stream)) != hipSuccess)
       return hip_fail(e, "hipEventRecord");
-    if ((e = hipStreamWaitEvent(b->stream, b->cls_events[c], 0)) != hipSuccess)
+    if ((e = hipStreamWaitEvent(origin, b->cls_events[c], 0)) != hipSuccess)
       return hip_fail(e, "hipStreamWaitEvent");
   }
-  if ((e = rlmi::launch_advance(b->iter_dev, b->stream)) != hipSuccess)
+  if ((e = rlmi::launch_advance(b->iter_dev, origin)) != hipSuccess)
     return hip_fail(e, "iteration counter launch");
   return RL_OK;
 }
 
+// Captured on the plan's private stream (the caller's stream may be the legacy
+// null stream, which cannot be captured); launched later on the caller's stream.
 rl_status capture_graph(rl_plan b, bool do_fwd, hipGraphExec_t* exec) {
   hipGraph_t g = nullptr;
-  hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+  hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-  rl_status st = enqueue_batch_iteration(b, do_fwd);
-  e = hipStreamEndCapture(b->stream, &g);
+  rl_status st = enqueue_batch_iteration(b, do_fwd, b->cap_stream);
+  e = hipStreamEndCapture(b->cap_stream, &g);
   if (st != RL_OK) {
     if (g) (void)hipGraphDestroy(g);
     return st;
@@ -1161,6 +1179,8 @@ rl_status iterate_batch_impl(rl_plan b, const float* const* observed, float* con
     if (b->graph_last) (void)hipGraphExecDestroy(b->graph_last);
     b->graph_full = b->graph_last = nullptr;
   }
+  if (!b->graph_full && (st = capture_graph(b, true, &b->graph_full)) != RL_OK) return st;
+  if (!b->graph_last && (st = capture_graph(b, false, &b->graph_last)) != RL_OK) return st;
   // per-volume pointer tables (ordered after earlier work on b->stream)
   for (size_t ci = 0; ci < b->classes.size(); ++ci) {
     rl_plan c = b->classes[ci];
@@ -1191,8 +1211,6 @@ rl_status iterate_batch_impl(rl_plan b, const float* const* observed, float* con
         (e = hipStreamWaitEvent(b->stream, b->cls_events[ci], 0)) != hipSuccess)
       return hip_fail(e, "prologue join");
   }
-  if (!b->graph_full && (st = capture_graph(b, true, &b->graph_full)) != RL_OK) return st;
-  if (!b->graph_last && (st = capture_graph(b, false, &b->graph_last)) != RL_OK) return st;
   for (int it = 0; it < n_iter; ++it)
     if ((e = hipGraphLaunch(it + 1 < n_iter ? b->graph_full : b->graph_last, b->stream)) !=
         hipSuccess)

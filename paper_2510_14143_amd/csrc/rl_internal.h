@@ -92,6 +92,8 @@ struct XArgs {
 hipError_t launch_pencil(int mode, int E, int prec, dim3 grid, dim3 block, size_t lds,
                          hipStream_t s, float2* data, const float2* otf, const float2* tw,
                          const PencilArgs& a, const Sched& sc);
+// Sets the kernel attributes a launch with this shape needs (no launch).
+hipError_t prepare_pencil(int mode, int E, int prec, dim3 block, size_t lds);
 hipError_t launch_xrow(int mode, int E, int prec, dim3 grid, dim3 block, size_t lds,
                        hipStream_t s, const XArgs& a, const Sched& sc, const float2* tw);
 hipError_t launch_twiddles(float2* tab, int n, hipStream_t s);

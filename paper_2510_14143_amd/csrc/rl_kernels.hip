@@ -238,8 +238,11 @@ __device__ __forceinline__ void dft16_mfma(float2 (&y)[16], float* stg) {
       if (mx > 0.f && isfinite(mx)) {
         int e;
         (void)frexpf(mx, &e);  // mx < 2^e
-        sc = ldexpf(1.f, 14 - e);
-        inv[grp] = ldexpf(1.f, e - 14);
+        // largest magnitude just below 2^14; the shift is capped so the scale stays
+        // finite for tiny inputs (e.g. the far tail of a PSF), which then round to 0
+        const int sh = min(14 - e, 64);
+        sc = ldexpf(1.f, sh);
+        inv[grp] = ldexpf(1.f, -sh);
       }
     }
     V8 bh, bl;
@@ -689,10 +692,11 @@ __global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ src,
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// With `launch` false only the LDS attribute is set (work-groups above 64 KB).
 template <int MODE, int MAXT, int EV, int PREC = 0>
 static hipError_t pencil_one(dim3 g, dim3 b, size_t lds, hipStream_t s, float2* data,
                              const float2* otf, const float2* tw, const PencilArgs& a,
-                             const Sched& sc) {
+                             const Sched& sc, bool launch = true) {
   if (lds > 65536) {
     static bool attr_done = false;  // once per instantiation
     if (!attr_done) {
@@ -703,6 +707,7 @@ static hipError_t pencil_one(dim3 g, dim3 b, size_t lds, hipStream_t s, float2* 
       attr_done = true;
     }
   }
+  if (!launch) return hipSuccess;
   hipLaunchKernelGGL((k_pencil<EV, MODE, MAXT, PREC>), g, b, lds, s, data, otf, tw, a, sc);
   return hipGetLastError();
 }
@@ -710,32 +715,45 @@ static hipError_t pencil_one(dim3 g, dim3 b, size_t lds, hipStream_t s, float2* 
 template <int MODE>
 static hipError_t pencil_e(int E, int prec, dim3 g, dim3 b, size_t lds, hipStream_t s,
                            float2* data, const float2* otf, const float2* tw, const PencilArgs& a,
-                           const Sched& sc) {
+                           const Sched& sc, bool launch = true) {
   if (b.x > 1024) return hipErrorInvalidValue;
   if (b.x % 64 != 0) prec = 0;  // MFMA stages need whole wavefronts
   if (E == 16 && prec == 1) {
-    return b.x > 512 ? pencil_one<MODE, 1024, 16, 1>(g, b, lds, s, data, otf, tw, a, sc)
-                     : pencil_one<MODE, 512, 16, 1>(g, b, lds, s, data, otf, tw, a, sc);
+    return b.x > 512 ? pencil_one<MODE, 1024, 16, 1>(g, b, lds, s, data, otf, tw, a, sc, launch)
+                     : pencil_one<MODE, 512, 16, 1>(g, b, lds, s, data, otf, tw, a, sc, launch);
   }
   if (E == 16 && prec == 2) {
-    return b.x > 512 ? pencil_one<MODE, 1024, 16, 2>(g, b, lds, s, data, otf, tw, a, sc)
-                     : pencil_one<MODE, 512, 16, 2>(g, b, lds, s, data, otf, tw, a, sc);
+    return b.x > 512 ? pencil_one<MODE, 1024, 16, 2>(g, b, lds, s, data, otf, tw, a, sc, launch)
+                     : pencil_one<MODE, 512, 16, 2>(g, b, lds, s, data, otf, tw, a, sc, launch);
   }
   if (b.x > 512) {
     switch (E) {
-      case 8: return pencil_one<MODE, 1024, 8>(g, b, lds, s, data, otf, tw, a, sc);
-      case 16: return pencil_one<MODE, 1024, 16>(g, b, lds, s, data, otf, tw, a, sc);
+      case 8: return pencil_one<MODE, 1024, 8>(g, b, lds, s, data, otf, tw, a, sc, launch);
+      case 16: return pencil_one<MODE, 1024, 16>(g, b, lds, s, data, otf, tw, a, sc, launch);
       default: return hipErrorInvalidValue;
     }
   }
   switch (E) {
 #define RL_CASE(EV) \
-  case EV: return pencil_one<MODE, 512, EV>(g, b, lds, s, data, otf, tw, a, sc);
+  case EV: return pencil_one<MODE, 512, EV>(g, b, lds, s, data, otf, tw, a, sc, launch);
     RL_CASE(1) RL_CASE(2) RL_CASE(3) RL_CASE(4) RL_CASE(6) RL_CASE(8) RL_CASE(12) RL_CASE(16)
     RL_CASE(24)
 #undef RL_CASE
     default:
       return hipErrorInvalidValue;
+  }
+}
+
+hipError_t prepare_pencil(int mode, int E, int prec, dim3 block, size_t lds) {
+  const PencilArgs a{};
+  const Sched sc{};
+  const dim3 g(1);
+  switch (mode) {
+    case PM_FWD: return pencil_e<PM_FWD>(E, prec, g, block, lds, 0, nullptr, nullptr, nullptr, a, sc, false);
+    case PM_INV: return pencil_e<PM_INV>(E, prec, g, block, lds, 0, nullptr, nullptr, nullptr, a, sc, false);
+    case PM_FKI: return pencil_e<PM_FKI>(E, prec, g, block, lds, 0, nullptr, nullptr, nullptr, a, sc, false);
+    case PM_FCKI: return pencil_e<PM_FCKI>(E, prec, g, block, lds, 0, nullptr, nullptr, nullptr, a, sc, false);
+    default: return hipErrorInvalidValue;
   }
 }
 

@@ -54,6 +54,21 @@ def test_split_conv(torch, precision, shape):
 
 
 @pytest.mark.parametrize("precision", SPLITS)
+def test_split_conv_gaussian_psf_tail(torch, precision):
+    # a Gaussian PSF over the whole grid has FP32 values far below 2^-100 in its
+    # tail: the FP16 per-DFT scale must stay finite there
+    shape = (32, 64, 64)
+    say("split conv gaussian", precision)
+    x = synth.uniform_volume(shape, 201)
+    psf = synth.gaussian_psf(shape, (1.5, 1.5, 3.0))
+    ref = oracle.conv3d(x, psf)
+    with rl.Plan(dev(torch, psf), precision=precision) as p:
+        got = p.conv(dev(torch, x)).cpu().numpy()
+    assert np.all(np.isfinite(got))
+    assert oracle.rel_l2(got, ref) <= CONV_TOL[precision]
+
+
+@pytest.mark.parametrize("precision", SPLITS)
 def test_split_rl_10_and_50(torch, precision):
     c = synth.make_config(0)
     say("split rl config0", precision)
