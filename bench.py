@@ -82,7 +82,8 @@ def run_workload(torch, rl, synth, cfg: int, steps: int, warmup: int, workload: 
     d = torch.from_numpy(c["d"]).to(dev)
     u0 = torch.from_numpy(c["u0"]).to(dev)
     u = u0.clone()
-    plan = rl.Plan(psf)
+    plan = rl.Plan(psf, autotune=True)  # tuned at creation, outside the timed region
+    launch_cfg = plan.launch()
     nvox = int(np.prod(shape))
 
     def step():
@@ -136,7 +137,7 @@ def run_workload(torch, rl, synth, cfg: int, steps: int, warmup: int, workload: 
     kernel_ms = sum(v["total_ms"] for v in per_kind.values())
     plan.close()
     return dict(shape=shape, n_iter=n_iter, nvox=nvox, ms=ms, value=value, roofline=roof,
-                per_kind=per_kind, flux_drift=drift,
+                per_kind=per_kind, flux_drift=drift, launch=launch_cfg,
                 all_kernels_gbs=round(model_bytes / (kernel_ms * 1e-3) / 1e9, 1),
                 bytes_per_vi=round(model_bytes / (nvox * n_iter), 2))
 
@@ -309,6 +310,7 @@ def main():
         large = {"workload": "rl_fp32_256x512x512_50it", "value": round(lr["value"], 3),
                  "unit": "Gvoxel-iter/s", "ms_per_step": round(lr["ms"], 3),
                  "roofline": lr["roofline"], "all_kernels_gbs": lr["all_kernels_gbs"],
+                 "launch": lr["launch"],
                  "bytes_per_vi": lr["bytes_per_vi"], "flux_drift": lr["flux_drift"]}
     batched = None
     if not args.no_batch:
@@ -340,7 +342,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "rl_fp32_128x256x256_100it", "shape_zyx": list(main_run["shape"]),
                    "n_iter": main_run["n_iter"], "psf_sigma_xyz": [2.0, 2.0, 5.0],
-                   "boundary": "periodic", "parallelism": "single_gpu"},
+                   "boundary": "periodic", "parallelism": "single_gpu",
+                   "launch": main_run["launch"]},
         "roofline": main_run["roofline"],
         "cpu_baseline": cpu,
         "all_kernels_gbs": main_run["all_kernels_gbs"],

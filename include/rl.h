@@ -166,8 +166,9 @@ rl_status rl_plan_get_info(rl_plan p, int64_t shape[3], int64_t* spectrum_pitch)
 
 /* Launch configuration in use: out = {X elements per thread, Y elements per
  * thread, Y work-group lanes, Z elements per thread, Z work-group lanes,
- * 1 if chosen by the autotuner else 0}. */
-rl_status rl_plan_get_launch(rl_plan p, int out[6]);
+ * 1 if chosen by the autotuner else 0, 1 if the Z grid runs row groups
+ * fastest else 0}. */
+rl_status rl_plan_get_launch(rl_plan p, int out[7]);
 
 /*
  * Per-kernel timing with HIP events (measurement support).  When enabled,

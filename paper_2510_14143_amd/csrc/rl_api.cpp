@@ -226,7 +226,7 @@ struct rl_plan_s {
   hipGraphExec_t graph_full = nullptr, graph_last = nullptr;
   int batch_n = 0;                // iterations of the last rl_iterate_batch call
   // applied launch choice (elements per thread and work-group widths)
-  int ch_x_e = 0, ch_y_e = 0, ch_y_txb = 0, ch_z_e = 0, ch_z_txb = 0;
+  int ch_x_e = 0, ch_y_e = 0, ch_y_txb = 0, ch_z_e = 0, ch_z_txb = 0, ch_z_swap = 0;
   bool tuned = false;
   // timing
   bool timing = false;
@@ -411,7 +411,10 @@ Pencil make_pencil_z(int64_t nz, int64_t ny, int64_t xt, int64_t ncols, int req,
 
 // --- launches (optionally bracketed by timing events) -----------------------
 
-rl_status timed_begin(rl_plan p, int kind, size_t* slot) {
+// With timing enabled, hands out the event pair the next launch passes to its
+// dispatch (start and end stamped by the kernel itself); else both are null.
+rl_status timed_begin(rl_plan p, int kind, size_t* slot, hipEvent_t* ev0, hipEvent_t* ev1) {
+  *ev0 = *ev1 = nullptr;
   if (!p->timing) return RL_OK;
   if (p->n_events == p->events.size()) {
     TimedLaunch t{kind, nullptr, nullptr};
@@ -421,14 +424,9 @@ rl_status timed_begin(rl_plan p, int kind, size_t* slot) {
   }
   *slot = p->n_events++;
   p->events[*slot].kind = kind;
-  hipError_t e = hipEventRecord(p->events[*slot].a, p->stream);
-  return e == hipSuccess ? RL_OK : hip_fail(e, "hipEventRecord");
-}
-
-rl_status timed_end(rl_plan p, size_t slot) {
-  if (!p->timing) return RL_OK;
-  hipError_t e = hipEventRecord(p->events[slot].b, p->stream);
-  return e == hipSuccess ? RL_OK : hip_fail(e, "hipEventRecord");
+  *ev0 = p->events[*slot].a;
+  *ev1 = p->events[*slot].b;
+  return RL_OK;
 }
 
 // One pencil pass over `nvol` consecutive volumes starting at `data` (and at
@@ -437,16 +435,17 @@ rl_status run_pencil(rl_plan p, const Pencil& pc, int mode, float2* data, const 
                      int kind, int nvol = 0) {
   if (pc.ax.L == 1 && (mode == rlmi::PM_FWD || mode == rlmi::PM_INV)) return RL_OK;  // identity
   size_t slot = 0;
-  rl_status st = timed_begin(p, kind, &slot);
+  hipEvent_t ev0, ev1;
+  rl_status st = timed_begin(p, kind, &slot, &ev0, &ev1);
   if (st != RL_OK) return st;
   dim3 grid = pc.grid;
   grid.z = (unsigned)(nvol > 0 ? nvol : p->count);
   PencilArgs args = pc.args;
   args.vstride = (long long)p->spec_elems;
   hipError_t e = rlmi::launch_pencil(mode, pc.ax.E, p->precision, grid, pc.block, pc.lds,
-                                     p->stream, data, p->otf, tw, args, pc.ax.sc);
+                                     p->stream, data, p->otf, tw, args, pc.ax.sc, ev0, ev1);
   if (e != hipSuccess) return hip_fail(e, "pencil pass launch");
-  return timed_end(p, slot);
+  return RL_OK;
 }
 
 XArgs base_xargs(rl_plan p, float2* spec) {
@@ -468,14 +467,15 @@ XArgs base_xargs(rl_plan p, float2* spec) {
 
 rl_status run_x(rl_plan p, int mode, const XArgs& a, int kind) {
   size_t slot = 0;
-  rl_status st = timed_begin(p, kind, &slot);
+  hipEvent_t ev0, ev1;
+  rl_status st = timed_begin(p, kind, &slot, &ev0, &ev1);
   if (st != RL_OK) return st;
   dim3 grid = p->x_grid;
   grid.y = (unsigned)a.nvol;
   hipError_t e = rlmi::launch_xrow(mode, p->axx.E, p->precision, grid, p->x_block, p->x_lds,
-                                   p->stream, a, p->axx.sc, p->tw_x);
+                                   p->stream, a, p->axx.sc, p->tw_x, ev0, ev1);
   if (e != hipSuccess) return hip_fail(e, "X pass launch");
-  return timed_end(p, slot);
+  return RL_OK;
 }
 
 // spectrum (X-transformed) -> spectrum (X-transformed) of H x or H^T x:
@@ -491,7 +491,7 @@ rl_status run_yz_filter(rl_plan p, bool adjoint) {
 
 // Launch choice: elements per thread and lane widths per pass (0 = default).
 struct Choice {
-  int x_e = 0, y_e = 0, y_txb = 0, z_e = 0, z_txb = 0;
+  int x_e = 0, y_e = 0, y_txb = 0, z_e = 0, z_txb = 0, z_swap = 0;
 };
 
 // X pass shape for E = x_e: each wavefront owns 64 / P whole rows, up to
@@ -543,10 +543,16 @@ bool configure_y(rl_plan p, int y_e, int y_txb) {
   return true;
 }
 
-bool configure_z(rl_plan p, int z_e, int z_txb) {
+bool configure_z(rl_plan p, int z_e, int z_txb, int z_swap) {
   Pencil pc = make_pencil_z(p->nz, p->ny, p->xt, p->ncols, z_txb, z_e, pencil_thread_cap(p));
   if (!pencil_fits(pc) || (int)pc.block.x > pencil_thread_cap(p) || !prepare_pencil(p, pc))
     return false;
+  if (z_swap) {  // outer (y group) index fastest: resident work-groups share tile columns
+    if (pc.grid.x > 65535) return false;
+    pc.args.swap = 1;
+    pc.grid = dim3(pc.grid.y, pc.grid.x);
+  }
+  p->ch_z_swap = z_swap ? 1 : 0;
   p->pz = pc;
   p->ch_z_e = pc.ax.E;
   p->ch_z_txb = pc.args.TXB;
@@ -554,7 +560,8 @@ bool configure_z(rl_plan p, int z_e, int z_txb) {
 }
 
 bool configure(rl_plan p, const Choice& c) {
-  return configure_x(p, c.x_e) && configure_y(p, c.y_e, c.y_txb) && configure_z(p, c.z_e, c.z_txb);
+  return configure_x(p, c.x_e) && configure_y(p, c.y_e, c.y_txb) &&
+         configure_z(p, c.z_e, c.z_txb, c.z_swap);
 }
 
 // --- autotuner ---------------------------------------------------------------
@@ -587,7 +594,7 @@ bool cache_lookup(const std::string& key, Choice* c) {
     std::istringstream ls(line);
     std::string k;
     Choice t;
-    if ((ls >> k >> t.x_e >> t.y_e >> t.y_txb >> t.z_e >> t.z_txb) && k == key) {
+    if ((ls >> k >> t.x_e >> t.y_e >> t.y_txb >> t.z_e >> t.z_txb >> t.z_swap) && k == key) {
       *c = t;
       return true;
     }
@@ -600,7 +607,7 @@ void cache_store(const std::string& key, const Choice& c) {
   if (!path || !*path) return;
   std::ofstream f(path, std::ios::app);
   f << key << " " << c.x_e << " " << c.y_e << " " << c.y_txb << " " << c.z_e << " " << c.z_txb
-    << "\n";
+    << " " << c.z_swap << "\n";
 }
 
 
@@ -701,8 +708,9 @@ rl_status autotune(rl_plan p, Choice* best) {
   // Z: forward * K * inverse
   bt = 1e30f;
   for (int ze : e_candidates(p->nz, 1024, p->precision))
-    for (int w : {32, 16, 64}) {
-      if (st != RL_OK || !configure_z(p, ze, w) || p->pz.args.TXB != w) continue;
+    for (int w : {32, 16, 64})
+    for (int sw : {0, 1}) {
+      if (st != RL_OK || !configure_z(p, ze, w, sw) || p->pz.args.TXB != w) continue;
       float ms = 0.f;
       st = time_ms(p, [&]() {
         return run_pencil(p, p->pz, rlmi::PM_FKI, p->spec, p->tw_z, RL_KERNEL_OTHER);
@@ -711,6 +719,7 @@ rl_status autotune(rl_plan p, Choice* best) {
         bt = ms;
         c.z_e = ze;
         c.z_txb = w;
+        c.z_swap = sw;
       }
     }
   (void)hipStreamSynchronize(p->stream);
@@ -984,11 +993,12 @@ rl_status enqueue_flux_reduce(rl_plan p, int n_iter, hipStream_t stream) {
   hipStream_t keep = p->stream;
   p->stream = stream;
   size_t slot = 0;
-  rl_status st = timed_begin(p, RL_KERNEL_OTHER, &slot);
+  hipEvent_t ev0, ev1;
+  rl_status st = timed_begin(p, RL_KERNEL_OTHER, &slot, &ev0, &ev1);
   if (st == RL_OK) {
     hipError_t e = rlmi::launch_flux_reduce(p->partials, (int)p->x_grid.x, n_iter * p->count,
-                                            p->flux, stream);
-    st = (e == hipSuccess) ? timed_end(p, slot) : hip_fail(e, "flux reduction launch");
+                                            p->flux, stream, ev0, ev1);
+    st = (e == hipSuccess) ? RL_OK : hip_fail(e, "flux reduction launch");
   }
   p->stream = keep;
   return st;
@@ -1370,7 +1380,7 @@ rl_status rl_plan_get_info(rl_plan p, int64_t shape[3], int64_t* spectrum_pitch)
   return RL_OK;
 }
 
-rl_status rl_plan_get_launch(rl_plan p, int out[6]) {
+rl_status rl_plan_get_launch(rl_plan p, int out[7]) {
   rl_status st = check_plan(p);
   if (st != RL_OK) return st;
   if (!out) return fail(RL_E_INVALID, "out is NULL");
@@ -1381,6 +1391,7 @@ rl_status rl_plan_get_launch(rl_plan p, int out[6]) {
   out[3] = p->ch_z_e;
   out[4] = p->ch_z_txb;
   out[5] = p->tuned ? 1 : 0;
+  out[6] = p->ch_z_swap;
   return RL_OK;
 }
 

@@ -49,6 +49,7 @@ struct PencilArgs {
   long long ostride;
   long long estride;
   long long vstride;  // complex elements between volumes (work-group z index = volume)
+  int swap;           // 1: tile index from blockIdx.y and outer index from blockIdx.x
 };
 
 enum PencilMode { PM_FWD = 0, PM_INV = 1, PM_FKI = 2, PM_FCKI = 3 };
@@ -89,18 +90,21 @@ struct XArgs {
 // 1024 threads (E = 8 and 16 only).
 // prec: 0 = FP32 butterflies; 1 / 2 = radix-16 stages of E = 16 transforms on
 // MFMA with BF16 / FP16 hi-lo split operands (other stages stay FP32).
+// ev0 / ev1 (may be null): timing events stamped by the kernel's own dispatch.
 hipError_t launch_pencil(int mode, int E, int prec, dim3 grid, dim3 block, size_t lds,
                          hipStream_t s, float2* data, const float2* otf, const float2* tw,
-                         const PencilArgs& a, const Sched& sc);
+                         const PencilArgs& a, const Sched& sc, hipEvent_t ev0 = nullptr,
+                         hipEvent_t ev1 = nullptr);
 // Sets the kernel attributes a launch with this shape needs (no launch).
 hipError_t prepare_pencil(int mode, int E, int prec, dim3 block, size_t lds);
 hipError_t launch_xrow(int mode, int E, int prec, dim3 grid, dim3 block, size_t lds,
-                       hipStream_t s, const XArgs& a, const Sched& sc, const float2* tw);
+                       hipStream_t s, const XArgs& a, const Sched& sc, const float2* tw,
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_twiddles(float2* tab, int n, hipStream_t s);
 // flux[r] = sum_g partials[r * groups + g] for r < rows (a row is one
 // (iteration, volume) pair), summed in a fixed order.
 hipError_t launch_flux_reduce(const double* partials, int groups, int rows, double* flux,
-                              hipStream_t s);
+                              hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // *counter += 1 (one thread); used to advance a device-side iteration index.
 hipError_t launch_advance(int* counter, hipStream_t s);
 // *counter = value (one thread).

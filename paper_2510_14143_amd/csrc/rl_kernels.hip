@@ -22,6 +22,8 @@
 // spectra.
 #include "rl_internal.h"
 
+#include <hip/hip_ext.h>
+
 namespace rlmi {
 
 // ---------------------------------------------------------------------------
@@ -388,11 +390,13 @@ __global__ void __launch_bounds__(MAXT, (MAXT == 1024 && E == 8) ? 8 : 1)
   for (int t = tid; t < a.L; t += blockDim.x) tw[t] = twg[t];
   const int lane = tid & (a.TXB - 1);
   const int i = tid / a.TXB;
-  const int xb = blockIdx.x / a.xsplit;
-  const int c = (blockIdx.x - xb * a.xsplit) * a.TXB + lane;
+  const int bx = a.swap ? blockIdx.y : blockIdx.x;  // tile (and split) index
+  const int by = a.swap ? blockIdx.x : blockIdx.y;  // outer index
+  const int xb = bx / a.xsplit;
+  const int c = (bx - xb * a.xsplit) * a.TXB + lane;
   const bool ok = xb * kTile + (c & (kTile - 1)) < a.ncols;
   const long long base = (long long)blockIdx.z * a.vstride + (long long)xb * a.xstride +
-                         (long long)blockIdx.y * a.ostride + c;
+                         (long long)by * a.ostride + c;
 
   float2 v[E];
 #pragma unroll
@@ -693,10 +697,21 @@ __global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ src,
 // launchers
 // ---------------------------------------------------------------------------
 // With `launch` false only the LDS attribute is set (work-groups above 64 KB).
+// Launch on `s`; with timing events the dispatch packet itself stamps them
+// (hipExtLaunchKernelGGL), so they bracket exactly the kernel's execution.
+#define RL_LAUNCH(K, G, B, LDS, S, EV0, EV1, ...)                            \
+  do {                                                                       \
+    if (EV0)                                                                 \
+      hipExtLaunchKernelGGL(K, G, B, LDS, S, EV0, EV1, 0, __VA_ARGS__);      \
+    else                                                                     \
+      hipLaunchKernelGGL(K, G, B, LDS, S, __VA_ARGS__);                      \
+  } while (0)
+
 template <int MODE, int MAXT, int EV, int PREC = 0>
 static hipError_t pencil_one(dim3 g, dim3 b, size_t lds, hipStream_t s, float2* data,
                              const float2* otf, const float2* tw, const PencilArgs& a,
-                             const Sched& sc, bool launch = true) {
+                             const Sched& sc, bool launch = true, hipEvent_t ev0 = nullptr,
+                             hipEvent_t ev1 = nullptr) {
   if (lds > 65536) {
     static bool attr_done = false;  // once per instantiation
     if (!attr_done) {
@@ -708,34 +723,35 @@ static hipError_t pencil_one(dim3 g, dim3 b, size_t lds, hipStream_t s, float2* 
     }
   }
   if (!launch) return hipSuccess;
-  hipLaunchKernelGGL((k_pencil<EV, MODE, MAXT, PREC>), g, b, lds, s, data, otf, tw, a, sc);
+  RL_LAUNCH((k_pencil<EV, MODE, MAXT, PREC>), g, b, lds, s, ev0, ev1, data, otf, tw, a, sc);
   return hipGetLastError();
 }
 
 template <int MODE>
 static hipError_t pencil_e(int E, int prec, dim3 g, dim3 b, size_t lds, hipStream_t s,
                            float2* data, const float2* otf, const float2* tw, const PencilArgs& a,
-                           const Sched& sc, bool launch = true) {
+                           const Sched& sc, bool launch = true, hipEvent_t ev0 = nullptr,
+                           hipEvent_t ev1 = nullptr) {
   if (b.x > 1024) return hipErrorInvalidValue;
   if (b.x % 64 != 0) prec = 0;  // MFMA stages need whole wavefronts
   if (E == 16 && prec == 1) {
-    return b.x > 512 ? pencil_one<MODE, 1024, 16, 1>(g, b, lds, s, data, otf, tw, a, sc, launch)
-                     : pencil_one<MODE, 512, 16, 1>(g, b, lds, s, data, otf, tw, a, sc, launch);
+    return b.x > 512 ? pencil_one<MODE, 1024, 16, 1>(g, b, lds, s, data, otf, tw, a, sc, launch, ev0, ev1)
+                     : pencil_one<MODE, 512, 16, 1>(g, b, lds, s, data, otf, tw, a, sc, launch, ev0, ev1);
   }
   if (E == 16 && prec == 2) {
-    return b.x > 512 ? pencil_one<MODE, 1024, 16, 2>(g, b, lds, s, data, otf, tw, a, sc, launch)
-                     : pencil_one<MODE, 512, 16, 2>(g, b, lds, s, data, otf, tw, a, sc, launch);
+    return b.x > 512 ? pencil_one<MODE, 1024, 16, 2>(g, b, lds, s, data, otf, tw, a, sc, launch, ev0, ev1)
+                     : pencil_one<MODE, 512, 16, 2>(g, b, lds, s, data, otf, tw, a, sc, launch, ev0, ev1);
   }
   if (b.x > 512) {
     switch (E) {
-      case 8: return pencil_one<MODE, 1024, 8>(g, b, lds, s, data, otf, tw, a, sc, launch);
-      case 16: return pencil_one<MODE, 1024, 16>(g, b, lds, s, data, otf, tw, a, sc, launch);
+      case 8: return pencil_one<MODE, 1024, 8>(g, b, lds, s, data, otf, tw, a, sc, launch, ev0, ev1);
+      case 16: return pencil_one<MODE, 1024, 16>(g, b, lds, s, data, otf, tw, a, sc, launch, ev0, ev1);
       default: return hipErrorInvalidValue;
     }
   }
   switch (E) {
 #define RL_CASE(EV) \
-  case EV: return pencil_one<MODE, 512, EV>(g, b, lds, s, data, otf, tw, a, sc, launch);
+  case EV: return pencil_one<MODE, 512, EV>(g, b, lds, s, data, otf, tw, a, sc, launch, ev0, ev1);
     RL_CASE(1) RL_CASE(2) RL_CASE(3) RL_CASE(4) RL_CASE(6) RL_CASE(8) RL_CASE(12) RL_CASE(16)
     RL_CASE(24)
 #undef RL_CASE
@@ -759,31 +775,37 @@ hipError_t prepare_pencil(int mode, int E, int prec, dim3 block, size_t lds) {
 
 hipError_t launch_pencil(int mode, int E, int prec, dim3 grid, dim3 block, size_t lds,
                          hipStream_t s, float2* data, const float2* otf, const float2* tw,
-                         const PencilArgs& a, const Sched& sc) {
+                         const PencilArgs& a, const Sched& sc, hipEvent_t ev0, hipEvent_t ev1) {
   switch (mode) {
-    case PM_FWD: return pencil_e<PM_FWD>(E, prec, grid, block, lds, s, data, otf, tw, a, sc);
-    case PM_INV: return pencil_e<PM_INV>(E, prec, grid, block, lds, s, data, otf, tw, a, sc);
-    case PM_FKI: return pencil_e<PM_FKI>(E, prec, grid, block, lds, s, data, otf, tw, a, sc);
-    case PM_FCKI: return pencil_e<PM_FCKI>(E, prec, grid, block, lds, s, data, otf, tw, a, sc);
+    case PM_FWD:
+      return pencil_e<PM_FWD>(E, prec, grid, block, lds, s, data, otf, tw, a, sc, true, ev0, ev1);
+    case PM_INV:
+      return pencil_e<PM_INV>(E, prec, grid, block, lds, s, data, otf, tw, a, sc, true, ev0, ev1);
+    case PM_FKI:
+      return pencil_e<PM_FKI>(E, prec, grid, block, lds, s, data, otf, tw, a, sc, true, ev0, ev1);
+    case PM_FCKI:
+      return pencil_e<PM_FCKI>(E, prec, grid, block, lds, s, data, otf, tw, a, sc, true, ev0,
+                               ev1);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int MODE>
 static hipError_t xrow_e(int E, int prec, dim3 g, dim3 b, size_t lds, hipStream_t s,
-                         const XArgs& a, const Sched& sc, const float2* tw) {
+                         const XArgs& a, const Sched& sc, const float2* tw, hipEvent_t ev0,
+                         hipEvent_t ev1) {
   if (E == 16 && prec == 1) {
-    hipLaunchKernelGGL((k_xrow<16, MODE, 1>), g, b, lds, s, a, sc, tw);
+    RL_LAUNCH((k_xrow<16, MODE, 1>), g, b, lds, s, ev0, ev1, a, sc, tw);
     return hipGetLastError();
   }
   if (E == 16 && prec == 2) {
-    hipLaunchKernelGGL((k_xrow<16, MODE, 2>), g, b, lds, s, a, sc, tw);
+    RL_LAUNCH((k_xrow<16, MODE, 2>), g, b, lds, s, ev0, ev1, a, sc, tw);
     return hipGetLastError();
   }
   switch (E) {
 #define RL_CASE(EV)                                                      \
   case EV:                                                               \
-    hipLaunchKernelGGL((k_xrow<EV, MODE>), g, b, lds, s, a, sc, tw);     \
+    RL_LAUNCH((k_xrow<EV, MODE>), g, b, lds, s, ev0, ev1, a, sc, tw);    \
     break;
     RL_CASE(1) RL_CASE(2) RL_CASE(3) RL_CASE(4) RL_CASE(6) RL_CASE(8) RL_CASE(12) RL_CASE(16)
     RL_CASE(24)
@@ -795,19 +817,20 @@ static hipError_t xrow_e(int E, int prec, dim3 g, dim3 b, size_t lds, hipStream_
 }
 
 hipError_t launch_xrow(int mode, int E, int prec, dim3 grid, dim3 block, size_t lds,
-                       hipStream_t s, const XArgs& a, const Sched& sc, const float2* tw) {
+                       hipStream_t s, const XArgs& a, const Sched& sc, const float2* tw,
+                       hipEvent_t ev0, hipEvent_t ev1) {
   switch (mode) {
-    case XM_R2C: return xrow_e<XM_R2C>(E, prec, grid, block, lds, s, a, sc, tw);
-    case XM_C2R: return xrow_e<XM_C2R>(E, prec, grid, block, lds, s, a, sc, tw);
-    case XM_RATIO: return xrow_e<XM_RATIO>(E, prec, grid, block, lds, s, a, sc, tw);
-    case XM_UPDATE: return xrow_e<XM_UPDATE>(E, prec, grid, block, lds, s, a, sc, tw);
+    case XM_R2C: return xrow_e<XM_R2C>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
+    case XM_C2R: return xrow_e<XM_C2R>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
+    case XM_RATIO: return xrow_e<XM_RATIO>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
+    case XM_UPDATE: return xrow_e<XM_UPDATE>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_flux_reduce(const double* partials, int groups, int rows, double* flux,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(k_flux_reduce, dim3(rows), dim3(256), 0, s, partials, groups, flux);
+                              hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  RL_LAUNCH(k_flux_reduce, dim3(rows), dim3(256), 0, s, ev0, ev1, partials, groups, flux);
   return hipGetLastError();
 }
 

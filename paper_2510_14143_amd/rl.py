@@ -189,10 +189,10 @@ def rl_plan_get_info(plan: int):
 
 
 def rl_plan_get_launch(plan: int) -> dict:
-    out = (ctypes.c_int * 6)()
+    out = (ctypes.c_int * 7)()
     _check(lib().rl_plan_get_launch(ctypes.c_void_p(plan), out))
     return dict(x_elems=out[0], y_elems=out[1], y_lanes=out[2], z_elems=out[3], z_lanes=out[4],
-                tuned=bool(out[5]))
+                tuned=bool(out[5]), z_rows_fastest=bool(out[6]))
 
 
 def rl_plan_set_timing(plan: int, enable: bool) -> None:

@@ -128,6 +128,27 @@ def test_autotuned_plan_matches_oracle(torch, tmp_path, monkeypatch):
     assert len(lines) == 1 and "24x48x96" in lines[0]
 
 
+@pytest.mark.parametrize("z_swap", [0, 1])
+def test_tuning_cache_choices_apply(torch, tmp_path, monkeypatch, z_swap):
+    # a cached configuration (here: edited by hand) is applied as written
+    shape = (16, 32, 64)
+    say("tuning cache z_swap", z_swap)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("RLMI_TUNE_CACHE", str(cache))
+    x = synth.uniform_volume(shape, 105)
+    psf = rand_psf(shape, 16)
+    with rl.Plan(dev(torch, psf), autotune=True):
+        pass
+    key, *vals = cache.read_text().split()
+    vals = [8, 8, 16, 16, 32, z_swap]  # x_e, y_e, y_lanes, z_e, z_lanes, z_swap
+    cache.write_text(key + " " + " ".join(map(str, vals)) + "\n")
+    with rl.Plan(dev(torch, psf), autotune=True) as p:
+        cfg = p.launch()
+        got = p.conv(dev(torch, x)).cpu().numpy()
+    assert cfg["x_elems"] == 8 and cfg["z_lanes"] == 32 and cfg["z_rows_fastest"] == bool(z_swap)
+    assert oracle.rel_l2(got, oracle.conv3d(x, psf)) <= CONV_TOL
+
+
 @pytest.mark.parametrize("tile_x", [3, 24, 48])
 def test_odd_tile_width_requests(torch, tile_x):
     # non-power-of-two requests round down to a power of two
