@@ -67,8 +67,8 @@ def measured_traffic(kind: str, workload: str):
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    h = re.search(r"kernel source sha256\[:16\]:\s*`?([0-9a-f]{16})", text)
-    v = re.search(r"per-launch HBM bytes \(calibrated\):\s*([0-9.eE+]+)", text)
+    h = re.search(r"kernel source sha256\[:16\]:\s*`?([0-9a-f]{16})", text, re.I)
+    v = re.search(r"per-launch HBM bytes \(calibrated\):\s*([0-9.eE+]+)", text, re.I)
     if not h or not v or h.group(1) != source_hash():
         return None
     return float(v.group(1))
@@ -102,28 +102,24 @@ def run_workload(torch, rl, synth, cfg: int, steps: int, warmup: int, workload: 
     ms = start.elapsed_time(stop) / steps
     value = nvox * n_iter / (ms * 1e-3) / 1e9
 
-    # per-kernel durations, HIP events around every launch (one extra step)
-    plan.set_timing(True)
-    step()
-    timing = plan.timing()
-    plan.set_timing(False)
     flux = plan.flux()
     total = float(c["d"].sum(dtype=np.float64))
     drift = float(np.max(np.abs(flux - total)) / total)
 
+    # per-pass durations: HIP events around a burst of back-to-back launches of each
+    # pass (an event per launch would add its completion cost to every launch)
+    # (prologue: X r2c, Y, Z, Y; per iteration: X ratio, Y, Z, Y, X update, and Y, Z, Y
+    # except after the last)
+    launches = {"x_ratio": n_iter, "x_update": n_iter, "y": 4 * n_iter, "z_otf": 2 * n_iter}
     kb = kernel_bytes(shape)
+    scratch = u0.clone()
     per_kind = {}
-    for kind, (cnt, tms) in timing.items():
-        if cnt == 0:
-            continue
-        if kind == "x_update":
-            byts = (kb["x_update"] * (cnt - 1) + kb["x_update_last"]) / cnt
-        else:
-            byts = kb.get(kind)
-        avg_us = tms * 1e3 / cnt
-        per_kind[kind] = dict(launches=cnt, total_ms=round(tms, 4), avg_us=round(avg_us, 3),
-                              bytes_per_launch=byts,
-                              gbs=(round(byts / (avg_us * 1e-6) / 1e9, 1) if byts else None))
+    for kind, cnt in launches.items():
+        avg_us = plan.time_pass(kind, d, scratch, reps=20) * 1e3
+        byts = kb[kind]
+        per_kind[kind] = dict(launches_per_step=cnt, avg_us=round(avg_us, 3),
+                              total_ms=round(avg_us * cnt / 1e3, 4), bytes_per_launch=byts,
+                              gbs=round(byts / (avg_us * 1e-6) / 1e9, 1))
     dom = max(per_kind, key=lambda k: per_kind[k]["total_ms"])
     dk = per_kind[dom]
     achieved = dk["bytes_per_launch"] / (dk["avg_us"] * 1e-6) / 1e9
@@ -133,7 +129,8 @@ def run_workload(torch, rl, synth, cfg: int, steps: int, warmup: int, workload: 
             "traffic": traffic, "bytes_per_launch": dk["bytes_per_launch"],
             "avg_launch_us": dk["avg_us"]}
     # whole-iteration effective bandwidth over all passes
-    model_bytes = sum((v["bytes_per_launch"] or 0) * v["launches"] for v in per_kind.values())
+    model_bytes = (sum(v["bytes_per_launch"] * v["launches_per_step"] for v in per_kind.values())
+                   + kb["x_r2c"] - (kb["x_update"] - kb["x_update_last"]))
     kernel_ms = sum(v["total_ms"] for v in per_kind.values())
     plan.close()
     return dict(shape=shape, n_iter=n_iter, nvox=nvox, ms=ms, value=value, roofline=roof,
@@ -240,12 +237,13 @@ def run_split(torch, rl, synth, steps: int, cfg: int = 2):
     return {"workload": "rl_split_256x512x512_50it", "unit": "Gvoxel-iter/s", **res}
 
 
-def copy_probe(torch, rl, nbytes: int = 1 << 30, reps: int = 5) -> float:
+def copy_probe(torch, rl, nbytes: int = 1 << 30, reps: int = 20) -> float:
     """Plain streaming copy kernel of the library: read + write bytes per second (GB/s)."""
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
     dst = torch.empty_like(src)
     stream = int(torch.cuda.current_stream().cuda_stream)
-    rl.rl_probe_copy(src.data_ptr(), dst.data_ptr(), nbytes, stream)
+    for _ in range(5):
+        rl.rl_probe_copy(src.data_ptr(), dst.data_ptr(), nbytes, stream)
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
@@ -258,8 +256,9 @@ def copy_probe(torch, rl, nbytes: int = 1 << 30, reps: int = 5) -> float:
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(synth, n_iter_sample: int = 4):
-    """The FP64 oracle on the host cores, bounded sample of the headline workload."""
+def cpu_baseline(synth, n_iter_sample: int = 16):
+    """The FP64 oracle on the host cores, bounded sample of the headline workload.
+    Returns the record and the oracle's estimate after the sample's iterations."""
     import oracle
     try:
         from threadpoolctl import threadpool_info
@@ -270,12 +269,43 @@ def cpu_baseline(synth, n_iter_sample: int = 4):
     c = synth.make_config(1)
     nvox = int(np.prod(c["shape"]))
     t = time.perf_counter()
-    oracle.rl(c["d"], c["psf"], c["u0"], n_iter_sample)
+    u, _, _ = oracle.rl(c["d"], c["psf"], c["u0"], n_iter_sample)
     dt = time.perf_counter() - t
-    return {"value": round(nvox * n_iter_sample / dt / 1e9, 6), "unit": "Gvoxel-iter/s",
-            "cores": threads, "kind": "oracle",
-            "sample": f"{n_iter_sample} FP64 RL iterations of the 128x256x256 volume "
-                      f"(naive per-axis DFT by BLAS matrix products), {dt:.1f} s"}
+    return ({"value": round(nvox * n_iter_sample / dt / 1e9, 6), "unit": "Gvoxel-iter/s",
+             "cores": threads, "kind": "oracle",
+             "sample": f"{n_iter_sample} FP64 RL iterations of the 128x256x256 volume "
+                       f"(naive per-axis DFT by BLAS matrix products), {dt:.1f} s"}, u)
+
+
+def cpu_fft_context(synth, n_iter: int = 4) -> dict:
+    """Context only (not the oracle, not a baseline): a conventional host RL with
+    scipy's multithreaded FFT in FP32 on the same 128x256x256 volume."""
+    import scipy.fft as sfft
+    c = synth.make_config(1)
+    d, h = c["d"].astype(np.float32), c["psf"].astype(np.float64)
+    k = np.roll(h / h.sum(), [-(n // 2) for n in h.shape], axis=(0, 1, 2)).astype(np.float32)
+    workers = os.cpu_count() or 1
+    K = sfft.rfftn(k, workers=workers)
+    u = c["u0"].astype(np.float32).copy()
+    t = time.perf_counter()
+    for _ in range(n_iter):
+        q = sfft.irfftn(K * sfft.rfftn(u, workers=workers), s=u.shape, workers=workers)
+        r = np.where(q > 1e-12, d / np.where(q > 1e-12, q, 1), 0).astype(np.float32)
+        cc = sfft.irfftn(np.conj(K) * sfft.rfftn(r, workers=workers), s=u.shape, workers=workers)
+        u *= np.maximum(cc, 0)
+    dt = time.perf_counter() - t
+    nvox = int(np.prod(c["shape"]))
+    return {"value": round(nvox * n_iter / dt / 1e9, 5), "unit": "Gvoxel-iter/s",
+            "workers": workers, "kind": "scipy.fft FP32 RL (context)",
+            "sample": f"{n_iter} iterations of the 128x256x256 volume, {dt:.1f} s"}
+
+
+def gpu_estimate_after(torch, rl, synth, cfg: int, n_iter: int) -> np.ndarray:
+    c = synth.make_config(cfg)
+    with rl.Plan(torch.from_numpy(c["psf"]).to("cuda:0"), autotune=True) as p:
+        u = torch.from_numpy(c["u0"]).to("cuda:0")
+        p.iterate(torch.from_numpy(c["d"]).to("cuda:0"), u, n_iter)
+        return u.cpu().numpy()
 
 
 def main():
@@ -310,6 +340,7 @@ def main():
         large = {"workload": "rl_fp32_256x512x512_50it", "value": round(lr["value"], 3),
                  "unit": "Gvoxel-iter/s", "ms_per_step": round(lr["ms"], 3),
                  "roofline": lr["roofline"], "all_kernels_gbs": lr["all_kernels_gbs"],
+                 "model_effective_gbs": round(lr["bytes_per_vi"] * lr["value"], 1),
                  "launch": lr["launch"],
                  "bytes_per_vi": lr["bytes_per_vi"], "flux_drift": lr["flux_drift"]}
     batched = None
@@ -322,10 +353,17 @@ def main():
         log("workload: split-precision forms, 256x512x512, 50 it")
         split = run_split(torch, rl, synth, max(1, args.steps // 5))
         log(json.dumps({"split": split}))
-    cpu = None
+    cpu = cpu_ctx = None
     if rank == 0 and not args.no_cpu:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(synth)
+        cpu, u_ref = cpu_baseline(synth)
+        n_s = 16
+        u_gpu = gpu_estimate_after(torch, rl, synth, 1, n_s)
+        import oracle
+        cpu["gpu_rel_l2_vs_oracle"] = float(oracle.rel_l2(u_gpu, u_ref))
+        cpu["gpu_rel_l2_iterations"] = n_s
+        log("cpu FFT context (scipy)")
+        cpu_ctx = cpu_fft_context(synth)
 
     out = {
         "metric": "RL Gvoxel-iter/s (plain FP32, one volume)",
@@ -346,8 +384,10 @@ def main():
                    "launch": main_run["launch"]},
         "roofline": main_run["roofline"],
         "cpu_baseline": cpu,
+        "cpu_fft_context": cpu_ctx,
         "all_kernels_gbs": main_run["all_kernels_gbs"],
         "bytes_per_vi": main_run["bytes_per_vi"],
+        "model_effective_gbs": round(main_run["bytes_per_vi"] * main_run["value"], 1),
         "flux_drift": main_run["flux_drift"],
         "large": large,
         "batched": batched,

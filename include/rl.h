@@ -192,6 +192,18 @@ rl_status rl_plan_set_timing(rl_plan p, int enable); /* RL_E_UNSUPPORTED for bat
 rl_status rl_plan_get_timing(rl_plan p, int count[RL_KERNEL_KINDS], double ms[RL_KERNEL_KINDS]);
 
 /*
+ * Steady-state duration of one pass (measurement support): launches the pass
+ * of kind RL_KERNEL_X_RATIO, RL_KERNEL_X_UPDATE, RL_KERNEL_Y (forward) or
+ * RL_KERNEL_Z_OTF `reps` times back to back on the plan's spectrum workspace
+ * (with `observed` / `estimate` as the real operands of the X passes; the
+ * update pass overwrites `estimate` and the workspace) and returns the average
+ * time per launch in milliseconds from two HIP events around the burst.
+ * Synchronises.  Single-volume plans only.
+ */
+rl_status rl_plan_time_pass(rl_plan p, int kind, const float* observed, float* estimate,
+                            int reps, double* ms_per_launch);
+
+/*
  * Bandwidth probe (measurement support): copy `bytes` bytes (multiple of 16)
  * from device `src` to device `dst` with a plain streaming kernel on
  * `hip_stream`.  Used to calibrate hardware byte counters against a known

@@ -1395,6 +1395,64 @@ rl_status rl_plan_get_launch(rl_plan p, int out[7]) {
   return RL_OK;
 }
 
+rl_status rl_plan_time_pass(rl_plan p, int kind, const float* observed, float* estimate,
+                            int reps, double* ms_per_launch) {
+  rl_status st = check_plan(p);
+  if (st != RL_OK) return st;
+  if (p->is_batch) return fail(RL_E_UNSUPPORTED, "time passes on a single-volume plan");
+  if (!ms_per_launch) return fail(RL_E_INVALID, "ms_per_launch is NULL");
+  if (reps < 1 || reps > 100000) return fail(RL_E_INVALID, "reps must be in [1, 100000]");
+  if (kind != RL_KERNEL_X_RATIO && kind != RL_KERNEL_X_UPDATE && kind != RL_KERNEL_Y &&
+      kind != RL_KERNEL_Z_OTF)
+    return fail(RL_E_INVALID, "kind must be X_RATIO, X_UPDATE, Y or Z_OTF");
+  const size_t bytes = (size_t)p->nvox * sizeof(float);
+  int dev = p->device;
+  if ((st = check_dev_ptr(observed, bytes, &dev, "observed")) != RL_OK) return st;
+  if ((st = check_dev_ptr(estimate, bytes, &dev, "estimate")) != RL_OK) return st;
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  const bool timing = p->timing;
+  p->timing = false;
+  auto one = [&]() -> rl_status {
+    switch (kind) {
+      case RL_KERNEL_X_RATIO: {
+        XArgs r = base_xargs(p, p->spec);
+        r.d = observed;
+        return run_x(p, rlmi::XM_RATIO, r, kind);
+      }
+      case RL_KERNEL_X_UPDATE: {
+        XArgs w = base_xargs(p, p->spec);
+        w.u = estimate;
+        w.partials = p->partials;
+        w.do_fwd = 1;
+        return run_x(p, rlmi::XM_UPDATE, w, kind);
+      }
+      case RL_KERNEL_Y:
+        return run_pencil(p, p->py, rlmi::PM_FWD, p->spec, p->tw_y, kind);
+      default:
+        return run_pencil(p, p->pz, rlmi::PM_FKI, p->spec, p->tw_z, kind);
+    }
+  };
+  hipEvent_t a = nullptr, b = nullptr;
+  if ((e = hipEventCreate(&a)) != hipSuccess || (e = hipEventCreate(&b)) != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
+    p->timing = timing;
+    return hip_fail(e, "hipEventCreate");
+  }
+  st = one();  // warm-up
+  if (st == RL_OK && (e = hipEventRecord(a, p->stream)) != hipSuccess) st = hip_fail(e, "record");
+  for (int r = 0; r < reps && st == RL_OK; ++r) st = one();
+  if (st == RL_OK && (e = hipEventRecord(b, p->stream)) != hipSuccess) st = hip_fail(e, "record");
+  if (st == RL_OK && (e = hipEventSynchronize(b)) != hipSuccess) st = hip_fail(e, "execution");
+  float ms = 0.f;
+  if (st == RL_OK && (e = hipEventElapsedTime(&ms, a, b)) != hipSuccess) st = hip_fail(e, "elapsed");
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  p->timing = timing;
+  if (st == RL_OK) *ms_per_launch = (double)ms / reps;
+  return st;
+}
+
 rl_status rl_plan_set_timing(rl_plan p, int enable) {
   rl_status st = check_plan(p);
   if (st != RL_OK) return st;

@@ -71,6 +71,8 @@ def lib() -> ctypes.CDLL:
         "rl_plan_get_info": ([vp, i64p, i64p], ctypes.c_int),
         "rl_plan_get_launch": ([vp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "rl_plan_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
+        "rl_plan_time_pass": ([vp, ctypes.c_int, vp, vp, ctypes.c_int,
+                               ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "rl_plan_get_timing": ([vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)],
                                ctypes.c_int),
         "rl_probe_copy": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
@@ -206,6 +208,16 @@ def rl_plan_get_timing(plan: int) -> dict:
     return {k: (cnt[i], ms[i]) for i, k in enumerate(KERNEL_KINDS)}
 
 
+def rl_plan_time_pass(plan: int, kind: str, observed_ptr: int, estimate_ptr: int,
+                      reps: int = 20) -> float:
+    """Average ms per launch of one pass kind over a burst of `reps` launches."""
+    ms = ctypes.c_double(0.0)
+    _check(lib().rl_plan_time_pass(ctypes.c_void_p(plan), KERNEL_KINDS.index(kind),
+                                   ctypes.c_void_p(observed_ptr), ctypes.c_void_p(estimate_ptr),
+                                   int(reps), ctypes.byref(ms)))
+    return ms.value
+
+
 def rl_probe_copy(src_ptr: int, dst_ptr: int, nbytes: int, stream: int = 0) -> None:
     _check(lib().rl_probe_copy(ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr),
                                ctypes.c_size_t(nbytes), ctypes.c_void_p(stream or None)))
@@ -303,6 +315,15 @@ class Plan:
     def info(self):
         self._live()
         return rl_plan_get_info(self.handle)
+
+    def time_pass(self, kind: str, observed, estimate, reps: int = 20) -> float:
+        """Steady-state ms per launch of a pass kind ('x_ratio', 'x_update', 'y', 'z_otf');
+        overwrites `estimate` for 'x_update'."""
+        self._live()
+        _check_volume(observed, self.shape, self.device, "observed")
+        _check_volume(estimate, self.shape, self.device, "estimate")
+        self._bind_stream()
+        return rl_plan_time_pass(self.handle, kind, observed.data_ptr(), estimate.data_ptr(), reps)
 
     def launch(self) -> dict:
         """Elements per thread and work-group widths in use (and whether tuned)."""

@@ -80,6 +80,8 @@ def test_handles_are_checked_without_dereference():
     assert L.rl_plan_set_stream(fake, None) == rl.RL_E_INVALID
     n = ctypes.c_int()
     assert L.rl_plan_get_flux(fake, None, 0, ctypes.byref(n)) == rl.RL_E_INVALID
+    ms = ctypes.c_double()
+    assert L.rl_plan_time_pass(fake, 4, None, None, 1, ctypes.byref(ms)) == rl.RL_E_INVALID
     L.rl_plan_destroy(None)
     L.rl_plan_destroy(fake)  # unknown handle: ignored
 

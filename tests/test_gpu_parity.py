@@ -263,6 +263,38 @@ def test_rl_resume_and_determinism(torch):
         assert torch.equal(a, e)
 
 
+def test_timing_queries_leave_results_unchanged(torch):
+    shape = (16, 32, 64)
+    say("timing queries")
+    c = synth.small_case(shape, seed=7)
+    with rl.Plan(dev(torch, c["psf"])) as p:
+        d = dev(torch, c["d"])
+        a = dev(torch, c["u0"])
+        p.iterate(d, a, 6)
+        p.set_timing(True)
+        b = dev(torch, c["u0"])
+        p.iterate(d, b, 6)
+        t = p.timing()
+        p.set_timing(False)
+        # per-launch counts: prologue X r2c + Y, Z, Y; per iteration X ratio, Y, Z, Y,
+        # X update, and Y, Z, Y except after the last
+        assert t["x_r2c"][0] == 1 and t["x_ratio"][0] == 6 and t["x_update"][0] == 6
+        assert t["y"][0] == 24 and t["z_otf"][0] == 12
+        assert all(ms >= 0 for _, ms in t.values())
+        scratch = dev(torch, c["u0"])
+        for kind in ("x_ratio", "x_update", "y", "z_otf"):
+            ms = p.time_pass(kind, d, scratch, reps=3)
+            assert 0 < ms < 1e3, (kind, ms)
+        with pytest.raises(rl.RLError):
+            p.time_pass("x_r2c", d, scratch)
+        with pytest.raises(rl.RLError):
+            p.time_pass("y", d, scratch, reps=0)
+        e = dev(torch, c["u0"])
+        p.iterate(d, e, 6)  # the workspace the bursts overwrote is rebuilt by the prologue
+        torch.cuda.synchronize()
+        assert torch.equal(a, b) and torch.equal(a, e)
+
+
 def test_rl_zero_guard(torch):
     shape = (8, 8, 16)
     say("rl zero data")
