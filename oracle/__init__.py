@@ -4,3 +4,4 @@ from .rl_oracle import (  # noqa: F401
     forward, adjoint, conv3d, conv_direct, corr_direct, conv_direct_at,
     ratio, loglik, rl, rl_direct, rel_l2,
 )
+from .accel_oracle import extrapolate, rl_accel  # noqa: F401,E402
