@@ -237,6 +237,67 @@ def run_split(torch, rl, synth, steps: int, cfg: int = 2):
     return {"workload": "rl_split_256x512x512_50it", "unit": "Gvoxel-iter/s", **res}
 
 
+def run_accel(torch, rl, synth, steps: int, cfg: int = 1):
+    """Biggs-Andrews extrapolated form on the 128x256x256 volume: throughput per
+    iteration at the plain form's iteration count, and the time to reach the
+    Poisson log-likelihood that the plain form reaches after that many iterations.
+    The likelihood sum(d log Hu - Hu) is evaluated with the plan's own convolution
+    and a float64 reduction (evaluation only)."""
+    c = synth.make_config(cfg)
+    n_plain = c["n_iter"]
+    dev = torch.device("cuda:0")
+    psf = torch.from_numpy(c["psf"]).to(dev)
+    d = torch.from_numpy(c["d"]).to(dev)
+    u0 = torch.from_numpy(c["u0"]).to(dev)
+    nvox = int(np.prod(c["shape"]))
+    d64 = d.double()
+
+    def loglik(plan, u):
+        q = plan.conv(u).double()
+        ok = q > 1e-12
+        return float(torch.where(ok, d64 * torch.log(torch.where(ok, q, 1.0)) - q, 0.0).sum())
+
+    def timed(plan, n):
+        u = u0.clone()
+        plan.iterate(d, u, n)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            u.copy_(u0)
+            plan.iterate(d, u, n)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    plain = rl.Plan(psf, autotune=True)
+    acc = rl.Plan(psf, autotune=True, accel="biggs_andrews")
+    u = u0.clone()
+    plain.iterate(d, u, n_plain)
+    target = loglik(plain, u)
+    n_equiv = None
+    for n in list(range(5, n_plain, 5)) + [n_plain]:
+        u = u0.clone()
+        acc.iterate(d, u, n)
+        if loglik(acc, u) >= target:
+            n_equiv = n
+            break
+    ms_plain = timed(plain, n_plain)
+    ms_acc = timed(acc, n_plain)
+    ms_equiv = timed(acc, n_equiv) if n_equiv else None
+    alpha = acc.alpha()
+    plain.close()
+    acc.close()
+    return {"workload": "rl_biggs_andrews_128x256x256", "unit": "Gvoxel-iter/s",
+            "plain_iterations": n_plain, "plain_ms": round(ms_plain, 3),
+            "accel_ms_at_plain_iterations": round(ms_acc, 3),
+            "accel_value": round(nvox * n_plain / (ms_acc * 1e-3) / 1e9, 3),
+            "accel_iterations_to_plain_loglik": n_equiv,
+            "accel_ms_to_plain_loglik": round(ms_equiv, 3) if ms_equiv else None,
+            "time_to_quality_speedup": round(ms_plain / ms_equiv, 3) if ms_equiv else None,
+            "plain_loglik": target, "mean_alpha": round(float(np.mean(alpha[2:])), 4)}
+
+
 def copy_probe(torch, rl, nbytes: int = 1 << 30, reps: int = 20) -> float:
     """Plain streaming copy kernel of the library: read + write bytes per second (GB/s)."""
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
@@ -317,6 +378,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 256x512x512 workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 96-volume workload")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision forms")
+    ap.add_argument("--no-accel", action="store_true", help="skip the extrapolated form")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the batched and single-volume paths "
@@ -348,6 +410,11 @@ def main():
         log("workload: batched, 96 uneven volumes, 50 it")
         batched = run_batched(torch, rl, synth, max(1, args.steps // 5), 1)
         log(json.dumps({"batched": batched}))
+    accel = None
+    if not args.no_accel:
+        log("workload: Biggs-Andrews extrapolation (128x256x256)")
+        accel = run_accel(torch, rl, synth, max(1, args.steps // 2))
+        log(json.dumps({"accel": accel}))
     split = None
     if not args.no_split:
         log("workload: split-precision forms, 256x512x512, 50 it")
@@ -392,6 +459,7 @@ def main():
         "large": large,
         "batched": batched,
         "split": split,
+        "accel": accel,
         "copy_probe_gbs": round(copy_gbs, 1),
     }
     if rank == 0:

@@ -69,6 +69,18 @@ typedef enum {
                                   per 16-point DFT */
 } rl_precision;
 
+/* Iteration scheme (rl_options.accel). */
+typedef enum {
+  RL_ACCEL_NONE = 0,           /* plain Richardson-Lucy */
+  RL_ACCEL_BIGGS_ANDREWS = 1   /* first-order vector extrapolation of Biggs & Andrews,
+                                  Applied Optics 36(8), 1997 (the acceleration behind the
+                                  CUDA deconvolution tool of the paper's related work):
+                                  each iteration starts from y_k = max(x_k + alpha_k h_k, 0),
+                                  h_k = x_k - x_{k-1},
+                                  alpha_k = <g_{k-1}, g_{k-2}> / <g_{k-2}, g_{k-2}> clipped
+                                  to [0, 1], g_k = x_{k+1} - y_k; alpha_0 = alpha_1 = 0 */
+} rl_accel;
+
 /* Options for rl_plan_create_ex.  Zero-initialise, then set fields. */
 typedef struct {
   int precision;  /* rl_precision */
@@ -86,6 +98,11 @@ typedef struct {
                      temporary device memory).  With RLMI_TUNE_CACHE naming a
                      text file, results are read from / appended to it, keyed
                      by GPU architecture, HIP runtime version and shape. */
+  int accel;      /* rl_accel.  RL_ACCEL_BIGGS_ANDREWS keeps two more plan-owned
+                     volumes (8 bytes per voxel: the last step h and change g) and
+                     costs one more X pass and a one-work-group reduction per
+                     iteration; single-volume plans only (rl_plan_create_batch
+                     returns RL_E_UNSUPPORTED). */
 } rl_options;
 
 /*
@@ -111,7 +128,10 @@ rl_status rl_plan_create_ex(const int64_t shape[3], const float* psf, int bounda
  * RL_E_INVALID.  The FP64 total flux sum(u) after each iteration is kept on
  * the device for rl_plan_get_flux.  Asynchronous on the plan's stream;
  * `observed` and `estimate` must stay valid until that work completes.
- * Calling again continues the iteration (resume).
+ * Calling again continues the iteration (resume).  With extrapolation
+ * (rl_options.accel) every call starts the extrapolation afresh from
+ * `estimate` (alpha_0 = alpha_1 = 0 again), so a split run differs from an
+ * unsplit one.
  */
 rl_status rl_iterate(rl_plan p, const float* observed, float* estimate, int n_iter);
 
@@ -159,6 +179,14 @@ rl_status rl_plan_set_stream(rl_plan p, void* hip_stream);
  * also where a NaN/Inf in the inputs is reported).
  */
 rl_status rl_plan_get_flux(rl_plan p, double* flux, int cap, int* n_written);
+
+/*
+ * Extrapolated plans (accel = RL_ACCEL_BIGGS_ANDREWS): copy the FP64 weight
+ * alpha_k used by iteration k = 0 .. n-1 of the most recent rl_iterate call
+ * into alpha[0 .. min(cap, n) - 1] and n into *n_written.  Synchronises the
+ * plan's stream.  RL_E_INVALID for a plan without extrapolation.
+ */
+rl_status rl_plan_get_alpha(rl_plan p, double* alpha, int cap, int* n_written);
 
 /* Shape {nz, ny, nx} and the number of complex columns the plan stores per
  * half-spectrum row (nx/2 + 1 rounded up to whole 16-column tiles). */

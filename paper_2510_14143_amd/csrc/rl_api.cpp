@@ -210,6 +210,13 @@ struct rl_plan_s {
   // Y and Z passes
   Pencil py, pz;
   int precision = RL_PRECISION_FP32;
+  // extrapolated iteration (single-volume plans)
+  int accel = RL_ACCEL_NONE;
+  float* hstep = nullptr;         // last step x_k - x_{k-1}
+  float* gchg = nullptr;          // last change x_k - y_{k-1}
+  float* alpha32 = nullptr;       // alpha per iteration (flux_cap + 1 entries)
+  double* alpha64 = nullptr;
+  double* acc_partials = nullptr; // [2][X work-groups]
   // batched volumes of this shape (a class of a batch plan); 1 for a single plan
   int count = 1;
   const float** d_tab = nullptr;  // device tables of per-volume pointers (count each)
@@ -312,6 +319,11 @@ void release(rl_plan p) {
   (void)hipFree(p->iter_dev);
   (void)hipFree(p->d_tab);
   (void)hipFree(p->u_tab);
+  (void)hipFree(p->hstep);
+  (void)hipFree(p->gchg);
+  (void)hipFree(p->alpha32);
+  (void)hipFree(p->alpha64);
+  (void)hipFree(p->acc_partials);
   for (rl_plan c : p->classes) release(c);
   if (p->graph_full) (void)hipGraphExecDestroy(p->graph_full);
   if (p->graph_last) (void)hipGraphExecDestroy(p->graph_last);
@@ -742,6 +754,8 @@ rl_status check_options(const int64_t shape[3], const rl_options* opt) {
       (!e_ok(shape[1], opt->yz_elems, 1024) || !e_ok(shape[0], opt->yz_elems, 1024)))
     return fail(RL_E_INVALID, "yz_elems does not fit ny and nz");
   if (opt->autotune != 0 && opt->autotune != 1) return fail(RL_E_INVALID, "autotune must be 0 or 1");
+  if (opt->accel != RL_ACCEL_NONE && opt->accel != RL_ACCEL_BIGGS_ANDREWS)
+    return fail(RL_E_INVALID, "unknown accel");
   return RL_OK;
 }
 
@@ -787,6 +801,7 @@ rl_status build_class(const int64_t shape[3], int count, const float* const* psf
 
   // launch choice: options first, defaults for the rest
   p->precision = opt ? opt->precision : RL_PRECISION_FP32;
+  p->accel = opt ? opt->accel : RL_ACCEL_NONE;
   Choice choice;
   if (p->precision != RL_PRECISION_FP32) {
     // split precision runs radix-16 stages on MFMA: 16 elements per thread
@@ -831,6 +846,18 @@ rl_status build_class(const int64_t shape[3], int count, const float* const* psf
     st = hip_fail(e, "hipMalloc");
     release(p);
     return st;
+  }
+  if (p->accel != RL_ACCEL_NONE) {
+    const size_t vb = (size_t)nvox * sizeof(float);
+    if ((e = hipMalloc(&p->hstep, vb)) != hipSuccess ||
+        (e = hipMalloc(&p->gchg, vb)) != hipSuccess ||
+        (e = hipMalloc(&p->alpha32, (size_t)(p->flux_cap + 1) * sizeof(float))) != hipSuccess ||
+        (e = hipMalloc(&p->alpha64, (size_t)(p->flux_cap + 1) * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&p->acc_partials, 2 * (size_t)p->nrows * sizeof(double))) != hipSuccess) {
+      st = hip_fail(e, "hipMalloc(extrapolation state)");
+      release(p);
+      return st;
+    }
   }
 #define RL_TRY(expr)                    \
   do {                                  \
@@ -935,6 +962,8 @@ rl_status ensure_flux_capacity(rl_plan p, int n_iter, bool* grew) {
   if (n_iter <= p->flux_cap) return RL_OK;
   double* nf = nullptr;
   double* np = nullptr;
+  float* na32 = nullptr;
+  double* na64 = nullptr;
   const size_t nparts = (size_t)n_iter * p->nrows * p->count;
   hipError_t e;
   if ((e = hipMalloc(&nf, (size_t)n_iter * p->count * sizeof(double))) != hipSuccess)
@@ -943,12 +972,26 @@ rl_status ensure_flux_capacity(rl_plan p, int n_iter, bool* grew) {
     (void)hipFree(nf);
     return hip_fail(e, "hipMalloc(flux partials)");
   }
+  if (p->accel != RL_ACCEL_NONE &&
+      ((e = hipMalloc(&na32, (size_t)(n_iter + 1) * sizeof(float))) != hipSuccess ||
+       (e = hipMalloc(&na64, (size_t)(n_iter + 1) * sizeof(double))) != hipSuccess)) {
+    (void)hipFree(nf);
+    (void)hipFree(np);
+    (void)hipFree(na32);
+    return hip_fail(e, "hipMalloc(alpha)");
+  }
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   else (void)hipDeviceSynchronize();
   (void)hipFree(p->flux);
   (void)hipFree(p->partials);
   p->flux = nf;
   p->partials = np;
+  if (p->accel != RL_ACCEL_NONE) {
+    (void)hipFree(p->alpha32);
+    (void)hipFree(p->alpha64);
+    p->alpha32 = na32;
+    p->alpha64 = na64;
+  }
   p->n_partials = nparts;
   p->flux_cap = n_iter;
   if (grew) *grew = true;
@@ -1004,6 +1047,43 @@ rl_status enqueue_flux_reduce(rl_plan p, int n_iter, hipStream_t stream) {
   return st;
 }
 
+// Extrapolated (Biggs-Andrews) iteration: x_k lives in `u`, the step h_k and
+// change g_{k-1} in plan buffers, alpha_k on the device.
+XArgs accel_xargs(rl_plan p, float* u, int it) {
+  XArgs a = base_xargs(p, p->spec);
+  a.u = u;
+  a.hstep = p->hstep;
+  a.gchg = p->gchg;
+  a.alpha = p->alpha32;
+  a.acc_partials = p->acc_partials;
+  a.partials = p->partials;
+  a.iter = it;
+  return a;
+}
+
+// Spectrum of H y_it, y_it = max(x_it + alpha_it h_it, 0).
+rl_status enqueue_accel_predict(rl_plan p, float* u, int it) {
+  rl_status st = run_x(p, rlmi::XM_PREDICT, accel_xargs(p, u, it), RL_KERNEL_X_R2C);
+  return st != RL_OK ? st : run_yz_filter(p, false);
+}
+
+rl_status enqueue_accel_iteration(rl_plan p, const float* d, float* u, int it, bool last) {
+  rl_status st;
+  XArgs r = base_xargs(p, p->spec);
+  r.d = d;
+  if ((st = run_x(p, rlmi::XM_RATIO, r, RL_KERNEL_X_RATIO)) != RL_OK) return st;
+  if ((st = run_yz_filter(p, true)) != RL_OK) return st;
+  if ((st = run_x(p, rlmi::XM_UPDATE_ACC, accel_xargs(p, u, it), RL_KERNEL_X_UPDATE)) != RL_OK)
+    return st;
+  size_t slot = 0;
+  hipEvent_t ev0, ev1;
+  if ((st = timed_begin(p, RL_KERNEL_OTHER, &slot, &ev0, &ev1)) != RL_OK) return st;
+  hipError_t e = rlmi::launch_accel_alpha(p->acc_partials, (int)p->x_grid.x, it, p->alpha32,
+                                          p->alpha64, p->stream, ev0, ev1);
+  if (e != hipSuccess) return hip_fail(e, "alpha reduction launch");
+  return last ? RL_OK : enqueue_accel_predict(p, u, it + 1);
+}
+
 rl_status iterate_impl(rl_plan p, const float* observed, float* estimate, int n_iter) {
   rl_status st = check_plan(p);
   if (st != RL_OK) return st;
@@ -1018,6 +1098,13 @@ rl_status iterate_impl(rl_plan p, const float* observed, float* estimate, int n_
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   if ((st = ensure_flux_capacity(p, n_iter, nullptr)) != RL_OK) return st;
   p->flux_count = n_iter;
+  if (p->accel != RL_ACCEL_NONE) {
+    if ((st = enqueue_accel_predict(p, estimate, 0)) != RL_OK) return st;
+    for (int it = 0; it < n_iter; ++it)
+      if ((st = enqueue_accel_iteration(p, observed, estimate, it, it + 1 == n_iter)) != RL_OK)
+        return st;
+    return enqueue_flux_reduce(p, n_iter, p->stream);
+  }
   if ((st = enqueue_prologue(p, estimate)) != RL_OK) return st;
   for (int it = 0; it < n_iter; ++it)
     if ((st = enqueue_iteration(p, observed, estimate, it, nullptr, it + 1 < n_iter)) != RL_OK)
@@ -1040,6 +1127,8 @@ rl_status create_batch_impl(int count, const int64_t* shapes, const float* const
     if ((st = check_options(shapes + 3 * v, opt)) != RL_OK)
       return fail(st, "volume " + std::to_string(v) + ": " + g_err);
     if (!psfs[v]) return fail(RL_E_INVALID, "psf of volume " + std::to_string(v) + " is NULL");
+    if (opt && opt->accel != RL_ACCEL_NONE)
+      return fail(RL_E_UNSUPPORTED, "extrapolation is available for single-volume plans only");
     if (reinterpret_cast<uintptr_t>(psfs[v]) % 16 != 0)
       return fail(RL_E_INVALID, "psf of volume " + std::to_string(v) + " is not 16-byte aligned");
   }
@@ -1365,6 +1454,26 @@ rl_status rl_plan_get_flux(rl_plan p, double* flux, int cap, int* n_written) {
   for (int i = 0; i < n; ++i)
     if (!std::isfinite(h[(size_t)i]))
       return fail(RL_E_NUMERIC, "non-finite flux at entry " + std::to_string(i));
+  return RL_OK;
+}
+
+rl_status rl_plan_get_alpha(rl_plan p, double* alpha, int cap, int* n_written) {
+  rl_status st = check_plan(p);
+  if (st != RL_OK) return st;
+  if (!n_written) return fail(RL_E_INVALID, "n_written is NULL");
+  if (cap < 0 || (cap > 0 && !alpha)) return fail(RL_E_INVALID, "alpha buffer is NULL");
+  if (p->is_batch || p->accel == RL_ACCEL_NONE)
+    return fail(RL_E_INVALID, "the plan was not created with extrapolation");
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return hip_fail(e, "execution");
+  const int n = p->flux_count;
+  std::vector<double> h((size_t)n);
+  if (n > 0 && (e = hipMemcpy(h.data(), p->alpha64, (size_t)n * sizeof(double),
+                              hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(e, "hipMemcpy(alpha)");
+  *n_written = n;
+  for (int i = 0; i < n && i < cap; ++i) alpha[i] = h[(size_t)i];
   return RL_OK;
 }
 

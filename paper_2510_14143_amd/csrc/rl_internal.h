@@ -53,7 +53,17 @@ struct PencilArgs {
 };
 
 enum PencilMode { PM_FWD = 0, PM_INV = 1, PM_FKI = 2, PM_FCKI = 3 };
-enum XMode { XM_R2C = 0, XM_C2R = 1, XM_RATIO = 2, XM_UPDATE = 3 };
+// XM_PREDICT and XM_UPDATE_ACC are the two X passes of the extrapolated
+// (Biggs-Andrews) iteration: the prediction y = max(x + alpha h, 0) transformed
+// forward, and the update from y that also keeps the step h and the change g.
+enum XMode {
+  XM_R2C = 0,
+  XM_C2R = 1,
+  XM_RATIO = 2,
+  XM_UPDATE = 3,
+  XM_PREDICT = 4,
+  XM_UPDATE_ACC = 5
+};
 
 // Arguments of an X-row pass (contiguous axis, real <-> half spectrum).
 struct XArgs {
@@ -79,6 +89,12 @@ struct XArgs {
   const int* iter_ptr;   // XM_UPDATE: if non-null, the iteration index is *iter_ptr
   int nvol;              // volumes in this launch (>= 1)
   int do_fwd;            // XM_UPDATE: also transform the new estimate forward
+  // Extrapolated iteration (single volume; dense rows like u):
+  float* hstep;          // h = x_k - x_{k-1}; XM_UPDATE_ACC replaces it by x_{k+1} - x_k
+  float* gchg;           // XM_UPDATE_ACC: g_{k-1} = x_k - y_{k-1}, replaced by g_k
+  const float* alpha;    // alpha[k] (FP32); not read (taken as 0) when iter == 0
+  double* acc_partials;  // XM_UPDATE_ACC: [2][work-group] FP64 partials of
+                         // <g_k, g_{k-1}> and <g_{k-1}, g_{k-1}>
   int M;                 // complex row length nx/2
   int P;                 // threads per row (M / E)
   int RPW;               // rows per work-group (a multiple of 64 / P)
@@ -105,6 +121,14 @@ hipError_t launch_twiddles(float2* tab, int n, hipStream_t s);
 // (iteration, volume) pair), summed in a fixed order.
 hipError_t launch_flux_reduce(const double* partials, int groups, int rows, double* flux,
                               hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Extrapolation weight of the next iteration from the XM_UPDATE_ACC partials of
+// iteration `it` (summed in a fixed order): alpha[it + 1] = <g_it, g_it-1> /
+// <g_it-1, g_it-1> clipped to [0, 1] (0 for it == 0 or a zero denominator),
+// stored in FP32 (alpha32, read by the kernels) and FP64 (alpha64, reported).
+// For it == 0 it also writes alpha[0] = 0.
+hipError_t launch_accel_alpha(const double* acc_partials, int groups, int it, float* alpha32,
+                              double* alpha64, hipStream_t s, hipEvent_t ev0 = nullptr,
+                              hipEvent_t ev1 = nullptr);
 // *counter += 1 (one thread); used to advance a device-side iteration index.
 hipError_t launch_advance(int* counter, hipStream_t s);
 // *counter = value (one thread).

@@ -480,6 +480,19 @@ __device__ __forceinline__ void c2r_prepare(float2 (&v)[E], float2 nyq, int M, i
   wave_sync();
 }
 
+// Extrapolated point max(x + al * h, 0) with one rounding; a NaN passes through
+// (the comparison is false) so that non-finite data still reach the flux check.
+// Both passes that need y evaluate it with this function, so the estimate that
+// is updated is bit for bit the one that was blurred.
+__device__ __forceinline__ float predict1(float x, float h, float al) {
+  const float y = __builtin_fmaf(al, h, x);
+  return y < 0.f ? 0.f : y;
+}
+
+__device__ __forceinline__ float2 predict2(float2 x, float2 h, float al) {
+  return make_float2(predict1(x.x, h.x, al), predict1(x.y, h.y, al));
+}
+
 template <int E, int MODE, int PREC = 0>
 __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const float2* __restrict__ twg) {
   extern __shared__ float2 lds[];
@@ -510,9 +523,31 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
     for (int m = 0; m < E; ++m) v[m] = ok ? in[i + P * m] : make_float2(0.f, 0.f);
     __syncthreads();  // twiddles in LDS
     r2c_store<E, PREC>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
+  } else if constexpr (MODE == XM_PREDICT) {
+    const long long ro = rix * (2LL * M);
+    const float2* xr = reinterpret_cast<const float2*>(a.u + ro);
+    const bool hist = a.iter > 0;
+    const float al = hist ? a.alpha[a.iter] : 0.f;
+    float2 hv[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = ok ? xr[i + P * m] : make_float2(0.f, 0.f);
+    if (hist) {
+      const float2* hr = reinterpret_cast<const float2*>(a.hstep + ro);
+#pragma unroll
+      for (int m = 0; m < E; ++m) hv[m] = ok ? hr[i + P * m] : make_float2(0.f, 0.f);
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) hv[m] = make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = predict2(v[m], hv[m], al);
+    __syncthreads();  // twiddles in LDS
+    r2c_store<E, PREC>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
   } else {
+    constexpr bool kAcc = MODE == XM_UPDATE_ACC;
     // issue every global load of the row first
-    float2 w[(MODE == XM_RATIO || MODE == XM_UPDATE) ? E : 1];
+    float2 w[(MODE == XM_RATIO || MODE == XM_UPDATE || kAcc) ? E : 1];
+    float2 hv[kAcc ? E : 1], gv[kAcc ? E : 1];
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = ok ? srow[col_off(i + P * m, ts)] : make_float2(0.f, 0.f);
     const float2 nyq = (ok && i == 0) ? srow[col_off(M, ts)] : make_float2(0.f, 0.f);
@@ -526,6 +561,23 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
       const float2* ur = reinterpret_cast<const float2*>(ubase + rix * (2LL * M));
 #pragma unroll
       for (int m = 0; m < E; ++m) w[m] = ok ? ur[i + P * m] : make_float2(0.f, 0.f);
+    } else if constexpr (kAcc) {
+      const long long ro = rix * (2LL * M);
+      const float2* xr = reinterpret_cast<const float2*>(a.u + ro);
+#pragma unroll
+      for (int m = 0; m < E; ++m) w[m] = ok ? xr[i + P * m] : make_float2(0.f, 0.f);
+      if (a.iter > 0) {
+        const float2* hr = reinterpret_cast<const float2*>(a.hstep + ro);
+        const float2* gr = reinterpret_cast<const float2*>(a.gchg + ro);
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+          hv[m] = ok ? hr[i + P * m] : make_float2(0.f, 0.f);
+          gv[m] = ok ? gr[i + P * m] : make_float2(0.f, 0.f);
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < E; ++m) hv[m] = gv[m] = make_float2(0.f, 0.f);
+      }
     }
     __syncthreads();  // twiddles in LDS
     c2r_prepare<E>(v, nyq, M, P, i, tw, row);
@@ -546,6 +598,56 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
       }
       wave_sync();  // row buffer reuse
       r2c_store<E, PREC>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
+    } else if constexpr (kAcc) {
+      // x_{k+1} = y_k * max(c, 0) from the prediction y_k; keep h and g for the next
+      // extrapolation and accumulate the flux and the two inner products of alpha
+      const long long ro = rix * (2LL * M);
+      float2* xr = reinterpret_cast<float2*>(a.u + ro);
+      float2* hr = reinterpret_cast<float2*>(a.hstep + ro);
+      float2* gr = reinterpret_cast<float2*>(a.gchg + ro);
+      const float al = a.iter > 0 ? a.alpha[a.iter] : 0.f;
+      double acc = 0.0, sgg = 0.0, spp = 0.0;
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const float2 c = v[m];
+        const float2 y = predict2(w[m], hv[m], al);
+        const float2 xn = make_float2(y.x * (c.x < 0.f ? 0.f : c.x), y.y * (c.y < 0.f ? 0.f : c.y));
+        const float2 g = make_float2(xn.x - y.x, xn.y - y.y);
+        const float2 hn = make_float2(xn.x - w[m].x, xn.y - w[m].y);
+        if (ok) {
+          xr[i + P * m] = xn;
+          hr[i + P * m] = hn;
+          gr[i + P * m] = g;
+        }
+        acc += (double)xn.x + (double)xn.y;
+        sgg += (double)g.x * (double)gv[m].x + (double)g.y * (double)gv[m].y;
+        spp += (double)gv[m].x * (double)gv[m].x + (double)gv[m].y * (double)gv[m].y;
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        acc += __shfl_xor(acc, off, 64);
+        sgg += __shfl_xor(sgg, off, 64);
+        spp += __shfl_xor(spp, off, 64);
+      }
+      __shared__ double wacc[3][kXMaxThreads / 64];
+      if (lane == 0) {
+        wacc[0][wave] = acc;
+        wacc[1][wave] = sgg;
+        wacc[2][wave] = spp;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+        const int nw = blockDim.x >> 6;
+        for (int q = 0; q < nw; ++q) {
+          t0 += wacc[0][q];
+          t1 += wacc[1][q];
+          t2 += wacc[2][q];
+        }
+        a.partials[(long long)a.iter * gridDim.x + blockIdx.x] = t0;
+        a.acc_partials[blockIdx.x] = t1;
+        a.acc_partials[gridDim.x + blockIdx.x] = t2;
+      }
     } else {  // XM_UPDATE
       float2* ur = reinterpret_cast<float2*>((a.u_tab ? a.u_tab[vol] : a.u) + rix * (2LL * M));
       double acc = 0.0;
@@ -595,6 +697,45 @@ __global__ void __launch_bounds__(256) k_flux_reduce(const double* __restrict__ 
   if ((tid & 63) == 0) ws[tid >> 6] = t;
   __syncthreads();
   if (tid == 0) flux[it] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+}
+
+// alpha of the next extrapolated iteration from the two inner-product rows.
+__global__ void __launch_bounds__(256) k_accel_alpha(const double* __restrict__ accp, int groups,
+                                                     int it, float* __restrict__ alpha32,
+                                                     double* __restrict__ alpha64) {
+  const int tid = threadIdx.x;
+  double num = 0.0, den = 0.0;
+  for (int g = tid; g < groups; g += blockDim.x) {
+    num += accp[g];
+    den += accp[groups + g];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    num += __shfl_xor(num, off, 64);
+    den += __shfl_xor(den, off, 64);
+  }
+  __shared__ double ws[2][4];
+  if ((tid & 63) == 0) {
+    ws[0][tid >> 6] = num;
+    ws[1][tid >> 6] = den;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double n = ((ws[0][0] + ws[0][1]) + ws[0][2]) + ws[0][3];
+    const double d = ((ws[1][0] + ws[1][1]) + ws[1][2]) + ws[1][3];
+    double al = 0.0;
+    if (it > 0 && d > 0.0) {
+      al = n / d;  // a NaN stays NaN and surfaces in the flux
+      if (al < 0.0) al = 0.0;
+      if (al > 1.0) al = 1.0;
+    }
+    alpha32[it + 1] = (float)al;
+    alpha64[it + 1] = al;
+    if (it == 0) {
+      alpha32[0] = 0.f;
+      alpha64[0] = 0.0;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -686,11 +827,23 @@ __global__ void k_psf_prep(const float* __restrict__ h, float* __restrict__ out,
   out[((long long)z * ny + y) * out_row_stride + x] = (float)((double)v * scale);
 }
 
+// Streaming copy of n 16-byte words: each thread loads kCopyUnroll words a
+// work-group width apart, then stores them (all loads in flight at once).
+constexpr int kCopyUnroll = 4;
 __global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ src,
                                               float4* __restrict__ dst, long long n) {
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
-       t += (long long)gridDim.x * blockDim.x)
-    dst[t] = src[t];
+  const long long base = (long long)blockIdx.x * blockDim.x * kCopyUnroll + threadIdx.x;
+  float4 v[kCopyUnroll];
+#pragma unroll
+  for (int u = 0; u < kCopyUnroll; ++u) {
+    const long long t = base + (long long)u * blockDim.x;
+    if (t < n) v[u] = src[t];
+  }
+#pragma unroll
+  for (int u = 0; u < kCopyUnroll; ++u) {
+    const long long t = base + (long long)u * blockDim.x;
+    if (t < n) dst[t] = v[u];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -824,8 +977,18 @@ hipError_t launch_xrow(int mode, int E, int prec, dim3 grid, dim3 block, size_t 
     case XM_C2R: return xrow_e<XM_C2R>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
     case XM_RATIO: return xrow_e<XM_RATIO>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
     case XM_UPDATE: return xrow_e<XM_UPDATE>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
+    case XM_PREDICT: return xrow_e<XM_PREDICT>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
+    case XM_UPDATE_ACC:
+      return xrow_e<XM_UPDATE_ACC>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_accel_alpha(const double* acc_partials, int groups, int it, float* alpha32,
+                              double* alpha64, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  RL_LAUNCH(k_accel_alpha, dim3(1), dim3(256), 0, s, ev0, ev1, acc_partials, groups, it, alpha32,
+            alpha64);
+  return hipGetLastError();
 }
 
 hipError_t launch_flux_reduce(const double* partials, int groups, int rows, double* flux,
@@ -872,8 +1035,8 @@ hipError_t launch_psf_prep(const float* h, float* out, int nz, int ny, int nx,
 
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
   const long long n = (long long)(bytes / 16);
-  long long blocks = (n + 255) / 256;
-  if (blocks > 256LL * 64) blocks = 256LL * 64;
+  long long blocks = (n + 256LL * kCopyUnroll - 1) / (256LL * kCopyUnroll);
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s,
                      reinterpret_cast<const float4*>(src), reinterpret_cast<float4*>(dst), n);

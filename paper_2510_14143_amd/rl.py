@@ -26,6 +26,8 @@ RL_BOUNDARY_PERIODIC, RL_BOUNDARY_ZERO = 0, 1
 RL_PRECISION_FP32, RL_PRECISION_SPLIT_BF16, RL_PRECISION_SPLIT_FP16 = 0, 1, 2
 _PRECISIONS = {"fp32": RL_PRECISION_FP32, "split_bf16": RL_PRECISION_SPLIT_BF16,
                "split_fp16": RL_PRECISION_SPLIT_FP16}
+RL_ACCEL_NONE, RL_ACCEL_BIGGS_ANDREWS = 0, 1
+_ACCELS = {"none": RL_ACCEL_NONE, "biggs_andrews": RL_ACCEL_BIGGS_ANDREWS}
 KERNEL_KINDS = ("x_r2c", "x_c2r", "x_ratio", "x_update", "y", "z_otf", "z", "other")
 
 
@@ -43,7 +45,8 @@ _STATUS_NAMES = {0: "RL_OK", 1: "RL_E_INVALID", 2: "RL_E_UNSUPPORTED", 3: "RL_E_
 
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("stream", ctypes.c_void_p), ("tile_x", ctypes.c_int),
-                ("x_elems", ctypes.c_int), ("yz_elems", ctypes.c_int), ("autotune", ctypes.c_int)]
+                ("x_elems", ctypes.c_int), ("yz_elems", ctypes.c_int), ("autotune", ctypes.c_int),
+                ("accel", ctypes.c_int)]
 
 
 _lib = None
@@ -68,6 +71,8 @@ def lib() -> ctypes.CDLL:
         "rl_plan_set_stream": ([vp, vp], ctypes.c_int),
         "rl_plan_get_flux": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                               ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "rl_plan_get_alpha": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                               ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "rl_plan_get_info": ([vp, i64p, i64p], ctypes.c_int),
         "rl_plan_get_launch": ([vp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "rl_plan_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
@@ -123,10 +128,11 @@ def rl_plan_create(shape, psf_ptr: int, boundary: int = RL_BOUNDARY_PERIODIC) ->
 
 def rl_plan_create_ex(shape, psf_ptr: int, boundary: int = RL_BOUNDARY_PERIODIC,
                       precision: int = RL_PRECISION_FP32, stream: int = 0, tile_x: int = 0,
-                      x_elems: int = 0, yz_elems: int = 0, autotune: bool = False) -> int:
+                      x_elems: int = 0, yz_elems: int = 0, autotune: bool = False,
+                      accel: int = RL_ACCEL_NONE) -> int:
     out = ctypes.c_void_p()
     opt = _Options(int(precision), ctypes.c_void_p(stream or None), int(tile_x), int(x_elems),
-                   int(yz_elems), 1 if autotune else 0)
+                   int(yz_elems), 1 if autotune else 0, int(accel))
     _check(lib().rl_plan_create_ex(_shape(shape), ctypes.c_void_p(psf_ptr), int(boundary),
                                    ctypes.byref(opt), ctypes.byref(out)))
     return out.value
@@ -151,7 +157,7 @@ def rl_plan_create_batch(shapes, psf_ptrs, boundary: int = RL_BOUNDARY_PERIODIC,
     ps = (ctypes.c_void_p * n)(*psf_ptrs)
     out = ctypes.c_void_p()
     opt = _Options(RL_PRECISION_FP32, ctypes.c_void_p(stream or None), 0, int(x_elems),
-                   int(yz_elems), 1 if autotune else 0)
+                   int(yz_elems), 1 if autotune else 0, RL_ACCEL_NONE)
     _check(lib().rl_plan_create_batch(n, sh, ps, int(boundary), ctypes.byref(opt),
                                       ctypes.byref(out)))
     return out.value
@@ -181,6 +187,14 @@ def rl_plan_get_flux(plan: int, cap: int = 1 << 20) -> np.ndarray:
     vals = np.array(buf[: min(cap, m.value)], dtype=np.float64)
     _check(st)
     return vals
+
+
+def rl_plan_get_alpha(plan: int) -> np.ndarray:
+    n = ctypes.c_int(0)
+    _check(lib().rl_plan_get_alpha(ctypes.c_void_p(plan), None, 0, ctypes.byref(n)))
+    buf = (ctypes.c_double * max(1, n.value))()
+    _check(lib().rl_plan_get_alpha(ctypes.c_void_p(plan), buf, n.value, ctypes.byref(n)))
+    return np.array(buf[: n.value], dtype=np.float64)
 
 
 def rl_plan_get_info(plan: int):
@@ -258,7 +272,8 @@ class Plan:
     """Richardson-Lucy plan for one volume shape and PSF (a float32 CUDA tensor [Z][Y][X])."""
 
     def __init__(self, psf, boundary: str = "periodic", tile_x: int = 0, x_elems: int = 0,
-                 yz_elems: int = 0, autotune: bool = False, precision: str = "fp32"):
+                 yz_elems: int = 0, autotune: bool = False, precision: str = "fp32",
+                 accel: str = "none"):
         bmap = {"periodic": RL_BOUNDARY_PERIODIC, "zero": RL_BOUNDARY_ZERO}
         if boundary not in bmap:
             raise ValueError("boundary must be 'periodic' or 'zero'")
@@ -269,10 +284,14 @@ class Plan:
         self.device = psf.device
         if precision not in _PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(_PRECISIONS)}")
+        if accel not in _ACCELS:
+            raise ValueError(f"accel must be one of {sorted(_ACCELS)}")
+        self.accel = accel
         self.handle = rl_plan_create_ex(self.shape, psf.data_ptr(), bmap[boundary],
                                         precision=_PRECISIONS[precision],
                                         stream=_stream_of(self.device), tile_x=tile_x,
-                                        x_elems=x_elems, yz_elems=yz_elems, autotune=autotune)
+                                        x_elems=x_elems, yz_elems=yz_elems, autotune=autotune,
+                                        accel=_ACCELS[accel])
 
     def _bind_stream(self):
         rl_plan_set_stream(self.handle, _stream_of(self.device))
@@ -302,6 +321,13 @@ class Plan:
         self._live()
         self._bind_stream()
         return rl_plan_get_flux(self.handle)
+
+    def alpha(self) -> np.ndarray:
+        """Extrapolation weight of each iteration of the last iterate() call
+        (plans with accel="biggs_andrews"; synchronises)."""
+        self._live()
+        self._bind_stream()
+        return rl_plan_get_alpha(self.handle)
 
     def set_timing(self, enable: bool) -> None:
         self._live()

@@ -116,3 +116,13 @@ def test_elems_options_validated_before_device_work():
         opt = rl._Options(0, None, 0, xe, yze)
         st = L.rl_plan_create_ex(sh, ctypes.c_void_p(4096), 0, ctypes.byref(opt), ctypes.byref(out))
         assert st == rl.RL_E_INVALID, (xe, yze, rl.rl_last_error())
+    for accel in (-1, 2, 7):
+        opt = rl._Options(0, None, 0, 0, 0, 0, accel)
+        st = L.rl_plan_create_ex(sh, ctypes.c_void_p(4096), 0, ctypes.byref(opt), ctypes.byref(out))
+        assert st == rl.RL_E_INVALID and "accel" in rl.rl_last_error()
+
+
+def test_alpha_query_checks_handle():
+    L = rl.lib()
+    n = ctypes.c_int()
+    assert L.rl_plan_get_alpha(ctypes.c_void_p(0x1234560), None, 0, ctypes.byref(n)) == rl.RL_E_INVALID
