@@ -5,3 +5,6 @@ from .rl_oracle import (  # noqa: F401
     ratio, loglik, rl, rl_direct, rel_l2,
 )
 from .accel_oracle import extrapolate, rl_accel  # noqa: F401,E402
+from .boundary_oracle import (  # noqa: F401,E402
+    embed_kernel, conv_periodic, corr_periodic, conv_zero, corr_zero, rl_general,
+)
