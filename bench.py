@@ -298,6 +298,43 @@ def run_accel(torch, rl, synth, steps: int, cfg: int = 1):
             "plain_loglik": target, "mean_alpha": round(float(np.mean(alpha[2:])), 4)}
 
 
+def run_zero_boundary(torch, rl, synth, steps: int, cfg: int = 1):
+    """Zero (linear) boundary on the 128x256x256 volume with its Gaussian PSF cut
+    to a +-4 sigma box (entries outside it are exactly zero): throughput over the
+    caller's voxels, the padded transform grid, and the periodic form beside it."""
+    c = synth.make_config(cfg)
+    n_iter = c["n_iter"]
+    shape = c["shape"]
+    sx, sy, sz = c["sigma"]
+    pshape = tuple(2 * int(np.ceil(4 * s)) + 1 for s in (sz, sy, sx))
+    dev = torch.device("cuda:0")
+    psf = torch.from_numpy(synth.gaussian_psf(pshape, (sx, sy, sz))).to(dev)
+    d = torch.from_numpy(c["d"]).to(dev)
+    u0 = torch.from_numpy(c["u0"]).to(dev)
+    nvox = int(np.prod(shape))
+    plan = rl.Plan(psf, shape=shape, boundary="zero", autotune=True)
+    u = u0.clone()
+    plan.iterate(d, u, n_iter)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        u.copy_(u0)
+        plan.iterate(d, u, n_iter)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    flux = plan.flux()
+    total = float(c["d"].sum(dtype=np.float64))
+    grid = plan.grid()
+    plan.close()
+    return {"workload": "rl_zero_boundary_128x256x256_100it", "unit": "Gvoxel-iter/s",
+            "psf_shape_zyx": list(pshape), "grid_zyx": list(grid),
+            "grid_voxels_per_voxel": round(float(np.prod(grid)) / nvox, 3),
+            "ms_per_step": round(ms, 3), "value": round(nvox * n_iter / (ms * 1e-3) / 1e9, 3),
+            "flux_drift": float(np.max(np.abs(flux - total)) / total)}
+
+
 def copy_probe(torch, rl, nbytes: int = 1 << 30, reps: int = 20) -> float:
     """Plain streaming copy kernel of the library: read + write bytes per second (GB/s)."""
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
@@ -379,6 +416,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 96-volume workload")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision forms")
     ap.add_argument("--no-accel", action="store_true", help="skip the extrapolated form")
+    ap.add_argument("--no-zero", action="store_true", help="skip the zero-boundary form")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the batched and single-volume paths "
@@ -415,6 +453,11 @@ def main():
         log("workload: Biggs-Andrews extrapolation (128x256x256)")
         accel = run_accel(torch, rl, synth, max(1, args.steps // 2))
         log(json.dumps({"accel": accel}))
+    zero = None
+    if not args.no_zero:
+        log("workload: zero boundary (128x256x256, truncated PSF)")
+        zero = run_zero_boundary(torch, rl, synth, max(1, args.steps // 2))
+        log(json.dumps({"zero_boundary": zero}))
     split = None
     if not args.no_split:
         log("workload: split-precision forms, 256x512x512, 50 it")
@@ -460,6 +503,7 @@ def main():
         "batched": batched,
         "split": split,
         "accel": accel,
+        "zero_boundary": zero,
         "copy_probe_gbs": round(copy_gbs, 1),
     }
     if rank == 0:

@@ -54,9 +54,22 @@ typedef enum {
   RL_E_INTERNAL = 6     /* unexpected internal failure */
 } rl_status;
 
+/*
+ * Boundary of the blur.  The PSF (shape p <= the volume's per axis, centre
+ * voxel floor(p/2), normalised to unit sum) acts as
+ *   (H x)[i] = sum_m h[m] x[i - (m - floor(p/2))]
+ * PERIODIC: indices wrap around the volume (circular convolution); the volume's
+ *   dimensions must be transform lengths (see rl_plan_create).
+ * ZERO: x is zero outside the volume (linear convolution, output kept on the
+ *   volume's grid).  The library transforms on a padded grid of at least
+ *   n + floor(p/2) per axis (rounded up to a transform length; rl_plan_get_grid),
+ *   so the volume may have any dimensions whose padded grid is supported.  The
+ *   adjoint is the linear correlation; the update is unchanged, so the flux
+ *   sum(u) is still conserved.  Single-volume plans only.
+ */
 typedef enum {
-  RL_BOUNDARY_PERIODIC = 0, /* circular convolution (the only boundary implemented) */
-  RL_BOUNDARY_ZERO = 1      /* linear convolution with zero padding: RL_E_UNSUPPORTED */
+  RL_BOUNDARY_PERIODIC = 0,
+  RL_BOUNDARY_ZERO = 1
 } rl_boundary;
 
 typedef enum {
@@ -103,16 +116,25 @@ typedef struct {
                      costs one more X pass and a one-work-group reduction per
                      iteration; single-volume plans only (rl_plan_create_batch
                      returns RL_E_UNSUPPORTED). */
+  int64_t psf_shape[3]; /* {pz, py, px} of the PSF passed to rl_plan_create_ex;
+                     {0, 0, 0} = the volume's shape.  Each must be in [1, the
+                     volume's dimension] (else RL_E_INVALID); the PSF is centred
+                     at voxel floor(p/2) and zero beyond its extent.  Single-
+                     volume plans only. */
 } rl_options;
 
 /*
  * Create a plan for volumes of shape {nz, ny, nx} blurred by `psf`
- * (device pointer, the same shape).  The PSF is read only during this call:
- * it must be finite, >= 0 and have a positive sum (else RL_E_INVALID); it is
- * normalised to unit sum in FP64 and its transfer function is stored in the
- * plan (plan-owned device memory, about 8 bytes per voxel including the
- * spectrum workspace).  Synchronous: returns after all device work is done.
- * On success *out receives the plan; on failure *out is set to NULL.
+ * (device pointer, the same shape; rl_options.psf_shape allows a smaller one).
+ * The PSF is read only during this call: it must be finite, >= 0 and have a
+ * positive sum (else RL_E_INVALID); it is normalised to unit sum in FP64 and
+ * its transfer function is stored in the plan (plan-owned device memory, about
+ * 8 bytes per voxel of the transform grid including the spectrum workspace).
+ * Periodic boundary: each dimension must be a transform length: nx even with
+ * nx/2 in {2^a, 3*2^a}, nx <= 2048; ny, nz in {1, 2^a, 3*2^a}, <= 1024 (else
+ * RL_E_UNSUPPORTED).  Zero boundary: those limits apply to the padded grid.
+ * Synchronous: returns after all device work is done.  On success *out
+ * receives the plan; on failure *out is set to NULL.
  */
 rl_status rl_plan_create(const int64_t shape[3], const float* psf, int boundary,
                          rl_plan* out);
@@ -188,9 +210,14 @@ rl_status rl_plan_get_flux(rl_plan p, double* flux, int cap, int* n_written);
  */
 rl_status rl_plan_get_alpha(rl_plan p, double* alpha, int cap, int* n_written);
 
-/* Shape {nz, ny, nx} and the number of complex columns the plan stores per
- * half-spectrum row (nx/2 + 1 rounded up to whole 16-column tiles). */
+/* Shape {nz, ny, nx} of the plan's volumes and the number of complex columns
+ * the plan stores per half-spectrum row (grid nx/2 + 1 rounded up to whole
+ * 16-column tiles). */
 rl_status rl_plan_get_info(rl_plan p, int64_t shape[3], int64_t* spectrum_pitch);
+
+/* Transform grid {nz, ny, nx}: the volume's shape for the periodic boundary,
+ * the padded grid for the zero boundary (batch plans: the first volume's). */
+rl_status rl_plan_get_grid(rl_plan p, int64_t grid[3]);
 
 /* Launch configuration in use: out = {X elements per thread, Y elements per
  * thread, Y work-group lanes, Z elements per thread, Z work-group lanes,

@@ -188,7 +188,11 @@ struct rl_plan_s {
   int device = 0;
   hipStream_t stream = nullptr;
   int64_t nz = 0, ny = 0, nx = 0;
-  int64_t M = 0, ncols = 0, xt = 0, nvox = 0, nrows = 0;
+  int64_t M = 0, ncols = 0, xt = 0, nvox = 0, nrows = 0;  // transform grid
+  // the caller's volumes (vz, vy, vx) at the grid's low corner, and the PSF shape
+  int64_t vz = 0, vy = 0, vx = 0, vnvox = 0;
+  int64_t psf_z = 0, psf_y = 0, psf_x = 0;
+  int boundary = RL_BOUNDARY_PERIODIC;
   size_t spec_elems = 0;
   float2* spec = nullptr;
   float2* otf = nullptr;
@@ -467,6 +471,11 @@ XArgs base_xargs(rl_plan p, float2* spec) {
   a.zstride = p->xt * p->ny * rlmi::kTile;
   a.tstride = p->ny * rlmi::kTile;
   a.ny = (int)p->ny;
+  a.vx = (int)p->vx;
+  a.vy = (int)p->vy;
+  a.vz = (int)p->vz;
+  a.rin_stride = p->vx;
+  a.rout_stride = p->vx;
   a.M = (int)p->M;
   a.P = p->axx.P;
   a.RPW = p->x_rpw;
@@ -659,7 +668,7 @@ std::vector<int> e_candidates(int64_t L, int64_t max_p, int precision) {
 rl_status autotune(rl_plan p, Choice* best) {
   float* dbuf = nullptr;
   float* ubuf = nullptr;
-  const size_t bytes = (size_t)p->nvox * sizeof(float);
+  const size_t bytes = (size_t)p->vnvox * sizeof(float);
   hipError_t e;
   if ((e = hipMalloc(&dbuf, bytes)) != hipSuccess) return hip_fail(e, "hipMalloc(tuning)");
   if ((e = hipMalloc(&ubuf, bytes)) != hipSuccess) {
@@ -668,9 +677,9 @@ rl_status autotune(rl_plan p, Choice* best) {
   }
   rl_status st = RL_OK;
   // benign contents: d = u = 1.0, spectrum = 0
-  if ((e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(dbuf), 0x3f800000u, p->nvox,
+  if ((e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(dbuf), 0x3f800000u, p->vnvox,
                              p->stream)) != hipSuccess ||
-      (e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(ubuf), 0x3f800000u, p->nvox,
+      (e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(ubuf), 0x3f800000u, p->vnvox,
                              p->stream)) != hipSuccess ||
       (e = hipMemsetAsync(p->spec, 0, p->spec_elems * sizeof(float2), p->stream)) != hipSuccess)
     st = hip_fail(e, "tuning buffers");
@@ -760,9 +769,58 @@ rl_status check_options(const int64_t shape[3], const rl_options* opt) {
 }
 
 rl_status check_boundary(int boundary) {
-  if (boundary == RL_BOUNDARY_ZERO)
-    return fail(RL_E_UNSUPPORTED, "only the periodic boundary is implemented");
-  if (boundary != RL_BOUNDARY_PERIODIC) return fail(RL_E_INVALID, "unknown boundary");
+  if (boundary != RL_BOUNDARY_PERIODIC && boundary != RL_BOUNDARY_ZERO)
+    return fail(RL_E_INVALID, "unknown boundary");
+  return RL_OK;
+}
+
+// Where a plan's volumes, PSF and transform grid sit: the caller's volume
+// (vol) at the low corner of the grid, the PSF (psf <= vol per axis) centred
+// on grid voxel 0.  Periodic: grid = vol.  Zero: grid >= vol + psf/2 per axis,
+// so that no wrapped term of the circular convolution on the grid reaches the
+// volume (the offsets of the PSF entries lie in [-psf/2, psf - 1 - psf/2]).
+struct Geometry {
+  int64_t grid[3], vol[3], psf[3];
+  int boundary;
+};
+
+// Smallest supported transform length >= need (1, 2^a or 3 * 2^a).
+int64_t next_len(int64_t need) {
+  // candidates in increasing order: 1, 2, 3, 4, 6, 8, 12, ... (b, then 3b/2 < 2b)
+  for (int64_t b = 1; b <= (int64_t)1 << 40; b <<= 1) {
+    if (b >= need) return b;
+    if (b >= 2 && 3 * b / 2 >= need) return 3 * b / 2;
+  }
+  return -1;
+}
+
+rl_status make_geometry(const int64_t shape[3], const rl_options* opt, int boundary,
+                        Geometry* g) {
+  if (!shape) return fail(RL_E_INVALID, "shape is NULL");
+  g->boundary = boundary;
+  for (int i = 0; i < 3; ++i) {
+    if (shape[i] < 1) return fail(RL_E_INVALID, "every dimension must be >= 1");
+    if (shape[i] > (int64_t)1 << 30) return fail(RL_E_UNSUPPORTED, "dimension too large");
+    g->vol[i] = shape[i];
+    const int64_t ps = opt ? opt->psf_shape[i] : 0;
+    if (ps < 0 || ps > shape[i])
+      return fail(RL_E_INVALID, "psf_shape must be 0 (the volume's) or in [1, volume dimension]");
+    g->psf[i] = ps > 0 ? ps : shape[i];
+  }
+  if (boundary == RL_BOUNDARY_PERIODIC) {
+    rl_status st = check_shape(shape);
+    if (st != RL_OK) return st;
+    for (int i = 0; i < 3; ++i) g->grid[i] = shape[i];
+    return RL_OK;
+  }
+  for (int i = 0; i < 2; ++i) g->grid[i] = next_len(g->vol[i] + g->psf[i] / 2);
+  const int64_t half = next_len((g->vol[2] + g->psf[2] / 2 + 1) / 2);
+  g->grid[2] = 2 * (half < 2 ? 2 : half);
+  rl_status st = check_shape(g->grid);
+  if (st != RL_OK)
+    return fail(st, "zero boundary: the padded transform grid " + std::to_string(g->grid[0]) +
+                        "x" + std::to_string(g->grid[1]) + "x" + std::to_string(g->grid[2]) +
+                        " is not supported (" + g_err + ")");
   return RL_OK;
 }
 
@@ -778,11 +836,11 @@ rl_status check_device_present() {
 
 // Build the plan of `count` volumes of one (validated) shape on `device`;
 // psfs[i] is volume i's PSF (validated device pointers).  Synchronous.
-rl_status build_class(const int64_t shape[3], int count, const float* const* psfs, int device,
+rl_status build_class(const Geometry& geo, int count, const float* const* psfs, int device,
                       const rl_options* opt, hipStream_t stream, rl_plan* out) {
   rl_status st;
   hipError_t e;
-  const int64_t nz = shape[0], ny = shape[1], nx = shape[2];
+  const int64_t nz = geo.grid[0], ny = geo.grid[1], nx = geo.grid[2];
   const int64_t nvox = nz * ny * nx;
   rl_plan p = new (std::nothrow) rl_plan_s();
   if (!p) return fail(RL_E_NOMEM, "host allocation failed");
@@ -797,6 +855,14 @@ rl_status build_class(const int64_t shape[3], int count, const float* const* psf
   p->xt = (p->ncols + rlmi::kTile - 1) / rlmi::kTile;  // 16-column tiles per row
   p->nvox = nvox;
   p->nrows = nz * ny;
+  p->vz = geo.vol[0];
+  p->vy = geo.vol[1];
+  p->vx = geo.vol[2];
+  p->vnvox = p->vz * p->vy * p->vx;
+  p->psf_z = geo.psf[0];
+  p->psf_y = geo.psf[1];
+  p->psf_x = geo.psf[2];
+  p->boundary = geo.boundary;
   p->spec_elems = (size_t)nz * p->xt * ny * rlmi::kTile;
 
   // launch choice: options first, defaults for the rest
@@ -848,7 +914,7 @@ rl_status build_class(const int64_t shape[3], int count, const float* const* psf
     return st;
   }
   if (p->accel != RL_ACCEL_NONE) {
-    const size_t vb = (size_t)nvox * sizeof(float);
+    const size_t vb = (size_t)p->vnvox * sizeof(float);
     if ((e = hipMalloc(&p->hstep, vb)) != hipSuccess ||
         (e = hipMalloc(&p->gchg, vb)) != hipSuccess ||
         (e = hipMalloc(&p->alpha32, (size_t)(p->flux_cap + 1) * sizeof(float))) != hipSuccess ||
@@ -874,8 +940,8 @@ rl_status build_class(const int64_t shape[3], int count, const float* const* psf
   RL_TRY(rlmi::launch_twiddles(p->tw_z, (int)nz, p->stream));
   for (int v = 0; v < count; ++v) {
     const float* psf = psfs[v];
-    RL_TRY(rlmi::launch_psf_stats(psf, nvox, p->partials, kStatBlocks, p->counter, p->stats,
-                                  p->stream));
+    RL_TRY(rlmi::launch_psf_stats(psf, p->psf_z * p->psf_y * p->psf_x, p->partials,
+                                  kStatBlocks, p->counter, p->stats, p->stream));
     double stats[3] = {0, 0, 0};
     RL_TRY(hipMemcpyAsync(stats, p->stats, 3 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
     RL_TRY(hipStreamSynchronize(p->stream));
@@ -896,11 +962,16 @@ rl_status build_class(const int64_t shape[3], int count, const float* const* psf
     // workspace, transformed along X into the volume's OTF slot, then along Y and Z.
     float2* otf_v = p->otf + (size_t)v * p->spec_elems;
     const double scale = 1.0 / (stats[0] * (double)nvox);
-    RL_TRY(rlmi::launch_psf_prep(psf, reinterpret_cast<float*>(p->spec), (int)nz, (int)ny,
-                                 (int)nx, nx, scale, p->stream));
+    RL_TRY(rlmi::launch_psf_prep(psf, (int)p->psf_z, (int)p->psf_y, (int)p->psf_x,
+                                 reinterpret_cast<float*>(p->spec), (int)nz, (int)ny, (int)nx, nx,
+                                 scale, p->stream));
+    // the prepared kernel covers the whole grid
     XArgs a = base_xargs(p, otf_v);
     a.rin = reinterpret_cast<const float*>(p->spec);
     a.rin_stride = nx;
+    a.vx = (int)nx;
+    a.vy = (int)ny;
+    a.vz = (int)nz;
     a.nvol = 1;
     if ((st = run_x(p, rlmi::XM_R2C, a, RL_KERNEL_OTHER)) != RL_OK ||
         (st = run_pencil(p, p->py, rlmi::PM_FWD, otf_v, p->tw_y, RL_KERNEL_OTHER, 1)) != RL_OK ||
@@ -935,21 +1006,22 @@ rl_status create_impl(const int64_t shape[3], const float* psf, int boundary,
                       const rl_options* opt, rl_plan* out) {
   if (!out) return fail(RL_E_INVALID, "out is NULL");
   *out = nullptr;
-  rl_status st = check_shape(shape);
+  rl_status st = check_boundary(boundary);
   if (st != RL_OK) return st;
-  if ((st = check_boundary(boundary)) != RL_OK) return st;
-  if ((st = check_options(shape, opt)) != RL_OK) return st;
+  Geometry geo;
+  if ((st = make_geometry(shape, opt, boundary, &geo)) != RL_OK) return st;
+  if ((st = check_options(geo.grid, opt)) != RL_OK) return st;
   if (!psf) return fail(RL_E_INVALID, "psf is NULL");
   if (reinterpret_cast<uintptr_t>(psf) % 16 != 0)
     return fail(RL_E_INVALID, "psf is not 16-byte aligned");
   if ((st = check_device_present()) != RL_OK) return st;
-  const int64_t nvox = shape[0] * shape[1] * shape[2];
+  const int64_t pnvox = geo.psf[0] * geo.psf[1] * geo.psf[2];
   int device = -1;
-  if ((st = check_dev_ptr(psf, (size_t)nvox * sizeof(float), &device, "psf")) != RL_OK) return st;
+  if ((st = check_dev_ptr(psf, (size_t)pnvox * sizeof(float), &device, "psf")) != RL_OK) return st;
   rl_plan p = nullptr;
   const float* psfs[1] = {psf};
   hipStream_t stream = opt ? reinterpret_cast<hipStream_t>(opt->stream) : nullptr;
-  if ((st = build_class(shape, 1, psfs, device, opt, stream, &p)) != RL_OK) return st;
+  if ((st = build_class(geo, 1, psfs, device, opt, stream, &p)) != RL_OK) return st;
   plan_register(p);
   *out = p;
   return RL_OK;
@@ -1004,7 +1076,6 @@ rl_status enqueue_prologue(rl_plan p, const float* u) {
   XArgs a = base_xargs(p, p->spec);
   a.rin = u;
   a.rin_tab = u ? nullptr : p->u_tab;
-  a.rin_stride = p->nx;
   rl_status st = run_x(p, rlmi::XM_R2C, a, RL_KERNEL_X_R2C);
   return st != RL_OK ? st : run_yz_filter(p, false);
 }
@@ -1089,7 +1160,7 @@ rl_status iterate_impl(rl_plan p, const float* observed, float* estimate, int n_
   if (st != RL_OK) return st;
   if (p->is_batch) return fail(RL_E_INVALID, "batch plans iterate with rl_iterate_batch");
   if (n_iter < 0) return fail(RL_E_INVALID, "n_iter must be >= 0");
-  const size_t bytes = (size_t)p->nvox * sizeof(float);
+  const size_t bytes = (size_t)p->vnvox * sizeof(float);
   int dev = p->device;
   if ((st = check_dev_ptr(observed, bytes, &dev, "observed")) != RL_OK) return st;
   if ((st = check_dev_ptr(estimate, bytes, &dev, "estimate")) != RL_OK) return st;
@@ -1133,6 +1204,10 @@ rl_status create_batch_impl(int count, const int64_t* shapes, const float* const
       return fail(RL_E_INVALID, "psf of volume " + std::to_string(v) + " is not 16-byte aligned");
   }
   if ((st = check_boundary(boundary)) != RL_OK) return st;
+  if (boundary != RL_BOUNDARY_PERIODIC)
+    return fail(RL_E_UNSUPPORTED, "batch plans use the periodic boundary");
+  if (opt && (opt->psf_shape[0] || opt->psf_shape[1] || opt->psf_shape[2]))
+    return fail(RL_E_UNSUPPORTED, "batch plans take PSFs of their volumes' shapes");
   if (opt && opt->tile_x != 0)
     return fail(RL_E_INVALID, "batch plans choose work-group widths per shape (tile_x must be 0)");
   if ((st = check_device_present()) != RL_OK) return st;
@@ -1191,7 +1266,10 @@ rl_status create_batch_impl(int count, const int64_t* shapes, const float* const
     std::vector<const float*> cpsf;
     for (int w : members) cpsf.push_back(psfs[w]);
     rl_plan c = nullptr;
-    if ((st = build_class(sh, (int)members.size(), cpsf.data(), device, opt, cs, &c)) != RL_OK) {
+    Geometry geo;
+    geo.boundary = RL_BOUNDARY_PERIODIC;
+    for (int i = 0; i < 3; ++i) geo.grid[i] = geo.vol[i] = geo.psf[i] = sh[i];
+    if ((st = build_class(geo, (int)members.size(), cpsf.data(), device, opt, cs, &c)) != RL_OK) {
       const std::string msg = g_err;
       release(b);
       return fail(st, msg);
@@ -1257,7 +1335,7 @@ rl_status iterate_batch_impl(rl_plan b, const float* const* observed, float* con
   if (!observed || !estimate) return fail(RL_E_INVALID, "observed or estimate is NULL");
   for (int v = 0; v < b->count; ++v) {
     const rl_plan c = b->classes[b->vol_class[v]];
-    const size_t bytes = (size_t)c->nvox * sizeof(float);
+    const size_t bytes = (size_t)c->vnvox * sizeof(float);
     int dev = b->device;
     if ((st = check_dev_ptr(observed[v], bytes, &dev, "observed volume")) != RL_OK ||
         (st = check_dev_ptr(estimate[v], bytes, &dev, "estimate volume")) != RL_OK)
@@ -1324,7 +1402,7 @@ rl_status conv_impl(rl_plan p, const float* x, float* out) {
   rl_status st = check_plan(p);
   if (st != RL_OK) return st;
   if (p->is_batch) return fail(RL_E_UNSUPPORTED, "conv3d_fft takes a single-volume plan");
-  const size_t bytes = (size_t)p->nvox * sizeof(float);
+  const size_t bytes = (size_t)p->vnvox * sizeof(float);
   int dev = p->device;
   if ((st = check_dev_ptr(x, bytes, &dev, "x")) != RL_OK) return st;
   if ((st = check_dev_ptr(out, bytes, &dev, "out")) != RL_OK) return st;
@@ -1332,12 +1410,10 @@ rl_status conv_impl(rl_plan p, const float* x, float* out) {
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   XArgs a = base_xargs(p, p->spec);
   a.rin = x;
-  a.rin_stride = p->nx;
   if ((st = run_x(p, rlmi::XM_R2C, a, RL_KERNEL_X_R2C)) != RL_OK) return st;
   if ((st = run_yz_filter(p, false)) != RL_OK) return st;
   XArgs c = base_xargs(p, p->spec);
   c.rout = out;
-  c.rout_stride = p->nx;
   return run_x(p, rlmi::XM_C2R, c, RL_KERNEL_X_C2R);
 }
 
@@ -1477,13 +1553,24 @@ rl_status rl_plan_get_alpha(rl_plan p, double* alpha, int cap, int* n_written) {
   return RL_OK;
 }
 
+rl_status rl_plan_get_grid(rl_plan p, int64_t grid[3]) {
+  rl_status st = check_plan(p);
+  if (st != RL_OK) return st;
+  if (!grid) return fail(RL_E_INVALID, "grid is NULL");
+  if (p->is_batch) p = p->classes[0];
+  grid[0] = p->nz;
+  grid[1] = p->ny;
+  grid[2] = p->nx;
+  return RL_OK;
+}
+
 rl_status rl_plan_get_info(rl_plan p, int64_t shape[3], int64_t* spectrum_pitch) {
   rl_status st = check_plan(p);
   if (st != RL_OK) return st;
   if (shape) {
-    shape[0] = p->nz;
-    shape[1] = p->ny;
-    shape[2] = p->nx;
+    shape[0] = p->is_batch ? p->nz : p->vz;
+    shape[1] = p->is_batch ? p->ny : p->vy;
+    shape[2] = p->is_batch ? p->nx : p->vx;
   }
   if (spectrum_pitch) *spectrum_pitch = p->xt * rlmi::kTile;
   return RL_OK;
@@ -1514,7 +1601,7 @@ rl_status rl_plan_time_pass(rl_plan p, int kind, const float* observed, float* e
   if (kind != RL_KERNEL_X_RATIO && kind != RL_KERNEL_X_UPDATE && kind != RL_KERNEL_Y &&
       kind != RL_KERNEL_Z_OTF)
     return fail(RL_E_INVALID, "kind must be X_RATIO, X_UPDATE, Y or Z_OTF");
-  const size_t bytes = (size_t)p->nvox * sizeof(float);
+  const size_t bytes = (size_t)p->vnvox * sizeof(float);
   int dev = p->device;
   if ((st = check_dev_ptr(observed, bytes, &dev, "observed")) != RL_OK) return st;
   if ((st = check_dev_ptr(estimate, bytes, &dev, "estimate")) != RL_OK) return st;

@@ -95,6 +95,12 @@ struct XArgs {
   const float* alpha;    // alpha[k] (FP32); not read (taken as 0) when iter == 0
   double* acc_partials;  // XM_UPDATE_ACC: [2][work-group] FP64 partials of
                          // <g_k, g_{k-1}> and <g_{k-1}, g_{k-1}>
+  // Real rows (rin, rout, d, u, hstep, gchg) cover the caller's volume
+  // vz x vy x vx at the low corner of the transform grid: grid row (z, y) is
+  // real row z * vy + y when z < vz and y < vy, and holds vx floats (the rest of
+  // the grid row reads as zero and is not written).  rin / rout rows are
+  // rin_stride / rout_stride floats apart, the others vx.
+  int vx, vy, vz;
   int M;                 // complex row length nx/2
   int P;                 // threads per row (M / E)
   int RPW;               // rows per work-group (a multiple of 64 / P)
@@ -136,8 +142,11 @@ hipError_t launch_set_counter(int* counter, int value, hipStream_t s);
 // out[0] = sum(h), out[1] = min(h), out[2] = number of non-finite entries (FP64).
 hipError_t launch_psf_stats(const float* h, long long n, double* partials, int nblk,
                             unsigned* counter, double* out, hipStream_t s);
-hipError_t launch_psf_prep(const float* h, float* out, int nz, int ny, int nx,
-                           long long out_row_stride, double scale, hipStream_t s);
+// Writes the PSF h (shape pz x py x px, each <= the grid's) times `scale`,
+// centred on voxel 0 of the periodic grid nz x ny x nx (zero elsewhere), as
+// real rows `out_row_stride` floats apart.
+hipError_t launch_psf_prep(const float* h, int pz, int py, int px, float* out, int nz, int ny,
+                           int nx, long long out_row_stride, double scale, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 
 }  // namespace rlmi

@@ -493,6 +493,27 @@ __device__ __forceinline__ float2 predict2(float2 x, float2 h, float al) {
   return make_float2(predict1(x.x, h.x, al), predict1(x.y, h.y, al));
 }
 
+// Pair q (elements 2q, 2q+1) of a real row of `vx` floats; zero beyond the row
+// or when `on` is false.  Rows of odd length are not 8-byte aligned, so they
+// are read one float at a time.
+__device__ __forceinline__ float2 load_pair(const float* row, int q, int vx, bool on) {
+  const int x = 2 * q;
+  if (!on || x >= vx) return make_float2(0.f, 0.f);
+  if ((vx & 1) == 0) return reinterpret_cast<const float2*>(row)[q];
+  return make_float2(row[x], x + 1 < vx ? row[x + 1] : 0.f);
+}
+
+__device__ __forceinline__ void store_pair(float* row, int q, int vx, bool on, float2 v) {
+  const int x = 2 * q;
+  if (!on || x >= vx) return;
+  if ((vx & 1) == 0) {
+    reinterpret_cast<float2*>(row)[q] = v;
+  } else {
+    row[x] = v.x;
+    if (x + 1 < vx) row[x + 1] = v.y;
+  }
+}
+
 template <int E, int MODE, int PREC = 0>
 __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const float2* __restrict__ twg) {
   extern __shared__ float2 lds[];
@@ -512,29 +533,30 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
   float* stg = reinterpret_cast<float*>(lds + 2 * M + wave * rpw * a.RS);
   const int vol = blockIdx.y;
   const int zz = (int)(rix / a.ny), yy = (int)(rix - (long long)zz * a.ny);
+  // real rows: the caller's volume (vz, vy, vx) inside the transform grid
+  const bool rv = ok && zz < a.vz && yy < a.vy;
+  const long long rr = rv ? (long long)zz * a.vy + yy : 0;
+  const int vx = a.vx;
   float2* srow = a.spec + (long long)vol * a.vstride + (long long)zz * a.zstride + yy * kTile;
   const long long ts = a.tstride;
 
   float2 v[E];
   if constexpr (MODE == XM_R2C) {
-    const float* rin = a.rin_tab ? a.rin_tab[vol] : a.rin;
-    const float2* in = reinterpret_cast<const float2*>(rin + rix * a.rin_stride);
+    const float* rin = (a.rin_tab ? a.rin_tab[vol] : a.rin) + rr * a.rin_stride;
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = ok ? in[i + P * m] : make_float2(0.f, 0.f);
+    for (int m = 0; m < E; ++m) v[m] = load_pair(rin, i + P * m, vx, rv);
     __syncthreads();  // twiddles in LDS
     r2c_store<E, PREC>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
   } else if constexpr (MODE == XM_PREDICT) {
-    const long long ro = rix * (2LL * M);
-    const float2* xr = reinterpret_cast<const float2*>(a.u + ro);
+    const long long ro = rr * vx;
     const bool hist = a.iter > 0;
     const float al = hist ? a.alpha[a.iter] : 0.f;
     float2 hv[E];
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = ok ? xr[i + P * m] : make_float2(0.f, 0.f);
+    for (int m = 0; m < E; ++m) v[m] = load_pair(a.u + ro, i + P * m, vx, rv);
     if (hist) {
-      const float2* hr = reinterpret_cast<const float2*>(a.hstep + ro);
 #pragma unroll
-      for (int m = 0; m < E; ++m) hv[m] = ok ? hr[i + P * m] : make_float2(0.f, 0.f);
+      for (int m = 0; m < E; ++m) hv[m] = load_pair(a.hstep + ro, i + P * m, vx, rv);
     } else {
 #pragma unroll
       for (int m = 0; m < E; ++m) hv[m] = make_float2(0.f, 0.f);
@@ -552,27 +574,22 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
     for (int m = 0; m < E; ++m) v[m] = ok ? srow[col_off(i + P * m, ts)] : make_float2(0.f, 0.f);
     const float2 nyq = (ok && i == 0) ? srow[col_off(M, ts)] : make_float2(0.f, 0.f);
     if constexpr (MODE == XM_RATIO) {
-      const float* dbase = a.d_tab ? a.d_tab[vol] : a.d;
-      const float2* dr = reinterpret_cast<const float2*>(dbase + rix * (2LL * M));
+      const float* dr = (a.d_tab ? a.d_tab[vol] : a.d) + rr * vx;
 #pragma unroll
-      for (int m = 0; m < E; ++m) w[m] = ok ? dr[i + P * m] : make_float2(0.f, 0.f);
+      for (int m = 0; m < E; ++m) w[m] = load_pair(dr, i + P * m, vx, rv);
     } else if constexpr (MODE == XM_UPDATE) {
-      const float* ubase = a.u_tab ? a.u_tab[vol] : a.u;
-      const float2* ur = reinterpret_cast<const float2*>(ubase + rix * (2LL * M));
+      const float* ur = (a.u_tab ? a.u_tab[vol] : a.u) + rr * vx;
 #pragma unroll
-      for (int m = 0; m < E; ++m) w[m] = ok ? ur[i + P * m] : make_float2(0.f, 0.f);
+      for (int m = 0; m < E; ++m) w[m] = load_pair(ur, i + P * m, vx, rv);
     } else if constexpr (kAcc) {
-      const long long ro = rix * (2LL * M);
-      const float2* xr = reinterpret_cast<const float2*>(a.u + ro);
+      const long long ro = rr * vx;
 #pragma unroll
-      for (int m = 0; m < E; ++m) w[m] = ok ? xr[i + P * m] : make_float2(0.f, 0.f);
+      for (int m = 0; m < E; ++m) w[m] = load_pair(a.u + ro, i + P * m, vx, rv);
       if (a.iter > 0) {
-        const float2* hr = reinterpret_cast<const float2*>(a.hstep + ro);
-        const float2* gr = reinterpret_cast<const float2*>(a.gchg + ro);
 #pragma unroll
         for (int m = 0; m < E; ++m) {
-          hv[m] = ok ? hr[i + P * m] : make_float2(0.f, 0.f);
-          gv[m] = ok ? gr[i + P * m] : make_float2(0.f, 0.f);
+          hv[m] = load_pair(a.hstep + ro, i + P * m, vx, rv);
+          gv[m] = load_pair(a.gchg + ro, i + P * m, vx, rv);
         }
       } else {
 #pragma unroll
@@ -584,12 +601,9 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
     fft<E, +1, true, kXPad, PREC>(v, sc, i, P, tw, row, 1, 0, stg);
     // v[m] holds (x[2n], x[2n+1]) for n = i + P*m (unnormalised; the 1/N is in the OTF)
     if constexpr (MODE == XM_C2R) {
-      if (ok) {
-        float* rout = a.rout_tab ? a.rout_tab[vol] : a.rout;
-        float2* out = reinterpret_cast<float2*>(rout + rix * a.rout_stride);
+      float* rout = (a.rout_tab ? a.rout_tab[vol] : a.rout) + rr * a.rout_stride;
 #pragma unroll
-        for (int m = 0; m < E; ++m) out[i + P * m] = v[m];
-      }
+      for (int m = 0; m < E; ++m) store_pair(rout, i + P * m, vx, rv, v[m]);
     } else if constexpr (MODE == XM_RATIO) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
@@ -601,10 +615,7 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
     } else if constexpr (kAcc) {
       // x_{k+1} = y_k * max(c, 0) from the prediction y_k; keep h and g for the next
       // extrapolation and accumulate the flux and the two inner products of alpha
-      const long long ro = rix * (2LL * M);
-      float2* xr = reinterpret_cast<float2*>(a.u + ro);
-      float2* hr = reinterpret_cast<float2*>(a.hstep + ro);
-      float2* gr = reinterpret_cast<float2*>(a.gchg + ro);
+      const long long ro = rr * vx;
       const float al = a.iter > 0 ? a.alpha[a.iter] : 0.f;
       double acc = 0.0, sgg = 0.0, spp = 0.0;
 #pragma unroll
@@ -614,11 +625,9 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
         const float2 xn = make_float2(y.x * (c.x < 0.f ? 0.f : c.x), y.y * (c.y < 0.f ? 0.f : c.y));
         const float2 g = make_float2(xn.x - y.x, xn.y - y.y);
         const float2 hn = make_float2(xn.x - w[m].x, xn.y - w[m].y);
-        if (ok) {
-          xr[i + P * m] = xn;
-          hr[i + P * m] = hn;
-          gr[i + P * m] = g;
-        }
+        store_pair(a.u + ro, i + P * m, vx, rv, xn);
+        store_pair(a.hstep + ro, i + P * m, vx, rv, hn);
+        store_pair(a.gchg + ro, i + P * m, vx, rv, g);
         acc += (double)xn.x + (double)xn.y;
         sgg += (double)g.x * (double)gv[m].x + (double)g.y * (double)gv[m].y;
         spp += (double)gv[m].x * (double)gv[m].x + (double)gv[m].y * (double)gv[m].y;
@@ -649,7 +658,7 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
         a.acc_partials[gridDim.x + blockIdx.x] = t2;
       }
     } else {  // XM_UPDATE
-      float2* ur = reinterpret_cast<float2*>((a.u_tab ? a.u_tab[vol] : a.u) + rix * (2LL * M));
+      float* ur = (a.u_tab ? a.u_tab[vol] : a.u) + rr * vx;
       double acc = 0.0;
 #pragma unroll
       for (int m = 0; m < E; ++m) {
@@ -658,7 +667,7 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
         // that non-finite inputs reach the flux check instead of being silently zeroed
         const float2 un = make_float2(w[m].x * (c.x < 0.f ? 0.f : c.x),
                                       w[m].y * (c.y < 0.f ? 0.f : c.y));
-        if (ok) ur[i + P * m] = un;
+        store_pair(ur, i + P * m, vx, rv, un);
         acc += (double)un.x + (double)un.y;
         v[m] = un;
       }
@@ -816,14 +825,27 @@ __global__ void __launch_bounds__(256) k_psf_stats(const float* __restrict__ h, 
 
 // out[z][y][x] (rows `out_row_stride` floats apart) = h[(z+cz)%nz][(y+cy)%ny][(x+cx)%nx] * scale,
 // with the product taken in FP64: moves the PSF centre floor(n/2) to index 0.
+// PSF index along one axis that lands on grid index o once the PSF (length p,
+// centre p/2) is centred on voxel 0 of a periodic grid of length n >= p:
+// offsets 0 .. p-1-c sit at o = offset, offsets -c .. -1 at o = n + offset.
+// -1: no PSF entry lands on o.
+__device__ __forceinline__ int psf_src(int o, int n, int p) {
+  const int c = p / 2;
+  if (o < p - c) return o + c;
+  if (o >= n - c) return o - n + c;
+  return -1;
+}
+
 __global__ void k_psf_prep(const float* __restrict__ h, float* __restrict__ out, int nz, int ny,
-                           int nx, long long out_row_stride, double scale) {
+                           int nx, int pz, int py, int px, long long out_row_stride,
+                           double scale) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   const int z = blockIdx.z;
   if (x >= nx) return;
-  const int sx = (x + nx / 2) % nx, sy = (y + ny / 2) % ny, sz = (z + nz / 2) % nz;
-  const float v = h[((long long)sz * ny + sy) * nx + sx];
+  const int sx = psf_src(x, nx, px), sy = psf_src(y, ny, py), sz = psf_src(z, nz, pz);
+  float v = 0.f;
+  if (sx >= 0 && sy >= 0 && sz >= 0) v = h[((long long)sz * py + sy) * px + sx];
   out[((long long)z * ny + y) * out_row_stride + x] = (float)((double)v * scale);
 }
 
@@ -1026,10 +1048,11 @@ hipError_t launch_psf_stats(const float* h, long long n, double* partials, int n
   return hipGetLastError();
 }
 
-hipError_t launch_psf_prep(const float* h, float* out, int nz, int ny, int nx,
-                           long long out_row_stride, double scale, hipStream_t s) {
+hipError_t launch_psf_prep(const float* h, int pz, int py, int px, float* out, int nz, int ny,
+                           int nx, long long out_row_stride, double scale, hipStream_t s) {
   dim3 g((nx + 255) / 256, ny, nz);
-  hipLaunchKernelGGL(k_psf_prep, g, dim3(256), 0, s, h, out, nz, ny, nx, out_row_stride, scale);
+  hipLaunchKernelGGL(k_psf_prep, g, dim3(256), 0, s, h, out, nz, ny, nx, pz, py, px,
+                     out_row_stride, scale);
   return hipGetLastError();
 }
 

@@ -46,7 +46,7 @@ _STATUS_NAMES = {0: "RL_OK", 1: "RL_E_INVALID", 2: "RL_E_UNSUPPORTED", 3: "RL_E_
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("stream", ctypes.c_void_p), ("tile_x", ctypes.c_int),
                 ("x_elems", ctypes.c_int), ("yz_elems", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("accel", ctypes.c_int)]
+                ("accel", ctypes.c_int), ("psf_shape", ctypes.c_int64 * 3)]
 
 
 _lib = None
@@ -74,6 +74,7 @@ def lib() -> ctypes.CDLL:
         "rl_plan_get_alpha": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "rl_plan_get_info": ([vp, i64p, i64p], ctypes.c_int),
+        "rl_plan_get_grid": ([vp, i64p], ctypes.c_int),
         "rl_plan_get_launch": ([vp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "rl_plan_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
         "rl_plan_time_pass": ([vp, ctypes.c_int, vp, vp, ctypes.c_int,
@@ -129,10 +130,11 @@ def rl_plan_create(shape, psf_ptr: int, boundary: int = RL_BOUNDARY_PERIODIC) ->
 def rl_plan_create_ex(shape, psf_ptr: int, boundary: int = RL_BOUNDARY_PERIODIC,
                       precision: int = RL_PRECISION_FP32, stream: int = 0, tile_x: int = 0,
                       x_elems: int = 0, yz_elems: int = 0, autotune: bool = False,
-                      accel: int = RL_ACCEL_NONE) -> int:
+                      accel: int = RL_ACCEL_NONE, psf_shape=(0, 0, 0)) -> int:
     out = ctypes.c_void_p()
     opt = _Options(int(precision), ctypes.c_void_p(stream or None), int(tile_x), int(x_elems),
-                   int(yz_elems), 1 if autotune else 0, int(accel))
+                   int(yz_elems), 1 if autotune else 0, int(accel),
+                   (ctypes.c_int64 * 3)(*[int(v) for v in psf_shape]))
     _check(lib().rl_plan_create_ex(_shape(shape), ctypes.c_void_p(psf_ptr), int(boundary),
                                    ctypes.byref(opt), ctypes.byref(out)))
     return out.value
@@ -195,6 +197,12 @@ def rl_plan_get_alpha(plan: int) -> np.ndarray:
     buf = (ctypes.c_double * max(1, n.value))()
     _check(lib().rl_plan_get_alpha(ctypes.c_void_p(plan), buf, n.value, ctypes.byref(n)))
     return np.array(buf[: n.value], dtype=np.float64)
+
+
+def rl_plan_get_grid(plan: int) -> tuple:
+    g = (ctypes.c_int64 * 3)()
+    _check(lib().rl_plan_get_grid(ctypes.c_void_p(plan), g))
+    return tuple(int(v) for v in g)
 
 
 def rl_plan_get_info(plan: int):
@@ -269,18 +277,25 @@ def _check_volume(t, shape, device, name):
 
 
 class Plan:
-    """Richardson-Lucy plan for one volume shape and PSF (a float32 CUDA tensor [Z][Y][X])."""
+    """Richardson-Lucy plan for one volume shape and PSF (a float32 CUDA tensor [Z][Y][X]).
+
+    `shape` is the volume's (Z, Y, X); None = the PSF's shape.  A smaller PSF is
+    centred at floor(p/2) per axis.  boundary "periodic" (circular) or "zero"
+    (linear convolution; the library pads the transform grid itself)."""
 
     def __init__(self, psf, boundary: str = "periodic", tile_x: int = 0, x_elems: int = 0,
                  yz_elems: int = 0, autotune: bool = False, precision: str = "fp32",
-                 accel: str = "none"):
+                 accel: str = "none", shape=None):
         bmap = {"periodic": RL_BOUNDARY_PERIODIC, "zero": RL_BOUNDARY_ZERO}
         if boundary not in bmap:
             raise ValueError("boundary must be 'periodic' or 'zero'")
         if psf.dim() != 3:
             raise ValueError("psf must be a 3-D tensor")
         _check_volume(psf, psf.shape, None, "psf")
-        self.shape = tuple(int(s) for s in psf.shape)
+        psf_shape = tuple(int(s) for s in psf.shape)
+        self.shape = tuple(int(s) for s in shape) if shape is not None else psf_shape
+        if len(self.shape) != 3:
+            raise ValueError("shape must have three dimensions")
         self.device = psf.device
         if precision not in _PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(_PRECISIONS)}")
@@ -291,7 +306,9 @@ class Plan:
                                         precision=_PRECISIONS[precision],
                                         stream=_stream_of(self.device), tile_x=tile_x,
                                         x_elems=x_elems, yz_elems=yz_elems, autotune=autotune,
-                                        accel=_ACCELS[accel])
+                                        accel=_ACCELS[accel],
+                                        psf_shape=psf_shape if psf_shape != self.shape else (0, 0, 0))
+        self.boundary = boundary
 
     def _bind_stream(self):
         rl_plan_set_stream(self.handle, _stream_of(self.device))
@@ -341,6 +358,11 @@ class Plan:
     def info(self):
         self._live()
         return rl_plan_get_info(self.handle)
+
+    def grid(self) -> tuple:
+        """Transform grid (Z, Y, X): the volume's shape, or the padded grid of the zero boundary."""
+        self._live()
+        return rl_plan_get_grid(self.handle)
 
     def time_pass(self, kind: str, observed, estimate, reps: int = 20) -> float:
         """Steady-state ms per launch of a pass kind ('x_ratio', 'x_update', 'y', 'z_otf');

@@ -58,9 +58,29 @@ def test_bad_arguments_rejected():
     assert L.rl_plan_create(sh, None, 0, ctypes.byref(out)) == rl.RL_E_INVALID
     assert L.rl_plan_create(sh, ctypes.c_void_p(4100), 0, ctypes.byref(out)) == rl.RL_E_INVALID
     assert L.rl_plan_create(sh, ctypes.c_void_p(4096), 7, ctypes.byref(out)) == rl.RL_E_INVALID
-    assert L.rl_plan_create(sh, ctypes.c_void_p(4096), rl.RL_BOUNDARY_ZERO,
+    # zero boundary: the padded grid must be supported (nx 1500 pads beyond 2048)
+    big = (ctypes.c_int64 * 3)(8, 8, 1500)
+    assert L.rl_plan_create(big, ctypes.c_void_p(4096), rl.RL_BOUNDARY_ZERO,
                             ctypes.byref(out)) == rl.RL_E_UNSUPPORTED
-    assert "periodic" in rl.rl_last_error()
+    assert "zero boundary" in rl.rl_last_error()
+    # psf_shape must lie in [1, volume dimension]
+    for ps in ((9, 8, 8), (8, -1, 8), (8, 8, 9)):
+        opt = rl._Options(0, None, 0, 0, 0, 0, 0, (ctypes.c_int64 * 3)(*ps))
+        st = L.rl_plan_create_ex(sh, ctypes.c_void_p(4096), 0, ctypes.byref(opt), ctypes.byref(out))
+        assert st == rl.RL_E_INVALID and "psf_shape" in rl.rl_last_error(), ps
+    # batch plans: periodic boundary, same-shape PSFs
+    ps = (ctypes.c_void_p * 1)(4096)
+    assert L.rl_plan_create_batch(1, sh, ps, rl.RL_BOUNDARY_ZERO, None,
+                                  ctypes.byref(out)) == rl.RL_E_UNSUPPORTED
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device path")
+@pytest.mark.parametrize("shape", [(7, 9, 11), (1, 5, 3), (30, 100, 90)])
+def test_zero_boundary_accepts_any_volume_shape(shape):
+    # every dimension is allowed with the zero boundary (the grid is padded); without a
+    # device the call gets as far as the device check
+    st, out = _create(shape, boundary=rl.RL_BOUNDARY_ZERO)
+    assert st == rl.RL_E_DEVICE, rl.rl_last_error()
 
 
 @pytest.mark.skipif(_has_gpu(), reason="checks the no-device path")
