@@ -355,6 +355,7 @@ void finish_pencil(Pencil& pc, int txb) {
   pc.args.P = pc.ax.P;
   pc.args.TXB = txb;
   pc.args.TXP = txb;
+  pc.args.lin = pc.args.lout = (int)pc.ax.L;
   // exchange buffer (L x TXP) followed by the twiddle table (L); the kernel
   // places the table at offset L * TXP whether or not the exchange is used
   pc.lds = (size_t)pc.ax.L * (txb + 1) * sizeof(float2);
@@ -447,8 +448,10 @@ rl_status timed_begin(rl_plan p, int kind, size_t* slot, hipEvent_t* ev0, hipEve
 
 // One pencil pass over `nvol` consecutive volumes starting at `data` (and at
 // the plan's OTF for the filtered modes); nvol = 0 means all of the plan's.
+// lin / lout > 0: only pencil elements below them are read / written; outer > 0:
+// only that many outer blocks (Y pass: z planes) are launched.
 rl_status run_pencil(rl_plan p, const Pencil& pc, int mode, float2* data, const float2* tw,
-                     int kind, int nvol = 0) {
+                     int kind, int nvol = 0, int lin = 0, int lout = 0, int outer = 0) {
   if (pc.ax.L == 1 && (mode == rlmi::PM_FWD || mode == rlmi::PM_INV)) return RL_OK;  // identity
   size_t slot = 0;
   hipEvent_t ev0, ev1;
@@ -457,12 +460,18 @@ rl_status run_pencil(rl_plan p, const Pencil& pc, int mode, float2* data, const 
   dim3 grid = pc.grid;
   grid.z = (unsigned)(nvol > 0 ? nvol : p->count);
   PencilArgs args = pc.args;
+  if (lin > 0) args.lin = lin;
+  if (lout > 0) args.lout = lout;
+  if (outer > 0) (args.swap ? grid.x : grid.y) = (unsigned)outer;
   args.vstride = (long long)p->spec_elems;
   hipError_t e = rlmi::launch_pencil(mode, pc.ax.E, p->precision, grid, pc.block, pc.lds,
                                      p->stream, data, p->otf, tw, args, pc.ax.sc, ev0, ev1);
   if (e != hipSuccess) return hip_fail(e, "pencil pass launch");
   return RL_OK;
 }
+
+// Grid rows the X passes cover: the planes of the caller's volume.
+int64_t x_rows(rl_plan p) { return p->vz * p->ny; }
 
 XArgs base_xargs(rl_plan p, float2* spec) {
   XArgs a;
@@ -480,18 +489,20 @@ XArgs base_xargs(rl_plan p, float2* spec) {
   a.P = p->axx.P;
   a.RPW = p->x_rpw;
   a.RS = p->x_rs;
-  a.nrows = (int)p->nrows;
+  a.nrows = (int)x_rows(p);
   a.nvol = p->count;
   a.vstride = (long long)p->spec_elems;
   return a;
 }
 
-rl_status run_x(rl_plan p, int mode, const XArgs& a, int kind) {
+// rows > 0: cover that many grid rows instead of the volume's.
+rl_status run_x(rl_plan p, int mode, const XArgs& a, int kind, int64_t rows = 0) {
   size_t slot = 0;
   hipEvent_t ev0, ev1;
   rl_status st = timed_begin(p, kind, &slot, &ev0, &ev1);
   if (st != RL_OK) return st;
   dim3 grid = p->x_grid;
+  if (rows > 0) grid.x = (unsigned)((rows + p->x_rpw - 1) / p->x_rpw);
   grid.y = (unsigned)a.nvol;
   hipError_t e = rlmi::launch_xrow(mode, p->axx.E, p->precision, grid, p->x_block, p->x_lds,
                                    p->stream, a, p->axx.sc, p->tw_x, ev0, ev1);
@@ -501,13 +512,23 @@ rl_status run_x(rl_plan p, int mode, const XArgs& a, int kind) {
 
 // spectrum (X-transformed) -> spectrum (X-transformed) of H x or H^T x:
 // Y forward, Z forward * (conj) OTF * Z inverse, Y inverse.
+// With the zero boundary only the caller's volume (vz planes, vy rows) of the
+// grid holds data between passes: the forward Y pass reads vy rows of vz planes,
+// the Z pass reads and writes vz planes, the inverse Y pass writes vy rows; the
+// rest of the grid is read as zero and never written.
+rl_status run_y_fwd(rl_plan p) {
+  return run_pencil(p, p->py, rlmi::PM_FWD, p->spec, p->tw_y, RL_KERNEL_Y, 0, (int)p->vy, 0,
+                    (int)p->vz);
+}
+
 rl_status run_yz_filter(rl_plan p, bool adjoint) {
   rl_status st;
-  if ((st = run_pencil(p, p->py, rlmi::PM_FWD, p->spec, p->tw_y, RL_KERNEL_Y)) != RL_OK) return st;
+  if ((st = run_y_fwd(p)) != RL_OK) return st;
   if ((st = run_pencil(p, p->pz, adjoint ? rlmi::PM_FCKI : rlmi::PM_FKI, p->spec, p->tw_z,
-                       RL_KERNEL_Z_OTF)) != RL_OK)
+                       RL_KERNEL_Z_OTF, 0, (int)p->vz, (int)p->vz)) != RL_OK)
     return st;
-  return run_pencil(p, p->py, rlmi::PM_INV, p->spec, p->tw_y, RL_KERNEL_Y);
+  return run_pencil(p, p->py, rlmi::PM_INV, p->spec, p->tw_y, RL_KERNEL_Y, 0, 0, (int)p->vy,
+                    (int)p->vz);
 }
 
 // Launch choice: elements per thread and lane widths per pass (0 = default).
@@ -534,7 +555,7 @@ bool configure_x(rl_plan p, int x_e) {
   p->x_rpw = waves * rows_per_wave;
   p->x_lds = lds_for(waves);
   p->x_block = dim3((unsigned)(64 * waves));
-  p->x_grid = dim3((unsigned)((p->nrows + p->x_rpw - 1) / p->x_rpw));
+  p->x_grid = dim3((unsigned)((x_rows(p) + p->x_rpw - 1) / p->x_rpw));
   p->ch_x_e = ax.E;
   return true;
 }
@@ -972,8 +993,9 @@ rl_status build_class(const Geometry& geo, int count, const float* const* psfs, 
     a.vx = (int)nx;
     a.vy = (int)ny;
     a.vz = (int)nz;
+    a.nrows = (int)p->nrows;
     a.nvol = 1;
-    if ((st = run_x(p, rlmi::XM_R2C, a, RL_KERNEL_OTHER)) != RL_OK ||
+    if ((st = run_x(p, rlmi::XM_R2C, a, RL_KERNEL_OTHER, p->nrows)) != RL_OK ||
         (st = run_pencil(p, p->py, rlmi::PM_FWD, otf_v, p->tw_y, RL_KERNEL_OTHER, 1)) != RL_OK ||
         (st = run_pencil(p, p->pz, rlmi::PM_FWD, otf_v, p->tw_z, RL_KERNEL_OTHER, 1)) != RL_OK) {
       release(p);
@@ -1624,9 +1646,10 @@ rl_status rl_plan_time_pass(rl_plan p, int kind, const float* observed, float* e
         return run_x(p, rlmi::XM_UPDATE, w, kind);
       }
       case RL_KERNEL_Y:
-        return run_pencil(p, p->py, rlmi::PM_FWD, p->spec, p->tw_y, kind);
+        return run_y_fwd(p);
       default:
-        return run_pencil(p, p->pz, rlmi::PM_FKI, p->spec, p->tw_z, kind);
+        return run_pencil(p, p->pz, rlmi::PM_FKI, p->spec, p->tw_z, kind, 0, (int)p->vz,
+                          (int)p->vz);
     }
   };
   hipEvent_t a = nullptr, b = nullptr;

@@ -50,6 +50,8 @@ struct PencilArgs {
   long long estride;
   long long vstride;  // complex elements between volumes (work-group z index = volume)
   int swap;           // 1: tile index from blockIdx.y and outer index from blockIdx.x
+  int lin;            // elements e >= lin of a pencil read as zero (not loaded)
+  int lout;           // elements e >= lout are not stored
 };
 
 enum PencilMode { PM_FWD = 0, PM_INV = 1, PM_FKI = 2, PM_FCKI = 3 };
@@ -105,7 +107,7 @@ struct XArgs {
   int P;                 // threads per row (M / E)
   int RPW;               // rows per work-group (a multiple of 64 / P)
   int RS;                // LDS row stride in complex elements (>= M + 1)
-  int nrows;             // nz * ny
+  int nrows;             // grid rows covered by the launch (row = z * ny + y)
 };
 
 // Pencil kernels exist for work-groups of up to 512 threads (all E) and up to

@@ -401,7 +401,8 @@ __global__ void __launch_bounds__(MAXT, (MAXT == 1024 && E == 8) ? 8 : 1)
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m)
-    v[m] = ok ? data[base + (long long)(i + a.P * m) * a.estride] : make_float2(0.f, 0.f);
+    v[m] = (ok && i + a.P * m < a.lin) ? data[base + (long long)(i + a.P * m) * a.estride]
+                                        : make_float2(0.f, 0.f);
   __syncthreads();  // twiddles in LDS
 
   // split-precision stages stage their operands in this wave's slice of the exchange buffer
@@ -418,7 +419,8 @@ __global__ void __launch_bounds__(MAXT, (MAXT == 1024 && E == 8) ? 8 : 1)
 
   if (ok) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) data[base + (long long)(i + a.P * m) * a.estride] = v[m];
+    for (int m = 0; m < E; ++m)
+      if (i + a.P * m < a.lout) data[base + (long long)(i + a.P * m) * a.estride] = v[m];
   }
 }
 
@@ -526,15 +528,17 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
   const int rw = lane / P, i = lane - rw * P;
   const int lrow = wave * rpw + rw;             // row within the work-group
   const int rowi = blockIdx.x * a.RPW + lrow;
-  const bool ok = rowi < a.nrows;
-  const long long rix = ok ? rowi : 0;
+  const bool inrow = rowi < a.nrows;
+  const long long rix = inrow ? rowi : 0;
   float2* row = lds + 2 * M + lrow * a.RS;
   // split-precision stages: the wave's rows double as its staging area (>= 64 * 32 floats)
   float* stg = reinterpret_cast<float*>(lds + 2 * M + wave * rpw * a.RS);
   const int vol = blockIdx.y;
   const int zz = (int)(rix / a.ny), yy = (int)(rix - (long long)zz * a.ny);
-  // real rows: the caller's volume (vz, vy, vx) inside the transform grid
-  const bool rv = ok && zz < a.vz && yy < a.vy;
+  // rows of the caller's volume (vz, vy, vx) inside the transform grid; grid rows
+  // outside it are neither read nor written (the pencil passes read them as zero)
+  const bool ok = inrow && zz < a.vz && yy < a.vy;
+  const bool rv = ok;
   const long long rr = rv ? (long long)zz * a.vy + yy : 0;
   const int vx = a.vx;
   float2* srow = a.spec + (long long)vol * a.vstride + (long long)zz * a.zstride + yy * kTile;
