@@ -6,5 +6,5 @@ from .rl_oracle import (  # noqa: F401
 )
 from .accel_oracle import extrapolate, rl_accel  # noqa: F401,E402
 from .boundary_oracle import (  # noqa: F401,E402
-    embed_kernel, conv_periodic, corr_periodic, conv_zero, corr_zero, rl_general,
+    embed_kernel, conv_periodic, corr_periodic, conv_zero, corr_zero, conv_zero_at, rl_general,
 )

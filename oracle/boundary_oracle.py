@@ -133,6 +133,25 @@ def corr_zero_direct(y, h) -> np.ndarray:
     return out
 
 
+def conv_zero_at(x, h, points) -> np.ndarray:
+    """conv_zero(x, h)[m] for each voxel m in ``points``, by the direct sum over the
+    PSF entries whose shifted voxel lies inside the volume."""
+    x = np.asarray(x, dtype=np.float64)
+    hn = _normalised(h)
+    c = psf_centre(hn.shape)
+    out = []
+    for m in points:
+        idx, keep = [], []
+        for ax in range(3):
+            j = np.arange(hn.shape[ax])
+            src = m[ax] - (j - c[ax])
+            ok = (src >= 0) & (src < x.shape[ax])
+            idx.append(src[ok])
+            keep.append(j[ok])
+        out.append(float(np.sum(hn[np.ix_(*keep)] * x[np.ix_(*idx)])))
+    return np.array(out)
+
+
 def operators(h, boundary: str):
     """(H, H^T) as functions of a volume, for boundary 'periodic' or 'zero'."""
     if boundary == "periodic":

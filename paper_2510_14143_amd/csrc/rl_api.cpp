@@ -30,7 +30,7 @@ namespace {
 
 constexpr uint64_t kMagic = 0x31504c4d494c52ull;  // live plan
 constexpr uint64_t kDead = 0xdeadbeefdeadbeefull;
-constexpr int64_t kMaxNx = 2048;
+constexpr int64_t kMaxNx = 4096;
 constexpr int64_t kMaxNyz = 1024;
 constexpr size_t kMaxLds = 65536;        // X pass work-group LDS budget
 constexpr size_t kMaxPencilLds = 163840;  // gfx950: 160 KB per work-group
@@ -73,34 +73,86 @@ rl_status hip_fail(hipError_t e, const char* what) {
 
 bool is_pow2(int64_t v) { return v >= 1 && (v & (v - 1)) == 0; }
 
-// Lengths handled by the radix set {16, 8, 4, 2} plus one final radix-3 stage.
-bool length_ok(int64_t L) {
-  if (L < 1) return false;
-  if (L % 3 == 0) L /= 3;
-  return is_pow2(L);
+// A thread holds E elements of its transform, E carrying every odd factor of the
+// length, so the odd part of a length is limited to what fits in E <= 30:
+// lengths o * 2^a with o in {1, 3, 5, 7, 9, 15} (radices 16, 8, 4, 2, 3, 5, 7).
+int64_t odd_part(int64_t v) {
+  while (v > 0 && v % 2 == 0) v /= 2;
+  return v;
 }
 
 int64_t pow2_part(int64_t v) { return v & -v; }
 
+bool length_ok(int64_t L) {
+  if (L < 1) return false;
+  const int64_t o = odd_part(L);
+  return o == 1 || o == 3 || o == 5 || o == 7 || o == 9 || o == 15;
+}
+
+// Elements-per-thread values the kernels are built for (ascending).
+constexpr int kE[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 14, 15, 16, 18, 20, 24, 30};
+
+// Radices of the schedule for length L with E elements per thread: the largest
+// power-of-two radix dividing E first, then the power-of-two remainder, then the
+// odd radices 7, 5, 3 (3 last).
+std::vector<int> radices(int64_t L, int E) {
+  int64_t n = L;
+  std::vector<int> odd;
+  for (int r : {7, 5, 3})
+    while (n % r == 0) {
+      n /= r;
+      odd.push_back(r);
+    }
+  int big = 1;
+  for (int r : {16, 8, 4, 2})
+    if (E % r == 0) {
+      big = r;
+      break;
+    }
+  std::vector<int> rads;
+  while (n > 1) {
+    int r = big;
+    while (r > 1 && n % r) r /= 2;
+    if (r == 1) break;  // E without a factor 2 for an even length: rejected by e_ok
+    rads.push_back(r);
+    n /= r;
+  }
+  for (int r : odd) rads.push_back(r);
+  return rads;
+}
+
 // A caller-chosen E for length L: divides L into a power-of-two thread count
-// <= max_p, carries every factor 3 of L, and leaves radices the schedule can use.
+// <= max_p, carries every odd factor of L, and leaves radices the schedule can use.
 bool e_ok(int64_t L, int E, int64_t max_p) {
-  static const int kE[] = {1, 2, 3, 4, 6, 8, 12, 16, 24};
   bool known = false;
   for (int k : kE) known = known || (k == E);
   if (!known || L % E != 0) return false;
   const int64_t P = L / E;
   if (!is_pow2(P) || P > max_p) return false;
-  if (L % 3 == 0 && E % 3 != 0) return false;
-  if (E % 3 == 0 && L % 3 != 0) return false;
+  if (odd_part(E) != odd_part(L)) return false;
   const int64_t l2 = pow2_part(L);
-  return l2 == 1 || pow2_part(E) >= 2;
+  if (l2 != 1 && pow2_part(E) < 2) return false;
+  return radices(L, E).size() <= (size_t)rlmi::kMaxStages;
+}
+
+// Largest E = odd part * 2^j of L with E <= cap (and at least one factor 2 when L
+// is even); 0 if none.
+int e_with_cap(int64_t L, int cap) {
+  const int64_t o = odd_part(L);
+  int best = 0;
+  for (int E : kE)
+    if (E <= cap && E > best && odd_part(E) == o && L % E == 0 &&
+        (pow2_part(L) == 1 || pow2_part(E) >= 2) &&
+        radices(L, E).size() <= (size_t)rlmi::kMaxStages)
+      best = E;
+  return best;
 }
 
 int pick_e(int64_t L) {
   if (L == 1) return 1;
   if (is_pow2(L)) return (int)(L < 16 ? L : 16);
-  return (int)(L < 24 ? L : 24);  // 3 * 2^a
+  const int e = e_with_cap(L, 24);
+  return e > 0 ? e : e_with_cap(L, 30);
 }
 
 // X pass: few elements per thread so that one row fills (up to) a wavefront;
@@ -110,8 +162,16 @@ int pick_e_x(int64_t M) {
     if (M <= 4) return (int)M;
     return (int)(M / 4 <= 64 ? 4 : M / 64);
   }
-  if (M <= 12) return (int)M;           // 3, 6, 12
-  return (int)(M / 12 <= 64 ? 12 : 24);  // 3 * 2^a
+  // the smallest valid E >= 2 * odd part with at most 64 threads per row, else
+  // the largest valid E
+  const int64_t o = odd_part(M);
+  int best_ge = 0, best_any = 0;
+  for (int E : kE)
+    if (e_ok(M, E, 64)) {
+      if (E >= 2 * o && best_ge == 0) best_ge = E;
+      best_any = E;
+    }
+  return best_ge > 0 ? best_ge : best_any > 0 ? best_any : pick_e(M);
 }
 
 // Split precision: 16 elements per thread (radix-16 stages) when the length is a
@@ -126,31 +186,13 @@ int pick_e_y(int64_t L) {
   return pick_e(L);
 }
 
-// Radix schedule: the largest power-of-two radix dividing E first, then the
-// power-of-two remainder, then radix 3 last (its stage needs no index wrap).
+// Radix schedule of radices(L, E); ns = 0 if it has more than kMaxStages stages
+// (callers validate E with e_ok first).
 Sched make_sched(int64_t L, int E, int table_stride) {
   Sched sc;
   std::memset(&sc, 0, sizeof(sc));
-  int64_t n = L;
-  int threes = 0;
-  while (n % 3 == 0) {
-    n /= 3;
-    ++threes;
-  }
-  int big = 1;
-  for (int r : {16, 8, 4, 2})
-    if (E % r == 0) {
-      big = r;
-      break;
-    }
-  std::vector<int> rads;
-  while (n > 1) {
-    int r = big;
-    while (r > 1 && n % r) r /= 2;
-    rads.push_back(r);
-    n /= r;
-  }
-  for (int t = 0; t < threes; ++t) rads.push_back(3);
+  const std::vector<int> rads = radices(L, E);
+  if (rads.size() > (size_t)rlmi::kMaxStages) return sc;
   int64_t p = 1;
   sc.ns = (int)rads.size();
   for (int s = 0; s < sc.ns; ++s) {
@@ -261,12 +303,19 @@ rl_status check_shape(const int64_t* shape) {
   const int64_t nz = shape[0], ny = shape[1], nx = shape[2];
   if (nx % 2 != 0 || nx < 4)
     return fail(RL_E_UNSUPPORTED, "nx must be even and >= 4");
-  if (!length_ok(nx / 2) || nx > kMaxNx)
-    return fail(RL_E_UNSUPPORTED, "nx must be 2^a or 3*2^a and <= 2048");
-  if (!length_ok(ny) || ny > kMaxNyz)
-    return fail(RL_E_UNSUPPORTED, "ny must be 1, 2^a or 3*2^a and <= 1024");
-  if (!length_ok(nz) || nz > kMaxNyz)
-    return fail(RL_E_UNSUPPORTED, "nz must be 1, 2^a or 3*2^a and <= 1024");
+  auto has_e = [](int64_t L, int64_t max_p) {
+    for (int E : kE)
+      if (e_ok(L, E, max_p)) return true;
+    return false;
+  };
+  static const char* kLens = "o * 2^a with o in {1, 3, 5, 7, 9, 15}";
+  if (!length_ok(nx / 2) || nx > kMaxNx || !has_e(nx / 2, 64))
+    return fail(RL_E_UNSUPPORTED, std::string("nx/2 must be ") + kLens +
+                                      ", nx <= 4096, split over at most 64 threads");
+  if (!length_ok(ny) || ny > kMaxNyz || !has_e(ny, 1024))
+    return fail(RL_E_UNSUPPORTED, std::string("ny must be ") + kLens + " and <= 1024");
+  if (!length_ok(nz) || nz > kMaxNyz || !has_e(nz, 1024))
+    return fail(RL_E_UNSUPPORTED, std::string("nz must be ") + kLens + " and <= 1024");
   return RL_OK;
 }
 
@@ -602,8 +651,12 @@ bool configure_z(rl_plan p, int z_e, int z_txb, int z_swap) {
 }
 
 bool configure(rl_plan p, const Choice& c) {
-  return configure_x(p, c.x_e) && configure_y(p, c.y_e, c.y_txb) &&
-         configure_z(p, c.z_e, c.z_txb, c.z_swap);
+  if (!configure_x(p, c.x_e) || !configure_y(p, c.y_e, c.y_txb) ||
+      !configure_z(p, c.z_e, c.z_txb, c.z_swap))
+    return false;
+  // every transform needs an element count the kernels and the schedule support
+  return e_ok(p->M, p->axx.E, 64) && e_ok(p->ny, p->py.ax.E, 1 << 20) &&
+         e_ok(p->nz, p->pz.ax.E, 1 << 20);
 }
 
 // --- autotuner ---------------------------------------------------------------
@@ -681,7 +734,7 @@ rl_status time_ms(rl_plan p, F fn, float* ms) {
 std::vector<int> e_candidates(int64_t L, int64_t max_p, int precision) {
   std::vector<int> out;
   if (precision != RL_PRECISION_FP32 && split_e(L, max_p) == 16) return {16};
-  for (int e : {4, 8, 16, 2, 6, 12, 24, 3})
+  for (int e : {4, 8, 16, 2, 6, 12, 24, 3, 20, 10, 5, 14, 7, 18, 9, 30, 15})
     if (e_ok(L, e, max_p)) out.push_back(e);
   return out;
 }
@@ -805,14 +858,30 @@ struct Geometry {
   int boundary;
 };
 
-// Smallest supported transform length >= need (1, 2^a or 3 * 2^a).
-int64_t next_len(int64_t need) {
-  // candidates in increasing order: 1, 2, 3, 4, 6, 8, 12, ... (b, then 3b/2 < 2b)
-  for (int64_t b = 1; b <= (int64_t)1 << 40; b <<= 1) {
-    if (b >= need) return b;
-    if (b >= 2 && 3 * b / 2 >= need) return 3 * b / 2;
-  }
-  return -1;
+// Transform length >= need that `fits` accepts (a supported length o * 2^a with
+// an element count for it) of least estimated cost L * w(o); -1 if none below
+// 2^31.  w is the time per element of a pass relative to power-of-two lengths,
+// measured on MI355X: odd parts 3 and 5 cost little more, 9 and 15 (whose
+// element counts leave only radix-2 stages or long registers) about twice.
+template <typename F>
+int64_t next_len(int64_t need, F fits) {
+  static const struct {
+    int64_t o;
+    double w;
+  } kCost[] = {{1, 1.0}, {3, 1.05}, {5, 1.2}, {7, 1.6}, {9, 2.0}, {15, 2.2}};
+  int64_t best = -1;
+  double best_cost = 0.0;
+  for (const auto& c : kCost)
+    for (int64_t L = c.o; L < ((int64_t)1 << 31); L *= 2)
+      if (L >= need && fits(L)) {
+        const double cost = (double)L * c.w;
+        if (best < 0 || cost < best_cost) {
+          best = L;
+          best_cost = cost;
+        }
+        break;
+      }
+  return best;
 }
 
 rl_status make_geometry(const int64_t shape[3], const rl_options* opt, int boundary,
@@ -834,9 +903,23 @@ rl_status make_geometry(const int64_t shape[3], const rl_options* opt, int bound
     for (int i = 0; i < 3; ++i) g->grid[i] = shape[i];
     return RL_OK;
   }
-  for (int i = 0; i < 2; ++i) g->grid[i] = next_len(g->vol[i] + g->psf[i] / 2);
-  const int64_t half = next_len((g->vol[2] + g->psf[2] / 2 + 1) / 2);
-  g->grid[2] = 2 * (half < 2 ? 2 : half);
+  auto has_e = [](int64_t L, int64_t max_p) {
+    for (int E : kE)
+      if (e_ok(L, E, max_p)) return true;
+    return false;
+  };
+  for (int i = 0; i < 2; ++i)
+    g->grid[i] = next_len(g->vol[i] + g->psf[i] / 2,
+                          [&](int64_t L) { return L <= kMaxNyz && has_e(L, 1024); });
+  const int64_t need_x = g->vol[2] + g->psf[2] / 2;
+  const int64_t half = next_len((need_x + 1) / 2 < 2 ? 2 : (need_x + 1) / 2,
+                                [&](int64_t m) { return 2 * m <= kMaxNx && has_e(m, 64); });
+  g->grid[2] = half > 0 ? 2 * half : -1;
+  for (int i = 0; i < 3; ++i)
+    if (g->grid[i] < 1)
+      return fail(RL_E_UNSUPPORTED, "zero boundary: no supported padded transform length for "
+                                    "dimension " + std::to_string(i) + " (needs " +
+                                        std::to_string(g->vol[i] + g->psf[i] / 2) + ")");
   rl_status st = check_shape(g->grid);
   if (st != RL_OK)
     return fail(st, "zero boundary: the padded transform grid " + std::to_string(g->grid[0]) +

@@ -128,6 +128,81 @@ struct Dft<4, S> {
   }
 };
 
+// cos and sin of 2 pi k / R (R = 5, 7), rounded from FP64 values.
+template <int R>
+__device__ __forceinline__ constexpr float cos_2pi(int k);
+template <int R>
+__device__ __forceinline__ constexpr float sin_2pi(int k);
+template <>
+__device__ __forceinline__ constexpr float cos_2pi<5>(int k) {
+  return k == 0 ? 1.f : (k == 1 || k == 4) ? 0.30901699437494742f : -0.80901699437494742f;
+}
+template <>
+__device__ __forceinline__ constexpr float sin_2pi<5>(int k) {
+  return k == 0 ? 0.f
+         : k == 1 ? 0.95105651629515357f
+         : k == 2 ? 0.58778525229247313f
+         : k == 3 ? -0.58778525229247313f
+                  : -0.95105651629515357f;
+}
+template <>
+__device__ __forceinline__ constexpr float cos_2pi<7>(int k) {
+  return k == 0 ? 1.f
+         : (k == 1 || k == 6) ? 0.62348980185873353f
+         : (k == 2 || k == 5) ? -0.22252093395631440f
+                              : -0.90096886790241913f;
+}
+template <>
+__device__ __forceinline__ constexpr float sin_2pi<7>(int k) {
+  return k == 0 ? 0.f
+         : k == 1 ? 0.78183148246802981f
+         : k == 2 ? 0.97492791218182361f
+         : k == 3 ? 0.43388373911755812f
+         : k == 4 ? -0.43388373911755812f
+         : k == 5 ? -0.97492791218182361f
+                  : -0.78183148246802981f;
+}
+
+// Odd prime radix R by the pair symmetry of the DFT: with t_k = x_k + x_{R-k} and
+// d_k = x_k - x_{R-k} (k = 1 .. (R-1)/2), X_m = x_0 + sum_k cos(2 pi mk/R) t_k
+// -/+ i sum_k sin(2 pi mk/R) d_k and X_{R-m} the same with the sign flipped
+// (upper sign forward, S = -1).
+template <int R, int S>
+struct DftOdd {
+  __device__ __forceinline__ static void run(float2* x) {
+    constexpr int H = (R - 1) / 2;
+    float2 t[H], d[H];
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+      t[k - 1] = cadd(x[k], x[R - k]);
+      d[k - 1] = csub(x[k], x[R - k]);
+    }
+    const float2 x0 = x[0];
+    float2 sum = x0;
+#pragma unroll
+    for (int k = 0; k < H; ++k) sum = cadd(sum, t[k]);
+    x[0] = sum;
+#pragma unroll
+    for (int m = 1; m <= H; ++m) {
+      float2 a = x0, b = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int k = 1; k <= H; ++k) {
+        const float c = cos_2pi<R>((m * k) % R), sn = sin_2pi<R>((m * k) % R);
+        a = make_float2(a.x + c * t[k - 1].x, a.y + c * t[k - 1].y);
+        b = make_float2(b.x + sn * d[k - 1].x, b.y + sn * d[k - 1].y);
+      }
+      const float2 ib = make_float2(-b.y, b.x);  // i * b
+      x[m] = (S < 0) ? csub(a, ib) : cadd(a, ib);
+      x[R - m] = (S < 0) ? cadd(a, ib) : csub(a, ib);
+    }
+  }
+};
+
+template <int S>
+struct Dft<5, S> : DftOdd<5, S> {};
+template <int S>
+struct Dft<7, S> : DftOdd<7, S> {};
+
 // Radix-2 decimation in time: split into even and odd halves.
 template <int R, int S>
 struct Dft {
@@ -303,7 +378,13 @@ __device__ __forceinline__ void stage(float2 (&v)[E], int i, int P, int p, int t
 #pragma unroll
   for (int q = 0; q < V; ++q) {
     const int b = i + q * P;
-    const int k = last ? b : (b & (p - 1));
+    // position inside the current span p: the schedule puts every odd radix after
+    // all power-of-two ones, so p is a power of two before any power-of-two stage
+    int k;
+    if constexpr ((R & (R - 1)) == 0)
+      k = last ? b : (b & (p - 1));
+    else
+      k = last ? b : (b % p);
     float2 y[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) y[j] = v[q + j * V];
@@ -357,6 +438,12 @@ __device__ __forceinline__ void fft(float2 (&v)[E], const Sched& sc, int i, int 
         break;
       case 3:
         if constexpr (E % 3 == 0) stage<E, 3, S, PAD>(v, i, P, p, tm, last, tw, lds, ls, lo);
+        break;
+      case 5:
+        if constexpr (E % 5 == 0) stage<E, 5, S, PAD>(v, i, P, p, tm, last, tw, lds, ls, lo);
+        break;
+      case 7:
+        if constexpr (E % 7 == 0) stage<E, 7, S, PAD>(v, i, P, p, tm, last, tw, lds, ls, lo);
         break;
       default:
         break;
@@ -827,8 +914,6 @@ __global__ void __launch_bounds__(256) k_psf_stats(const float* __restrict__ h, 
   }
 }
 
-// out[z][y][x] (rows `out_row_stride` floats apart) = h[(z+cz)%nz][(y+cy)%ny][(x+cx)%nx] * scale,
-// with the product taken in FP64: moves the PSF centre floor(n/2) to index 0.
 // PSF index along one axis that lands on grid index o once the PSF (length p,
 // centre p/2) is centred on voxel 0 of a periodic grid of length n >= p:
 // offsets 0 .. p-1-c sit at o = offset, offsets -c .. -1 at o = n + offset.
@@ -840,6 +925,9 @@ __device__ __forceinline__ int psf_src(int o, int n, int p) {
   return -1;
 }
 
+// out[z][y][x] (rows `out_row_stride` floats apart) = the PSF entry that lands on
+// grid voxel (z, y, x) times `scale` (product in FP64), else 0: the PSF with its
+// centre floor(p/2) moved to voxel 0.
 __global__ void k_psf_prep(const float* __restrict__ h, float* __restrict__ out, int nz, int ny,
                            int nx, int pz, int py, int px, long long out_row_stride,
                            double scale) {
@@ -932,7 +1020,8 @@ static hipError_t pencil_e(int E, int prec, dim3 g, dim3 b, size_t lds, hipStrea
 #define RL_CASE(EV) \
   case EV: return pencil_one<MODE, 512, EV>(g, b, lds, s, data, otf, tw, a, sc, launch, ev0, ev1);
     RL_CASE(1) RL_CASE(2) RL_CASE(3) RL_CASE(4) RL_CASE(6) RL_CASE(8) RL_CASE(12) RL_CASE(16)
-    RL_CASE(24)
+    RL_CASE(24) RL_CASE(5) RL_CASE(10) RL_CASE(20) RL_CASE(7) RL_CASE(14) RL_CASE(9) RL_CASE(18)
+    RL_CASE(15) RL_CASE(30)
 #undef RL_CASE
     default:
       return hipErrorInvalidValue;
@@ -987,7 +1076,8 @@ static hipError_t xrow_e(int E, int prec, dim3 g, dim3 b, size_t lds, hipStream_
     RL_LAUNCH((k_xrow<EV, MODE>), g, b, lds, s, ev0, ev1, a, sc, tw);    \
     break;
     RL_CASE(1) RL_CASE(2) RL_CASE(3) RL_CASE(4) RL_CASE(6) RL_CASE(8) RL_CASE(12) RL_CASE(16)
-    RL_CASE(24)
+    RL_CASE(24) RL_CASE(5) RL_CASE(10) RL_CASE(20) RL_CASE(7) RL_CASE(14) RL_CASE(9) RL_CASE(18)
+    RL_CASE(15) RL_CASE(30)
 #undef RL_CASE
     default:
       return hipErrorInvalidValue;

@@ -37,10 +37,13 @@ def _create(shape, psf_ptr=4096, boundary=0):
     ((8, -1, 8), rl.RL_E_INVALID),
     ((8, 8, 7), rl.RL_E_UNSUPPORTED),      # odd nx
     ((8, 8, 2), rl.RL_E_UNSUPPORTED),      # nx < 4
-    ((8, 8, 20), rl.RL_E_UNSUPPORTED),     # radix 5
-    ((8, 10, 8), rl.RL_E_UNSUPPORTED),
-    ((9, 8, 8), rl.RL_E_UNSUPPORTED),      # two factors of 3
-    ((8, 8, 4096), rl.RL_E_UNSUPPORTED),   # above the nx limit
+    ((8, 8, 22), rl.RL_E_UNSUPPORTED),     # radix 11
+    ((8, 26, 8), rl.RL_E_UNSUPPORTED),     # radix 13
+    ((27, 8, 8), rl.RL_E_UNSUPPORTED),     # three factors of 3
+    ((8, 25, 8), rl.RL_E_UNSUPPORTED),     # two factors of 5
+    ((8, 8, 70), rl.RL_E_UNSUPPORTED),     # nx/2 = 35 = 5 * 7
+    ((8, 8, 8192), rl.RL_E_UNSUPPORTED),   # above the nx limit
+    ((8, 8, 4096), rl.RL_E_UNSUPPORTED),   # nx/2 = 2048 needs 32 elements per thread
     ((2048, 8, 8), rl.RL_E_UNSUPPORTED),   # above the nz limit
 ])
 def test_bad_shapes_rejected(shape, code):
@@ -58,8 +61,8 @@ def test_bad_arguments_rejected():
     assert L.rl_plan_create(sh, None, 0, ctypes.byref(out)) == rl.RL_E_INVALID
     assert L.rl_plan_create(sh, ctypes.c_void_p(4100), 0, ctypes.byref(out)) == rl.RL_E_INVALID
     assert L.rl_plan_create(sh, ctypes.c_void_p(4096), 7, ctypes.byref(out)) == rl.RL_E_INVALID
-    # zero boundary: the padded grid must be supported (nx 1500 pads beyond 2048)
-    big = (ctypes.c_int64 * 3)(8, 8, 1500)
+    # zero boundary: the padded grid must be supported (nx 3000 pads beyond 4096)
+    big = (ctypes.c_int64 * 3)(8, 8, 3000)
     assert L.rl_plan_create(big, ctypes.c_void_p(4096), rl.RL_BOUNDARY_ZERO,
                             ctypes.byref(out)) == rl.RL_E_UNSUPPORTED
     assert "zero boundary" in rl.rl_last_error()

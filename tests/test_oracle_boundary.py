@@ -107,6 +107,16 @@ def test_small_psf_periodic_equals_padded_same_shape_psf(shape, pshape):
 
 
 @pytest.mark.parametrize("shape,pshape", SHAPES)
+def test_pointwise_zero_conv(shape, pshape):
+    x = rng(15).uniform(0, 5, size=shape)
+    h = rand_psf(pshape, 16)
+    full = _scipy_conv_zero(x, h)
+    pts = [tuple(int(v) for v in rng(17 + k).integers(0, shape)) for k in range(6)]
+    pts += [(0, 0, 0), tuple(n - 1 for n in shape)]
+    assert close(bo.conv_zero_at(x, h, pts), np.array([full[p] for p in pts]))
+
+
+@pytest.mark.parametrize("shape,pshape", SHAPES)
 def test_adjoint_and_pad_independence(shape, pshape):
     x = rng(7).uniform(0, 5, size=shape)
     y = rng(8).uniform(0, 5, size=shape)
