@@ -8,3 +8,4 @@ from .accel_oracle import extrapolate, rl_accel  # noqa: F401,E402
 from .boundary_oracle import (  # noqa: F401,E402
     embed_kernel, conv_periodic, corr_periodic, conv_zero, corr_zero, conv_zero_at, rl_general,
 )
+from .stop_oracle import psnr_si, rel_change, rl_stop  # noqa: F401,E402
