@@ -335,6 +335,49 @@ def run_zero_boundary(torch, rl, synth, steps: int, cfg: int = 1):
             "flux_drift": float(np.max(np.abs(flux - total)) / total)}
 
 
+def run_stop(torch, rl, synth, steps: int, cfg: int = 1):
+    """Metric-guided stopping on the 128x256x256 volume: iterations chosen by each
+    rule (at most the configuration's 100) and the wall-clock time of the call,
+    against 100 fixed iterations; the per-iteration cost of carrying the metric."""
+    c = synth.make_config(cfg)
+    n_max = c["n_iter"]
+    dev = torch.device("cuda:0")
+    psf = torch.from_numpy(c["psf"]).to(dev)
+    d = torch.from_numpy(c["d"]).to(dev)
+    u0 = torch.from_numpy(c["u0"]).to(dev)
+    truth = torch.from_numpy(c["truth"]).to(dev)
+    nvox = int(np.prod(c["shape"]))
+    plan = rl.Plan(psf, autotune=True)
+    u = u0.clone()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            u.copy_(u0)
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    out = {"workload": "rl_stop_128x256x256", "max_iter": n_max,
+           "fixed_ms": round(timed(lambda: plan.iterate(d, u, n_max)), 3)}
+    rules = {"loglik": (1e-4, None), "change": (2e-3, None), "psnr": (0.01, truth)}
+    for name, (tau, ref) in rules.items():
+        ms = timed(lambda: plan.iterate_until(d, u, n_max, name, tau, reference=ref))
+        n, hist = plan.stop()
+        # per-iteration cost of the metric: the full 100 iterations with a rule that never fires
+        ms_all = timed(lambda: plan.iterate_until(d, u, n_max, name, -1e300, reference=ref))
+        out[name] = {"threshold": tau, "iterations": n, "ms": round(ms, 3),
+                     "last_metric": float(hist[-1]) if len(hist) else None,
+                     "metric_overhead_per_iter_pct": round(100 * (ms_all / out["fixed_ms"] - 1), 2),
+                     "value": round(nvox * n / (ms * 1e-3) / 1e9, 3) if n else None}
+    plan.close()
+    return out
+
+
 def copy_probe(torch, rl, nbytes: int = 1 << 30, reps: int = 20) -> float:
     """Plain streaming copy kernel of the library: read + write bytes per second (GB/s)."""
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
@@ -417,6 +460,7 @@ def main():
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision forms")
     ap.add_argument("--no-accel", action="store_true", help="skip the extrapolated form")
     ap.add_argument("--no-zero", action="store_true", help="skip the zero-boundary form")
+    ap.add_argument("--no-stop", action="store_true", help="skip metric-guided stopping")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the batched and single-volume paths "
@@ -458,6 +502,11 @@ def main():
         log("workload: zero boundary (128x256x256, truncated PSF)")
         zero = run_zero_boundary(torch, rl, synth, max(1, args.steps // 2))
         log(json.dumps({"zero_boundary": zero}))
+    stop = None
+    if not args.no_stop:
+        log("workload: metric-guided stopping (128x256x256)")
+        stop = run_stop(torch, rl, synth, max(1, args.steps // 2))
+        log(json.dumps({"stop": stop}))
     split = None
     if not args.no_split:
         log("workload: split-precision forms, 256x512x512, 50 it")
@@ -504,6 +553,7 @@ def main():
         "split": split,
         "accel": accel,
         "zero_boundary": zero,
+        "stop": stop,
         "copy_probe_gbs": round(copy_gbs, 1),
     }
     if rank == 0:

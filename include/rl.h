@@ -188,6 +188,54 @@ rl_status rl_plan_create_batch(int count, const int64_t* shapes, const float* co
 rl_status rl_iterate_batch(rl_plan p, const float* const* observed, float* const* estimate,
                            int n_iter);
 
+/*
+ * Metric-guided automatic stopping (paper §4.3: the iteration count is chosen by
+ * monitoring an image-quality metric between consecutive iterations and stopping
+ * once its improvement falls below a configurable threshold).
+ *   RL_STOP_LOGLIK: l_k = sum over q > 1e-12 of (d log q - q), q = H u_k, the
+ *     Poisson log-likelihood RL maximises, evaluated for the estimate entering
+ *     iteration k (computed inside that iteration's ratio pass).  Stops at
+ *     iteration k >= 1 when (l_k - l_{k-1}) / |l_k| < threshold; iteration k is
+ *     then not carried out (k iterations done).  Values are FP64 sums of FP32
+ *     blurs: improvements below ~1e-7 are rounding.
+ *   RL_STOP_CHANGE: m_k = ||u_{k+1} - u_k|| / ||u_k|| after iteration k; stops
+ *     when m_k < threshold (k + 1 iterations done).
+ *   RL_STOP_PSNR: scale-invariant PSNR of u_{k+1} against `reference` (device,
+ *     the volume's shape): 20 log10(max g - min g) - 10 log10(mean squared
+ *     residual of the least-squares affine fit of u to g); stops at k >= 1 when
+ *     psnr_k - psnr_{k-1} < threshold (dB; k + 1 iterations done).
+ * No stop happens before min_iter iterations are done.  The metric is
+ * accumulated in FP64 inside the passes (no extra pass over the volume; PSNR
+ * reads the reference, 4 bytes per voxel per iteration).
+ */
+typedef enum { RL_STOP_LOGLIK = 1, RL_STOP_CHANGE = 2, RL_STOP_PSNR = 3 } rl_stop_metric;
+
+typedef struct {
+  int metric;              /* rl_stop_metric */
+  double threshold;        /* finite */
+  int min_iter;            /* >= 0 */
+  const float* reference;  /* RL_STOP_PSNR only */
+} rl_stop_rule;
+
+/*
+ * At most max_iter iterations of rl_iterate on a single-volume plan without
+ * extrapolation (else RL_E_UNSUPPORTED), ended early by `rule`.  The whole call
+ * is enqueued at once; a one-work-group kernel evaluates the rule after each
+ * check and sets a device flag, after which every remaining launch of the call
+ * returns at once, so no host synchronisation is needed.  Asynchronous like
+ * rl_iterate.  rl_plan_get_flux then returns the flux of the iterations done.
+ */
+rl_status rl_iterate_stop(rl_plan p, const float* observed, float* estimate, int max_iter,
+                          const rl_stop_rule* rule);
+
+/*
+ * After rl_iterate_stop (else RL_E_INVALID): iterations carried out in
+ * *n_done, and the metric value of every check in history[0 .. min(cap, n) - 1]
+ * with n in *n_history (LOGLIK: l_0 .. l_k; CHANGE and PSNR: one value per
+ * iteration done).  Synchronises the plan's stream.
+ */
+rl_status rl_plan_get_stop(rl_plan p, int* n_done, double* history, int cap, int* n_history);
+
 /* Release the plan and its device memory (waits for its pending work). NULL is a no-op. */
 void rl_plan_destroy(rl_plan p);
 

@@ -263,6 +263,13 @@ struct rl_plan_s {
   float* alpha32 = nullptr;       // alpha per iteration (flux_cap + 1 entries)
   double* alpha64 = nullptr;
   double* acc_partials = nullptr; // [2][X work-groups]
+  // metric-guided stopping (single-volume plans)
+  int* stop = nullptr;            // [0] stopped, [1] iterations carried out, [2] metric entries
+  double* met_partials = nullptr; // [kMetRows][X work-groups]
+  double* mhist = nullptr;        // metric per check (flux_cap + 1 entries)
+  bool stop_call = false;         // the last iterate call used a stop rule
+  int stop_max = 0;               // its max_iter
+  const int* active_stop = nullptr;  // passed to every launch while a stop call is enqueued
   // batched volumes of this shape (a class of a batch plan); 1 for a single plan
   int count = 1;
   const float** d_tab = nullptr;  // device tables of per-volume pointers (count each)
@@ -377,6 +384,9 @@ void release(rl_plan p) {
   (void)hipFree(p->alpha32);
   (void)hipFree(p->alpha64);
   (void)hipFree(p->acc_partials);
+  (void)hipFree(p->stop);
+  (void)hipFree(p->met_partials);
+  (void)hipFree(p->mhist);
   for (rl_plan c : p->classes) release(c);
   if (p->graph_full) (void)hipGraphExecDestroy(p->graph_full);
   if (p->graph_last) (void)hipGraphExecDestroy(p->graph_last);
@@ -513,6 +523,7 @@ rl_status run_pencil(rl_plan p, const Pencil& pc, int mode, float2* data, const 
   if (lout > 0) args.lout = lout;
   if (outer > 0) (args.swap ? grid.x : grid.y) = (unsigned)outer;
   args.vstride = (long long)p->spec_elems;
+  args.stop = p->active_stop;
   hipError_t e = rlmi::launch_pencil(mode, pc.ax.E, p->precision, grid, pc.block, pc.lds,
                                      p->stream, data, p->otf, tw, args, pc.ax.sc, ev0, ev1);
   if (e != hipSuccess) return hip_fail(e, "pencil pass launch");
@@ -540,6 +551,7 @@ XArgs base_xargs(rl_plan p, float2* spec) {
   a.RS = p->x_rs;
   a.nrows = (int)x_rows(p);
   a.nvol = p->count;
+  a.stop = p->active_stop;
   a.vstride = (long long)p->spec_elems;
   return a;
 }
@@ -1017,6 +1029,15 @@ rl_status build_class(const Geometry& geo, int count, const float* const* psfs, 
     release(p);
     return st;
   }
+  if (count == 1 &&
+      ((e = hipMalloc(&p->stop, 4 * sizeof(int))) != hipSuccess ||
+       (e = hipMalloc(&p->met_partials, rlmi::kMetRows * (size_t)p->nrows * sizeof(double))) !=
+           hipSuccess ||
+       (e = hipMalloc(&p->mhist, (size_t)(p->flux_cap + 1) * sizeof(double))) != hipSuccess)) {
+    st = hip_fail(e, "hipMalloc(stopping state)");
+    release(p);
+    return st;
+  }
   if (p->accel != RL_ACCEL_NONE) {
     const size_t vb = (size_t)p->vnvox * sizeof(float);
     if ((e = hipMalloc(&p->hstep, vb)) != hipSuccess ||
@@ -1157,6 +1178,14 @@ rl_status ensure_flux_capacity(rl_plan p, int n_iter, bool* grew) {
     (void)hipFree(na32);
     return hip_fail(e, "hipMalloc(alpha)");
   }
+  double* nh = nullptr;
+  if (p->mhist && (e = hipMalloc(&nh, (size_t)(n_iter + 1) * sizeof(double))) != hipSuccess) {
+    (void)hipFree(nf);
+    (void)hipFree(np);
+    (void)hipFree(na32);
+    (void)hipFree(na64);
+    return hip_fail(e, "hipMalloc(metric history)");
+  }
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   else (void)hipDeviceSynchronize();
   (void)hipFree(p->flux);
@@ -1168,6 +1197,10 @@ rl_status ensure_flux_capacity(rl_plan p, int n_iter, bool* grew) {
     (void)hipFree(p->alpha64);
     p->alpha32 = na32;
     p->alpha64 = na64;
+  }
+  if (nh) {
+    (void)hipFree(p->mhist);
+    p->mhist = nh;
   }
   p->n_partials = nparts;
   p->flux_cap = n_iter;
@@ -1274,6 +1307,7 @@ rl_status iterate_impl(rl_plan p, const float* observed, float* estimate, int n_
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   if ((st = ensure_flux_capacity(p, n_iter, nullptr)) != RL_OK) return st;
   p->flux_count = n_iter;
+  p->stop_call = false;
   if (p->accel != RL_ACCEL_NONE) {
     if ((st = enqueue_accel_predict(p, estimate, 0)) != RL_OK) return st;
     for (int it = 0; it < n_iter; ++it)
@@ -1286,6 +1320,94 @@ rl_status iterate_impl(rl_plan p, const float* observed, float* estimate, int n_
     if ((st = enqueue_iteration(p, observed, estimate, it, nullptr, it + 1 < n_iter)) != RL_OK)
       return st;
   return enqueue_flux_reduce(p, n_iter, p->stream);
+}
+
+// Metric-guided stopping: every launch of the call reads the plan's stop flag
+// and does nothing once the metric kernel has set it, so the whole call is
+// enqueued at once and ends early on the device without a host round trip.
+rl_status iterate_stop_impl(rl_plan p, const float* observed, float* estimate, int max_iter,
+                            const rl_stop_rule* rule) {
+  rl_status st = check_plan(p);
+  if (st != RL_OK) return st;
+  if (p->is_batch || !p->stop) return fail(RL_E_UNSUPPORTED, "stop rules need a single-volume plan");
+  if (p->accel != RL_ACCEL_NONE)
+    return fail(RL_E_UNSUPPORTED, "stop rules are not available with extrapolation");
+  if (!rule) return fail(RL_E_INVALID, "rule is NULL");
+  if (rule->metric != RL_STOP_LOGLIK && rule->metric != RL_STOP_CHANGE &&
+      rule->metric != RL_STOP_PSNR)
+    return fail(RL_E_INVALID, "unknown stop metric");
+  if (!std::isfinite(rule->threshold)) return fail(RL_E_INVALID, "threshold must be finite");
+  if (rule->min_iter < 0) return fail(RL_E_INVALID, "min_iter must be >= 0");
+  if (max_iter < 0) return fail(RL_E_INVALID, "max_iter must be >= 0");
+  const size_t bytes = (size_t)p->vnvox * sizeof(float);
+  int dev = p->device;
+  if ((st = check_dev_ptr(observed, bytes, &dev, "observed")) != RL_OK) return st;
+  if ((st = check_dev_ptr(estimate, bytes, &dev, "estimate")) != RL_OK) return st;
+  if (rule->metric == RL_STOP_PSNR &&
+      (st = check_dev_ptr(rule->reference, bytes, &dev, "reference")) != RL_OK)
+    return st;
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if ((st = ensure_flux_capacity(p, max_iter > 0 ? max_iter : 1, nullptr)) != RL_OK) return st;
+  if ((e = hipMemsetAsync(p->stop, 0, 4 * sizeof(int), p->stream)) != hipSuccess)
+    return hip_fail(e, "hipMemsetAsync(stop)");
+  p->flux_count = max_iter;
+  p->stop_call = true;
+  p->stop_max = max_iter;
+  if (max_iter == 0) return RL_OK;
+  const int metric = rule->metric;
+  const int groups = (int)p->x_grid.x;
+  auto decide = [&](int it) -> rl_status {
+    hipError_t me = rlmi::launch_metric(p->met_partials, groups, metric, it, rule->threshold,
+                                        rule->min_iter, (long long)p->vnvox, p->mhist, p->stop,
+                                        p->stream);
+    return me == hipSuccess ? RL_OK : hip_fail(me, "metric launch");
+  };
+  p->active_stop = p->stop;
+  st = enqueue_prologue(p, estimate);
+  for (int it = 0; it < max_iter && st == RL_OK; ++it) {
+    XArgs r = base_xargs(p, p->spec);
+    r.d = observed;
+    if (metric == RL_STOP_LOGLIK) {
+      r.metric = rlmi::MET_LOGLIK;
+      r.met_partials = p->met_partials;
+    }
+    if ((st = run_x(p, metric == RL_STOP_LOGLIK ? rlmi::XM_RATIO_LL : rlmi::XM_RATIO, r,
+                    RL_KERNEL_X_RATIO)) != RL_OK)
+      break;
+    if (metric == RL_STOP_LOGLIK && (st = decide(it)) != RL_OK) break;
+    if ((st = run_yz_filter(p, true)) != RL_OK) break;
+    XArgs w = base_xargs(p, p->spec);
+    w.u = estimate;
+    w.partials = p->partials;
+    w.iter = it;
+    w.do_fwd = it + 1 < max_iter ? 1 : 0;
+    if (metric != RL_STOP_LOGLIK) {
+      w.metric = metric == RL_STOP_CHANGE ? rlmi::MET_CHANGE : rlmi::MET_PSNR;
+      w.met_partials = p->met_partials;
+      w.ref = rule->reference;
+    }
+    if ((st = run_x(p, metric == RL_STOP_LOGLIK ? rlmi::XM_UPDATE : rlmi::XM_UPDATE_MET, w,
+                    RL_KERNEL_X_UPDATE)) != RL_OK)
+      break;
+    if (metric != RL_STOP_LOGLIK && (st = decide(it)) != RL_OK) break;
+    if (w.do_fwd && (st = run_yz_filter(p, false)) != RL_OK) break;
+  }
+  p->active_stop = nullptr;
+  if (st != RL_OK) return st;
+  return enqueue_flux_reduce(p, max_iter, p->stream);
+}
+
+// Iterations carried out by the last call with a stop rule (synchronises).
+rl_status stop_state(rl_plan p, int* n_done, int* n_hist) {
+  int h[4] = {0, 0, 0, 0};
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return hip_fail(e, "execution");
+  if ((e = hipMemcpy(h, p->stop, sizeof(h), hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(e, "hipMemcpy(stop)");
+  *n_done = h[0] ? h[1] : p->stop_max;
+  *n_hist = h[2];
+  return RL_OK;
 }
 
 // --- batched volumes -----------------------------------------------------------
@@ -1608,7 +1730,12 @@ rl_status rl_plan_get_flux(rl_plan p, double* flux, int cap, int* n_written) {
   if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return hip_fail(e, "execution");
   std::vector<double> h;
   if (!p->is_batch) {
-    const int n = p->flux_count;
+    int n = p->flux_count;
+    if (p->stop_call) {
+      int done = 0, nh = 0;
+      if ((st = stop_state(p, &done, &nh)) != RL_OK) return st;
+      n = done < n ? done : n;
+    }
     h.resize((size_t)n);
     if (n > 0 && (e = hipMemcpy(h.data(), p->flux, (size_t)n * sizeof(double),
                                 hipMemcpyDeviceToHost)) != hipSuccess)
@@ -1635,6 +1762,36 @@ rl_status rl_plan_get_flux(rl_plan p, double* flux, int cap, int* n_written) {
   for (int i = 0; i < n; ++i)
     if (!std::isfinite(h[(size_t)i]))
       return fail(RL_E_NUMERIC, "non-finite flux at entry " + std::to_string(i));
+  return RL_OK;
+}
+
+rl_status rl_iterate_stop(rl_plan p, const float* observed, float* estimate, int max_iter,
+                          const rl_stop_rule* rule) {
+  try {
+    return iterate_stop_impl(p, observed, estimate, max_iter, rule);
+  } catch (...) {
+    return fail(RL_E_INTERNAL, "unexpected exception in rl_iterate_stop");
+  }
+}
+
+rl_status rl_plan_get_stop(rl_plan p, int* n_done, double* history, int cap, int* n_history) {
+  rl_status st = check_plan(p);
+  if (st != RL_OK) return st;
+  if (!n_done || !n_history) return fail(RL_E_INVALID, "n_done or n_history is NULL");
+  if (cap < 0 || (cap > 0 && !history)) return fail(RL_E_INVALID, "history buffer is NULL");
+  if (p->is_batch || !p->stop_call)
+    return fail(RL_E_INVALID, "the plan's last call was not rl_iterate_stop");
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  int done = 0, nh = 0;
+  if ((st = stop_state(p, &done, &nh)) != RL_OK) return st;
+  std::vector<double> h((size_t)nh);
+  if (nh > 0 && (e = hipMemcpy(h.data(), p->mhist, (size_t)nh * sizeof(double),
+                               hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(e, "hipMemcpy(metric history)");
+  *n_done = done;
+  *n_history = nh;
+  for (int i = 0; i < nh && i < cap; ++i) history[i] = h[(size_t)i];
   return RL_OK;
 }
 

@@ -52,9 +52,13 @@ struct PencilArgs {
   int swap;           // 1: tile index from blockIdx.y and outer index from blockIdx.x
   int lin;            // elements e >= lin of a pencil read as zero (not loaded)
   int lout;           // elements e >= lout are not stored
+  const int* stop;    // if non-null and *stop != 0 the launch does nothing
 };
 
 enum PencilMode { PM_FWD = 0, PM_INV = 1, PM_FKI = 2, PM_FCKI = 3 };
+// Stopping metrics (values of rl_stop_metric).
+enum Metric { MET_NONE = 0, MET_LOGLIK = 1, MET_CHANGE = 2, MET_PSNR = 3 };
+constexpr int kMetRows = 7;
 // XM_PREDICT and XM_UPDATE_ACC are the two X passes of the extrapolated
 // (Biggs-Andrews) iteration: the prediction y = max(x + alpha h, 0) transformed
 // forward, and the update from y that also keeps the step h and the change g.
@@ -64,7 +68,9 @@ enum XMode {
   XM_RATIO = 2,
   XM_UPDATE = 3,
   XM_PREDICT = 4,
-  XM_UPDATE_ACC = 5
+  XM_UPDATE_ACC = 5,
+  XM_RATIO_LL = 6,   // XM_RATIO that also accumulates the log-likelihood (MET_LOGLIK)
+  XM_UPDATE_MET = 7  // XM_UPDATE that also accumulates MET_CHANGE or MET_PSNR sums
 };
 
 // Arguments of an X-row pass (contiguous axis, real <-> half spectrum).
@@ -97,7 +103,15 @@ struct XArgs {
   const float* alpha;    // alpha[k] (FP32); not read (taken as 0) when iter == 0
   double* acc_partials;  // XM_UPDATE_ACC: [2][work-group] FP64 partials of
                          // <g_k, g_{k-1}> and <g_{k-1}, g_{k-1}>
-  // Real rows (rin, rout, d, u, hstep, gchg) cover the caller's volume
+  // Metric-guided stopping (single volume): if stop is non-null and *stop != 0
+  // the launch does nothing.  XM_RATIO_LL (log-likelihood) and XM_UPDATE_MET
+  // (metric = MET_CHANGE or MET_PSNR) accumulate FP64 work-group partials into
+  // met_partials[row * gridDim.x + work-group] (rows as for launch_metric).
+  const int* stop;
+  int metric;
+  double* met_partials;
+  const float* ref;      // MET_PSNR: reference volume (dense rows like u)
+  // Real rows (rin, rout, d, u, hstep, gchg, ref) cover the caller's volume
   // vz x vy x vx at the low corner of the transform grid: grid row (z, y) is
   // real row z * vy + y when z < vz and y < vy, and holds vx floats (the rest of
   // the grid row reads as zero and is not written).  rin / rout rows are
@@ -137,6 +151,14 @@ hipError_t launch_flux_reduce(const double* partials, int groups, int rows, doub
 hipError_t launch_accel_alpha(const double* acc_partials, int groups, int it, float* alpha32,
                               double* alpha64, hipStream_t s, hipEvent_t ev0 = nullptr,
                               hipEvent_t ev1 = nullptr);
+// Metric of iteration `it` from the work-group partials (rows: LOGLIK: sum of
+// d log q - q; CHANGE: sum (u' - u)^2, sum u^2; PSNR: sum u', u'^2, u' g, g, g^2,
+// min g, max g), stored in hist[it]; then the stop decision (see rl.h):
+// stop[0] = 1 and stop[1] = iterations carried out.  stop[2] = entries of hist.
+// Does nothing once stop[0] is set.
+hipError_t launch_metric(const double* met_partials, int groups, int metric, int it,
+                         double threshold, int min_iter, long long nvox, double* hist, int* stop,
+                         hipStream_t s);
 // *counter += 1 (one thread); used to advance a device-side iteration index.
 hipError_t launch_advance(int* counter, hipStream_t s);
 // *counter = value (one thread).

@@ -470,6 +470,7 @@ template <int E, int MODE, int MAXT, int PREC = 0>
 __global__ void __launch_bounds__(MAXT, (MAXT == 1024 && E == 8) ? 8 : 1)
     k_pencil(float2* __restrict__ data, const float2* __restrict__ otf,
              const float2* __restrict__ twg, PencilArgs a, Sched sc) {
+  if (a.stop && *a.stop) return;  // stopped: the whole work-group leaves together
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
   // twiddle table (L entries) after the exchange buffer
@@ -603,8 +604,38 @@ __device__ __forceinline__ void store_pair(float* row, int q, int vx, bool on, f
   }
 }
 
+// Work-group FP64 reduction of K values per thread (op per value: 0 sum, 1 min,
+// 2 max): wavefront butterfly, then the waves in order; row r of the result goes
+// to out[r * gridDim.x + blockIdx.x].  All threads of the work-group call it.
+template <int K>
+__device__ __forceinline__ void wg_reduce_rows(double (&v)[K], const int (&op)[K], double* out) {
+  __shared__ double red[K][kXMaxThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int r = 0; r < K; ++r) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(v[r], off, 64);
+      v[r] = op[r] == 0 ? v[r] + o : op[r] == 1 ? fmin(v[r], o) : fmax(v[r], o);
+    }
+    if (lane == 0) red[r][wave] = v[r];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int nw = blockDim.x >> 6;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      double t = red[r][0];
+      for (int q = 1; q < nw; ++q)
+        t = op[r] == 0 ? t + red[r][q] : op[r] == 1 ? fmin(t, red[r][q]) : fmax(t, red[r][q]);
+      out[(long long)r * gridDim.x + blockIdx.x] = t;
+    }
+  }
+}
+
 template <int E, int MODE, int PREC = 0>
 __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const float2* __restrict__ twg) {
+  if (a.stop && *a.stop) return;  // stopped: the whole work-group leaves together
   extern __shared__ float2 lds[];
   const int M = a.M, P = a.P;
   const int tid = threadIdx.x;
@@ -659,16 +690,20 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
   } else {
     constexpr bool kAcc = MODE == XM_UPDATE_ACC;
     // issue every global load of the row first
-    float2 w[(MODE == XM_RATIO || MODE == XM_UPDATE || kAcc) ? E : 1];
+    // the metric variants of the ratio and update passes are separate kernels so
+    // that the plain ones keep their register budget
+    constexpr bool kRatio = MODE == XM_RATIO || MODE == XM_RATIO_LL;
+    constexpr bool kUpdate = MODE == XM_UPDATE || MODE == XM_UPDATE_MET;
+    float2 w[(kRatio || kUpdate || kAcc) ? E : 1];
     float2 hv[kAcc ? E : 1], gv[kAcc ? E : 1];
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = ok ? srow[col_off(i + P * m, ts)] : make_float2(0.f, 0.f);
     const float2 nyq = (ok && i == 0) ? srow[col_off(M, ts)] : make_float2(0.f, 0.f);
-    if constexpr (MODE == XM_RATIO) {
+    if constexpr (kRatio) {
       const float* dr = (a.d_tab ? a.d_tab[vol] : a.d) + rr * vx;
 #pragma unroll
       for (int m = 0; m < E; ++m) w[m] = load_pair(dr, i + P * m, vx, rv);
-    } else if constexpr (MODE == XM_UPDATE) {
+    } else if constexpr (kUpdate) {
       const float* ur = (a.u_tab ? a.u_tab[vol] : a.u) + rr * vx;
 #pragma unroll
       for (int m = 0; m < E; ++m) w[m] = load_pair(ur, i + P * m, vx, rv);
@@ -695,14 +730,28 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
       float* rout = (a.rout_tab ? a.rout_tab[vol] : a.rout) + rr * a.rout_stride;
 #pragma unroll
       for (int m = 0; m < E; ++m) store_pair(rout, i + P * m, vx, rv, v[m]);
-    } else if constexpr (MODE == XM_RATIO) {
+    } else if constexpr (kRatio) {
+      double ll = 0.0;  // Poisson log-likelihood of the caller's voxels (XM_RATIO_LL)
+      constexpr bool want_ll = MODE == XM_RATIO_LL;
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const float2 q = v[m];
+        if (want_ll && rv) {
+          const int x0 = 2 * (i + P * m);
+          if (x0 < vx && q.x > 1e-12f)
+            ll += (w[m].x > 0.f ? (double)w[m].x * log((double)q.x) : 0.0) - (double)q.x;
+          if (x0 + 1 < vx && q.y > 1e-12f)
+            ll += (w[m].y > 0.f ? (double)w[m].y * log((double)q.y) : 0.0) - (double)q.y;
+        }
         v[m] = make_float2(q.x > 1e-12f ? w[m].x / q.x : 0.f, q.y > 1e-12f ? w[m].y / q.y : 0.f);
       }
       wave_sync();  // row buffer reuse
       r2c_store<E, PREC>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
+      if constexpr (want_ll) {
+        double r[1] = {ll};
+        constexpr int ops[1] = {0};
+        wg_reduce_rows<1>(r, ops, a.met_partials);
+      }
     } else if constexpr (kAcc) {
       // x_{k+1} = y_k * max(c, 0) from the prediction y_k; keep h and g for the next
       // extrapolation and accumulate the flux and the two inner products of alpha
@@ -751,6 +800,11 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
     } else {  // XM_UPDATE
       float* ur = (a.u_tab ? a.u_tab[vol] : a.u) + rr * vx;
       double acc = 0.0;
+      // stopping metrics of the new estimate (MET_CHANGE / MET_PSNR)
+      double met[kMetRows] = {0.0, 0.0, 0.0, 0.0, 0.0, 1.0e300, -1.0e300};
+      constexpr bool kMet = MODE == XM_UPDATE_MET;
+      const bool want_change = kMet && a.metric == MET_CHANGE;
+      const bool want_psnr = kMet && a.metric == MET_PSNR;
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const float2 c = v[m];
@@ -760,6 +814,27 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
                                       w[m].y * (c.y < 0.f ? 0.f : c.y));
         store_pair(ur, i + P * m, vx, rv, un);
         acc += (double)un.x + (double)un.y;
+        if (want_change) {
+          const double dx = (double)un.x - (double)w[m].x, dy = (double)un.y - (double)w[m].y;
+          met[0] += dx * dx + dy * dy;
+          met[1] += (double)w[m].x * (double)w[m].x + (double)w[m].y * (double)w[m].y;
+        } else if (want_psnr && rv) {
+          const float2 g = load_pair(a.ref + rr * vx, i + P * m, vx, true);
+          const int x0 = 2 * (i + P * m);
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            if (x0 + h < vx) {
+              const double uu = h ? un.y : un.x, gg = h ? g.y : g.x;
+              met[0] += uu;
+              met[1] += uu * uu;
+              met[2] += uu * gg;
+              met[3] += gg;
+              met[4] += gg * gg;
+              met[5] = fmin(met[5], gg);
+              met[6] = fmax(met[6], gg);
+            }
+          }
+        }
         v[m] = un;
       }
       if (a.do_fwd) {
@@ -779,7 +854,72 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
         const int it = a.iter_ptr ? *a.iter_ptr : a.iter;
         a.partials[((long long)it * a.nvol + vol) * gridDim.x + blockIdx.x] = t;
       }
+      if constexpr (kMet) {
+        constexpr int ops[kMetRows] = {0, 0, 0, 0, 0, 1, 2};
+        wg_reduce_rows<kMetRows>(met, ops, a.met_partials);
+      }
     }
+  }
+}
+
+// Metric and stop decision of iteration `it` (one work-group; fixed summation order).
+__global__ void __launch_bounds__(256) k_metric(const double* __restrict__ mp, int groups,
+                                                int metric, int it, double threshold,
+                                                int min_iter, long long nvox,
+                                                double* __restrict__ hist, int* __restrict__ stop) {
+  if (stop[0]) return;
+  const int tid = threadIdx.x;
+  const int rows = metric == MET_LOGLIK ? 1 : metric == MET_CHANGE ? 2 : kMetRows;
+  __shared__ double ws[kMetRows][4];
+  for (int r = 0; r < rows; ++r) {
+    const int op = (metric == MET_PSNR && r == 5) ? 1 : (metric == MET_PSNR && r == 6) ? 2 : 0;
+    double t = op == 1 ? 1.0e300 : op == 2 ? -1.0e300 : 0.0;
+    for (int g = tid; g < groups; g += blockDim.x) {
+      const double x = mp[(long long)r * groups + g];
+      t = op == 0 ? t + x : op == 1 ? fmin(t, x) : fmax(t, x);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(t, off, 64);
+      t = op == 0 ? t + o : op == 1 ? fmin(t, o) : fmax(t, o);
+    }
+    if ((tid & 63) == 0) ws[r][tid >> 6] = t;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  double s[kMetRows];
+  for (int r = 0; r < rows; ++r) {
+    const int op = (metric == MET_PSNR && r == 5) ? 1 : (metric == MET_PSNR && r == 6) ? 2 : 0;
+    double t = ws[r][0];
+    for (int q = 1; q < 4; ++q)
+      t = op == 0 ? t + ws[r][q] : op == 1 ? fmin(t, ws[r][q]) : fmax(t, ws[r][q]);
+    s[r] = t;
+  }
+  double m;
+  bool halt = false;
+  int done = it + 1;  // iterations carried out if the iteration stops here
+  if (metric == MET_LOGLIK) {
+    // likelihood of the estimate entering iteration it; stopping skips that iteration
+    m = s[0];
+    done = it;
+    halt = it >= 1 && it >= min_iter && (m - hist[it - 1]) / fabs(m) < threshold;
+  } else if (metric == MET_CHANGE) {
+    m = sqrt(s[0] / s[1]);
+    halt = done >= min_iter && m < threshold;
+  } else {
+    const double n = (double)nvox;
+    const double cuu = s[1] - s[0] * s[0] / n, cug = s[2] - s[0] * s[3] / n;
+    const double cgg = s[4] - s[3] * s[3] / n;
+    double sse = cgg - (cuu > 0.0 ? cug * cug / cuu : 0.0);
+    if (sse < 0.0) sse = 0.0;
+    m = 20.0 * log10(s[6] - s[5]) - 10.0 * log10(sse / n);
+    halt = it >= 1 && done >= min_iter && m - hist[it - 1] < threshold;
+  }
+  hist[it] = m;
+  stop[2] = it + 1;
+  if (halt) {
+    stop[1] = done;
+    stop[0] = 1;
   }
 }
 
@@ -1093,11 +1233,23 @@ hipError_t launch_xrow(int mode, int E, int prec, dim3 grid, dim3 block, size_t 
     case XM_C2R: return xrow_e<XM_C2R>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
     case XM_RATIO: return xrow_e<XM_RATIO>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
     case XM_UPDATE: return xrow_e<XM_UPDATE>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
+    case XM_RATIO_LL:
+      return xrow_e<XM_RATIO_LL>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
+    case XM_UPDATE_MET:
+      return xrow_e<XM_UPDATE_MET>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
     case XM_PREDICT: return xrow_e<XM_PREDICT>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
     case XM_UPDATE_ACC:
       return xrow_e<XM_UPDATE_ACC>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_metric(const double* met_partials, int groups, int metric, int it,
+                         double threshold, int min_iter, long long nvox, double* hist, int* stop,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_metric, dim3(1), dim3(256), 0, s, met_partials, groups, metric, it,
+                     threshold, min_iter, nvox, hist, stop);
+  return hipGetLastError();
 }
 
 hipError_t launch_accel_alpha(const double* acc_partials, int groups, int it, float* alpha32,

@@ -27,6 +27,8 @@ RL_PRECISION_FP32, RL_PRECISION_SPLIT_BF16, RL_PRECISION_SPLIT_FP16 = 0, 1, 2
 _PRECISIONS = {"fp32": RL_PRECISION_FP32, "split_bf16": RL_PRECISION_SPLIT_BF16,
                "split_fp16": RL_PRECISION_SPLIT_FP16}
 RL_ACCEL_NONE, RL_ACCEL_BIGGS_ANDREWS = 0, 1
+RL_STOP_LOGLIK, RL_STOP_CHANGE, RL_STOP_PSNR = 1, 2, 3
+_STOP_METRICS = {"loglik": RL_STOP_LOGLIK, "change": RL_STOP_CHANGE, "psnr": RL_STOP_PSNR}
 _ACCELS = {"none": RL_ACCEL_NONE, "biggs_andrews": RL_ACCEL_BIGGS_ANDREWS}
 KERNEL_KINDS = ("x_r2c", "x_c2r", "x_ratio", "x_update", "y", "z_otf", "z", "other")
 
@@ -41,6 +43,11 @@ class RLError(RuntimeError):
 
 _STATUS_NAMES = {0: "RL_OK", 1: "RL_E_INVALID", 2: "RL_E_UNSUPPORTED", 3: "RL_E_NOMEM",
                  4: "RL_E_DEVICE", 5: "RL_E_NUMERIC", 6: "RL_E_INTERNAL"}
+
+
+class _StopRule(ctypes.Structure):
+    _fields_ = [("metric", ctypes.c_int), ("threshold", ctypes.c_double), ("min_iter", ctypes.c_int),
+                ("reference", ctypes.c_void_p)]
 
 
 class _Options(ctypes.Structure):
@@ -75,6 +82,9 @@ def lib() -> ctypes.CDLL:
                                ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "rl_plan_get_info": ([vp, i64p, i64p], ctypes.c_int),
         "rl_plan_get_grid": ([vp, i64p], ctypes.c_int),
+        "rl_iterate_stop": ([vp, vp, vp, ctypes.c_int, ctypes.POINTER(_StopRule)], ctypes.c_int),
+        "rl_plan_get_stop": ([vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                              ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "rl_plan_get_launch": ([vp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "rl_plan_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
         "rl_plan_time_pass": ([vp, ctypes.c_int, vp, vp, ctypes.c_int,
@@ -199,6 +209,25 @@ def rl_plan_get_alpha(plan: int) -> np.ndarray:
     return np.array(buf[: n.value], dtype=np.float64)
 
 
+def rl_iterate_stop(plan: int, observed_ptr: int, estimate_ptr: int, max_iter: int, metric: int,
+                    threshold: float, min_iter: int = 0, reference_ptr: int = 0) -> None:
+    rule = _StopRule(int(metric), float(threshold), int(min_iter),
+                     ctypes.c_void_p(reference_ptr or None))
+    _check(lib().rl_iterate_stop(ctypes.c_void_p(plan), ctypes.c_void_p(observed_ptr),
+                                 ctypes.c_void_p(estimate_ptr), int(max_iter), ctypes.byref(rule)))
+
+
+def rl_plan_get_stop(plan: int):
+    """(iterations done, metric history) of the last rl_iterate_stop call."""
+    n_done, n_hist = ctypes.c_int(0), ctypes.c_int(0)
+    _check(lib().rl_plan_get_stop(ctypes.c_void_p(plan), ctypes.byref(n_done), None, 0,
+                                  ctypes.byref(n_hist)))
+    buf = (ctypes.c_double * max(1, n_hist.value))()
+    _check(lib().rl_plan_get_stop(ctypes.c_void_p(plan), ctypes.byref(n_done), buf, n_hist.value,
+                                  ctypes.byref(n_hist)))
+    return n_done.value, np.array(buf[: n_hist.value], dtype=np.float64)
+
+
 def rl_plan_get_grid(plan: int) -> tuple:
     g = (ctypes.c_int64 * 3)()
     _check(lib().rl_plan_get_grid(ctypes.c_void_p(plan), g))
@@ -320,6 +349,31 @@ class Plan:
         _check_volume(estimate, self.shape, self.device, "estimate")
         self._bind_stream()
         rl_iterate(self.handle, observed.data_ptr(), estimate.data_ptr(), n_iter)
+
+    def iterate_until(self, observed, estimate, max_iter: int, metric: str, threshold: float,
+                      min_iter: int = 0, reference=None) -> None:
+        """At most max_iter iterations, stopped on the device by `metric` ("loglik",
+        "change" or "psnr" against `reference`); results via stop() and flux()."""
+        self._live()
+        _check_volume(observed, self.shape, self.device, "observed")
+        _check_volume(estimate, self.shape, self.device, "estimate")
+        if metric not in _STOP_METRICS:
+            raise ValueError(f"metric must be one of {sorted(_STOP_METRICS)}")
+        ref_ptr = 0
+        if metric == "psnr":
+            if reference is None:
+                raise ValueError("psnr needs a reference volume")
+            _check_volume(reference, self.shape, self.device, "reference")
+            ref_ptr = reference.data_ptr()
+        self._bind_stream()
+        rl_iterate_stop(self.handle, observed.data_ptr(), estimate.data_ptr(), max_iter,
+                        _STOP_METRICS[metric], threshold, min_iter, ref_ptr)
+
+    def stop(self):
+        """(iterations done, metric history) of the last iterate_until call (synchronises)."""
+        self._live()
+        self._bind_stream()
+        return rl_plan_get_stop(self.handle)
 
     def conv(self, x, out=None):
         """H x into `out` (new tensor if None)."""
