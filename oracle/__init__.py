@@ -9,3 +9,4 @@ from .boundary_oracle import (  # noqa: F401,E402
     embed_kernel, conv_periodic, corr_periodic, conv_zero, corr_zero, conv_zero_at, rl_general,
 )
 from .stop_oracle import psnr_si, rel_change, rl_stop  # noqa: F401,E402
+from .fsc_oracle import fsc, fsc_sums, resolution, split_diagonal  # noqa: F401,E402
