@@ -236,6 +236,36 @@ rl_status rl_iterate_stop(rl_plan p, const float* observed, float* estimate, int
  */
 rl_status rl_plan_get_stop(rl_plan p, int* n_done, double* history, int cap, int* n_history);
 
+/*
+ * Fourier shell correlation (paper §3 and §4.3: FRC/FSC and a single-image
+ * FRC-derived resolution are among its quality metrics) of volumes a and b
+ * (device, the plan's shape; periodic single-volume plans, else
+ * RL_E_UNSUPPORTED), with the plan's transforms: F = DFT(a), G = DFT(b);
+ * shell s = floor(rho / 0.5 * nbins) of each frequency, rho = sqrt(sum_i
+ * (k_i / n_i)^2) with k_i the signed index in [-n_i/2, n_i/2) (shells 0 ..
+ * nbins-1 cover rho < 0.5 cycles per voxel, shell nbins the corners beyond);
+ * curve[s] = sum_s Re(F conj G) / sqrt(sum_s |F|^2 sum_s |G|^2) (0 if a
+ * denominator is 0) for s = 0 .. nbins (host array of nbins + 1).
+ * *resolution (may be NULL): the frequency, in cycles per voxel, where the
+ * curve first drops below `threshold` (shell s >= 1, interpolated linearly
+ * between the centres (s - 0.5) * 0.5 / nbins and (s + 0.5) * 0.5 / nbins);
+ * 0.5 if it never does.  nbins in [2, 1024].  Uses the plan's spectrum
+ * workspace and a second one allocated on first use; synchronous.
+ * Shell sums are accumulated with shared-memory atomics, so their last bits
+ * may vary between calls.
+ */
+rl_status rl_fsc(rl_plan p, const float* a, const float* b, int nbins, double threshold,
+                 double* curve, double* resolution);
+
+/*
+ * Single-image split: a = u[0::2, 0::2, 0::2], b = u[1::2, 1::2, 1::2] of the
+ * dense volume u of `shape` (every dimension even; a and b hold shape/2 each;
+ * all device pointers).  Asynchronous on `hip_stream`.  rl_fsc of a and b on a
+ * plan of the half shape gives the single-image FSC.
+ */
+rl_status rl_split_diagonal(const float* u, const int64_t shape[3], float* a, float* b,
+                            void* hip_stream);
+
 /* Release the plan and its device memory (waits for its pending work). NULL is a no-op. */
 void rl_plan_destroy(rl_plan p);
 

@@ -13,9 +13,10 @@ notes):
 * FSC of volumes a, b (same shape): with F = DFT(a), G = DFT(b) and the
   normalised radius rho(k) = sqrt(sum_i (k_i / n_i)^2) of each frequency, k_i
   the signed index in [-n_i/2, n_i/2), shell s = floor(rho / 0.5 * nbins)
-  (shells 0 .. nbins-1 cover rho < 0.5 cycles per voxel; shell nbins collects
-  the corners beyond), FSC_s = sum_s Re(F conj G) / sqrt(sum_s |F|^2 sum_s |G|^2)
-  (0 where a denominator vanishes).
+  evaluated exactly (rho^2 is rational; frequencies on a shell boundary belong
+  to the outer shell), shells 0 .. nbins-1 covering rho < 0.5 cycles per voxel
+  and shell nbins the corners beyond; FSC_s = sum_s Re(F conj G) /
+  sqrt(sum_s |F|^2 sum_s |G|^2) (0 where a denominator vanishes).
 * Resolution: the first shell s >= 1 with FSC_s below the threshold (default
   1/7); the crossing frequency is interpolated linearly between the centres
   f_s = (s + 0.5) * 0.5 / nbins of shells s-1 and s; 0.5 if the curve never
@@ -25,6 +26,8 @@ notes):
 """
 
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -38,10 +41,15 @@ def signed_index(n: int) -> np.ndarray:
 
 
 def shell_index(shape, nbins: int) -> np.ndarray:
-    """Shell of every frequency of a full DFT grid of `shape`."""
-    fz, fy, fx = (signed_index(n) / n for n in shape)
-    rho = np.sqrt(fz[:, None, None] ** 2 + fy[None, :, None] ** 2 + fx[None, None, :] ** 2)
-    return np.minimum(np.floor(rho / 0.5 * nbins).astype(np.int64), nbins)
+    """Shell of every frequency of a full DFT grid of `shape`:
+    floor(2 nbins rho) = isqrt(floor(4 nbins^2 rho^2)), in exact integer
+    arithmetic over the common denominator L = lcm(n_z, n_y, n_x)."""
+    L = math.lcm(*[int(n) for n in shape])
+    kz, ky, kx = (signed_index(n).astype(object) * (L // n) for n in shape)
+    q = (kz[:, None, None] ** 2 + ky[None, :, None] ** 2) + kx[None, None, :] ** 2
+    four = 4 * nbins * nbins
+    s = np.vectorize(lambda v: math.isqrt((four * int(v)) // (L * L)), otypes=[np.int64])(q)
+    return np.minimum(s, nbins)
 
 
 def fsc_sums(a, b, nbins: int):

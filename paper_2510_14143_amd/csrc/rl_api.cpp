@@ -270,6 +270,11 @@ struct rl_plan_s {
   bool stop_call = false;         // the last iterate call used a stop rule
   int stop_max = 0;               // its max_iter
   const int* active_stop = nullptr;  // passed to every launch while a stop call is enqueued
+  // Fourier shell correlation (allocated on first use)
+  float2* spec2 = nullptr;        // second spectrum
+  double* fsc_part = nullptr;     // shell partials, fsc_cap shells
+  double* fsc_out = nullptr;
+  int fsc_cap = 0;
   // batched volumes of this shape (a class of a batch plan); 1 for a single plan
   int count = 1;
   const float** d_tab = nullptr;  // device tables of per-volume pointers (count each)
@@ -387,6 +392,9 @@ void release(rl_plan p) {
   (void)hipFree(p->stop);
   (void)hipFree(p->met_partials);
   (void)hipFree(p->mhist);
+  (void)hipFree(p->spec2);
+  (void)hipFree(p->fsc_part);
+  (void)hipFree(p->fsc_out);
   for (rl_plan c : p->classes) release(c);
   if (p->graph_full) (void)hipGraphExecDestroy(p->graph_full);
   if (p->graph_last) (void)hipGraphExecDestroy(p->graph_last);
@@ -1410,6 +1418,80 @@ rl_status stop_state(rl_plan p, int* n_done, int* n_hist) {
   return RL_OK;
 }
 
+// Half spectrum of a real volume of the plan's shape into `spec` (forward along X,
+// Y and Z; no filter).
+rl_status forward3(rl_plan p, const float* x, float2* spec) {
+  XArgs a = base_xargs(p, spec);
+  a.rin = x;
+  rl_status st = run_x(p, rlmi::XM_R2C, a, RL_KERNEL_OTHER);
+  if (st == RL_OK) st = run_pencil(p, p->py, rlmi::PM_FWD, spec, p->tw_y, RL_KERNEL_OTHER);
+  if (st == RL_OK) st = run_pencil(p, p->pz, rlmi::PM_FWD, spec, p->tw_z, RL_KERNEL_OTHER);
+  return st;
+}
+
+rl_status fsc_impl(rl_plan p, const float* a, const float* b, int nbins, double threshold,
+                   double* curve, double* resolution) {
+  rl_status st = check_plan(p);
+  if (st != RL_OK) return st;
+  if (p->is_batch) return fail(RL_E_UNSUPPORTED, "rl_fsc takes a single-volume plan");
+  if (p->boundary != RL_BOUNDARY_PERIODIC)
+    return fail(RL_E_UNSUPPORTED, "rl_fsc needs a periodic plan (its grid is the volume)");
+  if (nbins < 2 || nbins > 1024) return fail(RL_E_INVALID, "nbins must be in [2, 1024]");
+  if (!std::isfinite(threshold)) return fail(RL_E_INVALID, "threshold must be finite");
+  if (!curve) return fail(RL_E_INVALID, "curve is NULL");
+  const size_t bytes = (size_t)p->vnvox * sizeof(float);
+  int dev = p->device;
+  if ((st = check_dev_ptr(a, bytes, &dev, "a")) != RL_OK) return st;
+  if ((st = check_dev_ptr(b, bytes, &dev, "b")) != RL_OK) return st;
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if (!p->spec2 &&
+      (e = hipMalloc(&p->spec2, p->spec_elems * sizeof(float2))) != hipSuccess)
+    return hip_fail(e, "hipMalloc(second spectrum)");
+  if (nbins + 1 > p->fsc_cap) {
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    else (void)hipDeviceSynchronize();
+    (void)hipFree(p->fsc_part);
+    (void)hipFree(p->fsc_out);
+    p->fsc_part = nullptr;
+    p->fsc_out = nullptr;
+    p->fsc_cap = 0;
+    const size_t groups = (size_t)p->nz * p->xt;
+    if ((e = hipMalloc(&p->fsc_part, groups * (nbins + 1) * 3 * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&p->fsc_out, (4 * (size_t)(nbins + 1) + 1) * sizeof(double))) !=
+            hipSuccess)
+      return hip_fail(e, "hipMalloc(shell sums)");
+    p->fsc_cap = nbins + 1;
+  }
+  auto gcd = [](int64_t x, int64_t y) {
+    while (y) {
+      const int64_t t = x % y;
+      x = y;
+      y = t;
+    }
+    return x;
+  };
+  int64_t lcm = p->nz;
+  lcm = lcm / gcd(lcm, p->ny) * p->ny;
+  lcm = lcm / gcd(lcm, p->nx) * p->nx;
+  if (lcm >= ((int64_t)1 << 21))
+    return fail(RL_E_UNSUPPORTED, "rl_fsc: lcm of the dimensions must be below 2^21");
+  if ((st = forward3(p, a, p->spec)) != RL_OK) return st;
+  if ((st = forward3(p, b, p->spec2)) != RL_OK) return st;
+  if ((e = rlmi::launch_fsc(p->spec, p->spec2, (int)p->nz, (int)p->ny, (int)p->nx, (int)p->xt,
+                            nbins, (long long)lcm, threshold, p->fsc_part, p->fsc_out,
+                            p->stream)) != hipSuccess)
+    return hip_fail(e, "shell correlation launch");
+  std::vector<double> h(4 * (size_t)(nbins + 1) + 1);
+  if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return hip_fail(e, "execution");
+  if ((e = hipMemcpy(h.data(), p->fsc_out, h.size() * sizeof(double), hipMemcpyDeviceToHost)) !=
+      hipSuccess)
+    return hip_fail(e, "hipMemcpy(shell correlation)");
+  for (int i = 0; i <= nbins; ++i) curve[i] = h[(size_t)i];
+  if (resolution) *resolution = h[4 * (size_t)(nbins + 1)];
+  return RL_OK;
+}
+
 // --- batched volumes -----------------------------------------------------------
 
 rl_status create_batch_impl(int count, const int64_t* shapes, const float* const* psfs,
@@ -1763,6 +1845,40 @@ rl_status rl_plan_get_flux(rl_plan p, double* flux, int cap, int* n_written) {
     if (!std::isfinite(h[(size_t)i]))
       return fail(RL_E_NUMERIC, "non-finite flux at entry " + std::to_string(i));
   return RL_OK;
+}
+
+rl_status rl_fsc(rl_plan p, const float* a, const float* b, int nbins, double threshold,
+                 double* curve, double* resolution) {
+  try {
+    return fsc_impl(p, a, b, nbins, threshold, curve, resolution);
+  } catch (...) {
+    return fail(RL_E_INTERNAL, "unexpected exception in rl_fsc");
+  }
+}
+
+rl_status rl_split_diagonal(const float* u, const int64_t shape[3], float* a, float* b,
+                            void* hip_stream) {
+  try {
+    if (!shape) return fail(RL_E_INVALID, "shape is NULL");
+    for (int i = 0; i < 3; ++i)
+      if (shape[i] < 2 || shape[i] % 2 != 0 || shape[i] > ((int64_t)1 << 30))
+        return fail(RL_E_INVALID, "every dimension must be even and >= 2");
+    if (shape[1] / 2 > 65535 || shape[0] / 2 > 65535)
+      return fail(RL_E_UNSUPPORTED, "ny/2 and nz/2 must be <= 65535");
+    const int64_t n = shape[0] * shape[1] * shape[2];
+    int dev = -1;
+    rl_status st = check_dev_ptr(u, (size_t)n * sizeof(float), &dev, "u");
+    if (st != RL_OK) return st;
+    if ((st = check_dev_ptr(a, (size_t)(n / 8) * sizeof(float), &dev, "a")) != RL_OK) return st;
+    if ((st = check_dev_ptr(b, (size_t)(n / 8) * sizeof(float), &dev, "b")) != RL_OK) return st;
+    hipError_t e = hipSetDevice(dev);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    e = rlmi::launch_split_diag(u, (int)shape[0], (int)shape[1], (int)shape[2], a, b,
+                                reinterpret_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? RL_OK : hip_fail(e, "split launch");
+  } catch (...) {
+    return fail(RL_E_INTERNAL, "unexpected exception in rl_split_diagonal");
+  }
 }
 
 rl_status rl_iterate_stop(rl_plan p, const float* observed, float* estimate, int max_iter,

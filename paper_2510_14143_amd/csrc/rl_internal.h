@@ -159,6 +159,17 @@ hipError_t launch_accel_alpha(const double* acc_partials, int groups, int it, fl
 hipError_t launch_metric(const double* met_partials, int groups, int metric, int it,
                          double threshold, int min_iter, long long nvox, double* hist, int* stop,
                          hipStream_t s);
+// a = u[0::2, 0::2, 0::2], b = u[1::2, 1::2, 1::2] of a dense nz x ny x nx volume
+// (even dimensions; a and b hold (nz/2)(ny/2)(nx/2) floats each).
+hipError_t launch_split_diag(const float* u, int nz, int ny, int nx, float* a, float* b,
+                             hipStream_t s);
+// Fourier shell correlation of two half spectra (tiled layout of an nz x ny x nx
+// grid with xt tiles; lcm = lcm(nz, ny, nx) < 2^21): part holds
+// nz * xt * (nbins + 1) * 3 doubles, out 4 * (nbins + 1) + 1 (curve, the three
+// sums per shell, resolution).
+hipError_t launch_fsc(const float2* F, const float2* G, int nz, int ny, int nx, int xt, int nbins,
+                      long long lcm, double threshold, double* part, double* out,
+                      hipStream_t s);
 // *counter += 1 (one thread); used to advance a device-side iteration index.
 hipError_t launch_advance(int* counter, hipStream_t s);
 // *counter = value (one thread).

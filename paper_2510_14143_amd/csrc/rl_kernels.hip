@@ -979,6 +979,110 @@ __global__ void __launch_bounds__(256) k_accel_alpha(const double* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Fourier shell correlation
+// ---------------------------------------------------------------------------
+// a[z][y][x] = u[2z][2y][2x], b[z][y][x] = u[2z+1][2y+1][2x+1] (half-size volumes).
+__global__ void k_split_diag(const float* __restrict__ u, int nz, int ny, int nx,
+                             float* __restrict__ a, float* __restrict__ b) {
+  const int hz = nz / 2, hy = ny / 2, hx = nx / 2;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+  if (x >= hx) return;
+  const long long o = ((long long)z * hy + y) * hx + x;
+  a[o] = u[((long long)(2 * z) * ny + 2 * y) * nx + 2 * x];
+  b[o] = u[((long long)(2 * z + 1) * ny + 2 * y + 1) * nx + 2 * x + 1];
+}
+
+// |signed DFT index| of bin j of length n: j below ceil(n/2), n - j above.
+__device__ __forceinline__ long long abs_index(int j, int n) {
+  return j < (n + 1) / 2 ? j : n - j;
+}
+
+// One work-group per tile column (z, 16 kx columns, all ny rows) of two half
+// spectra F and G: per shell s = floor(2 nbins rho) (nbins for rho >= 0.5),
+// rho^2 = sum_i (k_i / n_i)^2, the sums of Re(F conj G), |F|^2, |G|^2, each column
+// kx in 1 .. M-1 counted twice (it stands for its conjugate partner too).  The
+// shell is exact: with L = lcm(n_i) and m_i = L / n_i, Q = sum_i (k_i m_i)^2 and
+// s is the largest integer with s^2 L^2 <= 4 nbins^2 Q (all below 2^63 for
+// L < 2^21).  Work-group partials go to
+// part[((z * XT + tile) * (nbins + 1) + s) * 3 + {0, 1, 2}].
+__global__ void __launch_bounds__(256) k_shell(const float2* __restrict__ F,
+                                               const float2* __restrict__ G, int nz, int ny,
+                                               int nx, int xt, int nbins, long long lcm,
+                                               double* __restrict__ part) {
+  extern __shared__ double hist[];  // (nbins + 1) * 3
+  const int tid = threadIdx.x;
+  const int nb1 = nbins + 1;
+  for (int t = tid; t < nb1 * 3; t += blockDim.x) hist[t] = 0.0;
+  __syncthreads();
+  const int tile = blockIdx.x, z = blockIdx.y;
+  const int M = nx / 2;
+  const long long base = ((long long)z * xt + tile) * ny * kTile;
+  const unsigned long long D = (unsigned long long)lcm * (unsigned long long)lcm;
+  const unsigned long long four = 4ull * (unsigned long long)nbins * (unsigned long long)nbins;
+  const unsigned long long kz = (unsigned long long)(abs_index(z, nz) * (lcm / nz));
+  for (int e = tid; e < ny * kTile; e += blockDim.x) {
+    const int y = e >> 4, c = e & (kTile - 1);
+    const int kx = tile * kTile + c;
+    if (kx > M) continue;
+    const unsigned long long ky = (unsigned long long)(abs_index(y, ny) * (lcm / ny));
+    const unsigned long long kxx = (unsigned long long)kx * (unsigned long long)(lcm / nx);
+    const unsigned long long Q = kz * kz + ky * ky + kxx * kxx;
+    const unsigned long long A = four * Q;
+    long long sh = (long long)(2.0 * nbins * sqrt((double)Q) / (double)lcm);
+    while (sh > 0 && (unsigned long long)(sh * sh) * D > A) --sh;
+    while ((unsigned long long)((sh + 1) * (sh + 1)) * D <= A) ++sh;
+    if (sh > nbins) sh = nbins;
+    const double w = (kx == 0 || kx == M) ? 1.0 : 2.0;
+    const float2 f = F[base + e], g = G[base + e];
+    const double fr = f.x, fi = f.y, gr = g.x, gi = g.y;
+    atomicAdd(&hist[sh * 3 + 0], w * (fr * gr + fi * gi));
+    atomicAdd(&hist[sh * 3 + 1], w * (fr * fr + fi * fi));
+    atomicAdd(&hist[sh * 3 + 2], w * (gr * gr + gi * gi));
+  }
+  __syncthreads();
+  double* out = part + ((long long)z * xt + tile) * nb1 * 3;
+  for (int t = tid; t < nb1 * 3; t += blockDim.x) out[t] = hist[t];
+}
+
+// Sums the work-group partials per shell in a fixed order and writes
+// out = [curve (nbins + 1), sums Re(F conj G), |F|^2, |G|^2 (nbins + 1 each),
+// resolution]: the first shell s >= 1 whose FSC is below `threshold`, crossing
+// interpolated between the centres of shells s-1 and s; 0.5 if none.
+__global__ void __launch_bounds__(256) k_fsc_final(const double* __restrict__ part, int groups,
+                                                   int nbins, double threshold,
+                                                   double* __restrict__ out) {
+  const int nb1 = nbins + 1;
+  for (int sh = threadIdx.x; sh < nb1; sh += blockDim.x) {
+    double n = 0.0, d1 = 0.0, d2 = 0.0;
+    for (int g = 0; g < groups; ++g) {
+      const double* q = part + ((long long)g * nb1 + sh) * 3;
+      n += q[0];
+      d1 += q[1];
+      d2 += q[2];
+    }
+    const double den = sqrt(d1 * d2);
+    out[sh] = den > 0.0 ? n / den : 0.0;
+    out[nb1 + sh] = n;
+    out[2 * nb1 + sh] = d1;
+    out[3 * nb1 + sh] = d2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double res = 0.5;
+    for (int sh = 1; sh < nbins; ++sh) {
+      if (out[sh] < threshold) {
+        const double c0 = out[sh - 1], c1 = out[sh];
+        const double t = c0 != c1 ? (c0 - threshold) / (c0 - c1) : 0.0;
+        const double f0 = (sh - 0.5) * 0.5 / nbins, f1 = (sh + 0.5) * 0.5 / nbins;
+        res = f0 + t * (f1 - f0);
+        break;
+      }
+    }
+    out[4 * nb1] = res;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // small kernels: twiddles, PSF statistics and preparation, copy probe
 // ---------------------------------------------------------------------------
 // tab[m] = exp(-2 pi i m / n), evaluated in FP64 from the exact integer m / n
@@ -1249,6 +1353,25 @@ hipError_t launch_metric(const double* met_partials, int groups, int metric, int
                          hipStream_t s) {
   hipLaunchKernelGGL(k_metric, dim3(1), dim3(256), 0, s, met_partials, groups, metric, it,
                      threshold, min_iter, nvox, hist, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_diag(const float* u, int nz, int ny, int nx, float* a, float* b,
+                             hipStream_t s) {
+  dim3 g((unsigned)((nx / 2 + 255) / 256), (unsigned)(ny / 2), (unsigned)(nz / 2));
+  hipLaunchKernelGGL(k_split_diag, g, dim3(256), 0, s, u, nz, ny, nx, a, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_fsc(const float2* F, const float2* G, int nz, int ny, int nx, int xt, int nbins,
+                      long long lcm, double threshold, double* part, double* out,
+                      hipStream_t s) {
+  const size_t lds = (size_t)(nbins + 1) * 3 * sizeof(double);
+  hipLaunchKernelGGL(k_shell, dim3((unsigned)xt, (unsigned)nz), dim3(256), lds, s, F, G, nz, ny,
+                     nx, xt, nbins, lcm, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fsc_final, dim3(1), dim3(256), 0, s, part, nz * xt, nbins, threshold, out);
   return hipGetLastError();
 }
 

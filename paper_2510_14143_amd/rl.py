@@ -83,6 +83,9 @@ def lib() -> ctypes.CDLL:
         "rl_plan_get_info": ([vp, i64p, i64p], ctypes.c_int),
         "rl_plan_get_grid": ([vp, i64p], ctypes.c_int),
         "rl_iterate_stop": ([vp, vp, vp, ctypes.c_int, ctypes.POINTER(_StopRule)], ctypes.c_int),
+        "rl_fsc": ([vp, vp, vp, ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                    ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "rl_split_diagonal": ([vp, i64p, vp, vp, vp], ctypes.c_int),
         "rl_plan_get_stop": ([vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
                               ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "rl_plan_get_launch": ([vp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
@@ -226,6 +229,33 @@ def rl_plan_get_stop(plan: int):
     _check(lib().rl_plan_get_stop(ctypes.c_void_p(plan), ctypes.byref(n_done), buf, n_hist.value,
                                   ctypes.byref(n_hist)))
     return n_done.value, np.array(buf[: n_hist.value], dtype=np.float64)
+
+
+def rl_fsc(plan: int, a_ptr: int, b_ptr: int, nbins: int = 64, threshold: float = 1.0 / 7.0):
+    """(FSC curve over nbins + 1 shells, resolution in cycles per voxel)."""
+    curve = (ctypes.c_double * (nbins + 1))()
+    res = ctypes.c_double(0.0)
+    _check(lib().rl_fsc(ctypes.c_void_p(plan), ctypes.c_void_p(a_ptr), ctypes.c_void_p(b_ptr),
+                        int(nbins), float(threshold), curve, ctypes.byref(res)))
+    return np.array(curve[:], dtype=np.float64), res.value
+
+
+def rl_split_diagonal(u_ptr: int, shape, a_ptr: int, b_ptr: int, stream: int = 0) -> None:
+    _check(lib().rl_split_diagonal(ctypes.c_void_p(u_ptr), _shape(shape), ctypes.c_void_p(a_ptr),
+                                   ctypes.c_void_p(b_ptr), ctypes.c_void_p(stream or None)))
+
+
+def split_diagonal(u):
+    """The two diagonal half-size sub-volumes of u (new tensors)."""
+    import torch
+    if u.dim() != 3:
+        raise ValueError("u must be a 3-D tensor")
+    _check_volume(u, u.shape, None, "u")
+    half = tuple(int(n) // 2 for n in u.shape)
+    a = torch.empty(half, dtype=torch.float32, device=u.device)
+    b = torch.empty_like(a)
+    rl_split_diagonal(u.data_ptr(), tuple(u.shape), a.data_ptr(), b.data_ptr(), _stream_of(u.device))
+    return a, b
 
 
 def rl_plan_get_grid(plan: int) -> tuple:
@@ -374,6 +404,14 @@ class Plan:
         self._live()
         self._bind_stream()
         return rl_plan_get_stop(self.handle)
+
+    def fsc(self, a, b, nbins: int = 64, threshold: float = 1.0 / 7.0):
+        """FSC curve of volumes a and b and the resolution crossing (synchronises)."""
+        self._live()
+        _check_volume(a, self.shape, self.device, "a")
+        _check_volume(b, self.shape, self.device, "b")
+        self._bind_stream()
+        return rl_fsc(self.handle, a.data_ptr(), b.data_ptr(), nbins, threshold)
 
     def conv(self, x, out=None):
         """H x into `out` (new tensor if None)."""

@@ -145,6 +145,18 @@ def test_elems_options_validated_before_device_work():
         assert st == rl.RL_E_INVALID and "accel" in rl.rl_last_error()
 
 
+def test_fsc_and_split_validation():
+    L = rl.lib()
+    curve = (ctypes.c_double * 9)()
+    fake = ctypes.c_void_p(0x1234560)
+    assert L.rl_fsc(fake, None, None, 8, 0.1, curve, None) == rl.RL_E_INVALID
+    for shape in ((3, 4, 4), (4, 0, 4), (4, 4, 5)):
+        sh = (ctypes.c_int64 * 3)(*shape)
+        assert L.rl_split_diagonal(ctypes.c_void_p(4096), sh, ctypes.c_void_p(4096),
+                                   ctypes.c_void_p(4096), None) == rl.RL_E_INVALID
+    assert L.rl_split_diagonal(None, None, None, None, None) == rl.RL_E_INVALID
+
+
 def test_alpha_query_checks_handle():
     L = rl.lib()
     n = ctypes.c_int()
