@@ -374,6 +374,40 @@ def run_stop(torch, rl, synth, steps: int, cfg: int = 1):
                      "last_metric": float(hist[-1]) if len(hist) else None,
                      "metric_overhead_per_iter_pct": round(100 * (ms_all / out["fixed_ms"] - 1), 2),
                      "value": round(nvox * n / (ms * 1e-3) / 1e9, 3) if n else None}
+    # single-image FSC of the 100-iteration estimate: split + two transforms + shell
+    # sums on the device, against numpy's FFT on the host (context)
+    u.copy_(u0)
+    plan.iterate(d, u, n_max)
+    half = tuple(n // 2 for n in c["shape"])
+    delta = torch.zeros(half, dtype=torch.float32, device=dev)
+    delta[tuple(n // 2 for n in half)] = 1.0
+    with rl.Plan(delta) as q:
+        a, b = rl.split_diagonal(u)
+        q.fsc(a, b, 64)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        reps = 10
+        for _ in range(reps):
+            a, b = rl.split_diagonal(u)
+            _, res = q.fsc(a, b, 64)
+        fsc_ms = (time.perf_counter() - t) * 1e3 / reps
+    un = u.cpu().numpy().astype(np.float64)
+    t = time.perf_counter()
+    fa = np.fft.rfftn(un[0::2, 0::2, 0::2])
+    fb = np.fft.rfftn(un[1::2, 1::2, 1::2])
+    _ = np.real(fa * np.conj(fb)).sum(), (np.abs(fa) ** 2).sum(), (np.abs(fb) ** 2).sum()
+    host_ms = (time.perf_counter() - t) * 1e3
+    # FSC-guided stop: stop when the resolution no longer improves (threshold 0)
+    u.copy_(u0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    n_fsc, hist = plan.iterate_until_fsc(d, u, n_max, 0.0, nbins=64)
+    fsc_stop_ms = (time.perf_counter() - t) * 1e3
+    out["fsc"] = {"single_image_fsc_ms": round(fsc_ms, 3), "resolution_cycles_per_voxel": res,
+                  "numpy_fft_only_ms_context": round(host_ms, 1),
+                  "guided_stop_threshold": 0.0, "guided_stop_iterations": n_fsc,
+                  "guided_stop_ms": round(fsc_stop_ms, 2),
+                  "guided_stop_last_resolution": float(hist[-1])}
     plan.close()
     return out
 

@@ -23,6 +23,10 @@ reasons in the design notes):
   20 log10(max g - min g) - 10 log10(MSE of the least-squares affine fit
   a u + b to g); improvement psnr_k - psnr_{k-1} (dB, none at k = 0); stop once it
   is below the threshold, returning u_{k+1}.
+* "fsc": the single-image FSC resolution of u_{k+1} (``fsc_oracle``: FSC of the
+  two diagonal half-size sub-volumes, frequency where it first drops below
+  `fsc_threshold`, default 1/7); improvement r_k - r_{k-1} (cycles per voxel,
+  none at k = 0); stop once it is below the threshold, returning u_{k+1}.
 * No stop before `min_iter` iterations have been carried out; at most
   `max_iter` iterations.
 """
@@ -31,9 +35,16 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import fsc_oracle
 from .rl_oracle import EPS, adjoint, forward, loglik, otf, ratio
 
-METRICS = ("loglik", "change", "psnr")
+METRICS = ("loglik", "change", "psnr", "fsc")
+
+
+def fsc_resolution(u, nbins: int = 64, fsc_threshold: float = 1.0 / 7.0) -> float:
+    """Single-image FSC resolution (cycles per voxel) of u."""
+    a, b = fsc_oracle.split_diagonal(u)
+    return fsc_oracle.resolution(fsc_oracle.fsc(a, b, nbins), nbins, fsc_threshold)
 
 
 def psnr_si(u, g) -> float:
@@ -57,7 +68,8 @@ def rel_change(u_new, u_old) -> float:
 
 
 def rl_stop(d, h, u0, max_iter: int, metric: str, threshold: float, reference=None,
-            min_iter: int = 0, eps: float = EPS):
+            min_iter: int = 0, eps: float = EPS, nbins: int = 64,
+            fsc_threshold: float = 1.0 / 7.0):
     """Richardson-Lucy with metric-guided stopping.
 
     Returns (u, n_done, history): the estimate after the iterations carried out,
@@ -88,6 +100,9 @@ def rl_stop(d, h, u0, max_iter: int, metric: str, threshold: float, reference=No
             stop = hist[-1] < threshold
         elif metric == "psnr":
             hist.append(psnr_si(u_new, reference))
+            stop = k >= 1 and hist[k] - hist[k - 1] < threshold
+        elif metric == "fsc":
+            hist.append(fsc_resolution(u_new, nbins, fsc_threshold))
             stop = k >= 1 and hist[k] - hist[k - 1] < threshold
         u = u_new
         if stop and n_done >= min_iter:

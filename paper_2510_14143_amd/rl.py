@@ -399,6 +399,34 @@ class Plan:
         rl_iterate_stop(self.handle, observed.data_ptr(), estimate.data_ptr(), max_iter,
                         _STOP_METRICS[metric], threshold, min_iter, ref_ptr)
 
+    def iterate_until_fsc(self, observed, estimate, max_iter: int, threshold: float,
+                          nbins: int = 64, fsc_threshold: float = 1.0 / 7.0, min_iter: int = 0):
+        """At most max_iter iterations, stopped once the single-image FSC resolution
+        of the estimate (FSC of its two diagonal half-size sub-volumes, frequency where
+        it first drops below fsc_threshold) improves by less than `threshold` cycles
+        per voxel between consecutive iterations.  Every step runs on the device
+        (iterations, split, transforms, shell sums); the host only compares the
+        resolutions.  Returns (iterations done, resolution after each)."""
+        import torch
+        self._live()
+        if any(n % 2 for n in self.shape):
+            raise ValueError("the single-image split needs even dimensions")
+        half = tuple(n // 2 for n in self.shape)
+        delta = torch.zeros(half, dtype=torch.float32, device=self.device)
+        delta[tuple(n // 2 for n in half)] = 1.0
+        hist = []
+        n_done = 0
+        with Plan(delta) as q:
+            while n_done < max_iter:
+                self.iterate(observed, estimate, 1)
+                n_done += 1
+                a, b = split_diagonal(estimate)
+                _, res = q.fsc(a, b, nbins, fsc_threshold)
+                hist.append(res)
+                if len(hist) >= 2 and n_done >= min_iter and hist[-1] - hist[-2] < threshold:
+                    break
+        return n_done, np.array(hist)
+
     def stop(self):
         """(iterations done, metric history) of the last iterate_until call (synchronises)."""
         self._live()

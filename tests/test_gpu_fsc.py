@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 from oracle import fsc_oracle as fo
+from oracle import stop_oracle as so
 from paper_2510_14143_amd import rl, synth
 
 pytestmark = pytest.mark.gpu
@@ -94,3 +95,25 @@ def test_fsc_errors(torch):
         assert ei.value.status == rl.RL_E_UNSUPPORTED
     with pytest.raises(rl.RLError):
         rl.split_diagonal(dev(torch, np.ones((3, 4, 4))))
+
+
+def test_fsc_guided_stop_matches_oracle(torch):
+    c = synth.make_config(0)
+    say("fsc-guided stop")
+    nb = 16
+    _, _, full = so.rl_stop(c["d"], c["psf"], c["u0"], 20, "fsc", -1e300, nbins=nb)
+    delta = np.diff(full)                       # delta[j]: after iteration j + 2
+    # a threshold halfway between two well-separated consecutive improvements
+    gaps = [(abs(delta[j] - delta[j + 1]), j) for j in range(2, len(delta) - 1)
+            if delta[j + 1] < delta[j]]
+    _, j = max(gaps)
+    tau = 0.5 * (delta[j] + delta[j + 1])
+    ref_u, ref_n, ref_hist = so.rl_stop(c["d"], c["psf"], c["u0"], 20, "fsc", tau, nbins=nb)
+    with rl.Plan(dev(torch, c["psf"])) as p:
+        u = dev(torch, c["u0"])
+        n, hist = p.iterate_until_fsc(dev(torch, c["d"]), u, 20, tau, nbins=nb)
+        got = u.cpu().numpy()
+    say("  oracle n", ref_n, "gpu n", n, "tau", tau)
+    assert n == ref_n
+    assert np.max(np.abs(hist - ref_hist)) <= 1e-4
+    assert np.max(np.abs(got - ref_u)) / np.max(np.abs(ref_u)) <= 1e-4

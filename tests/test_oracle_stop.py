@@ -101,6 +101,16 @@ def test_loglik_improvements_are_non_negative():
     assert np.all(np.diff(hist) >= -1e-12 * np.abs(hist[1:]))
 
 
+def test_fsc_metric_is_the_fsc_oracle_of_each_iterate():
+    d, h, u0, _ = _case()
+    u, n, hist = so.rl_stop(d, h, u0, 4, "fsc", -1e300, nbins=8)
+    assert n == 4 and len(hist) == 4
+    for k in range(4):
+        uk = oracle.rl(d, h, u0, k + 1)[0]
+        a, b = uk[0::2, 0::2, 0::2], uk[1::2, 1::2, 1::2]
+        assert hist[k] == oracle.resolution(oracle.fsc(a, b, 8), 8)
+
+
 def test_delta_psf_change_stops_after_fixed_point():
     shape = (4, 6, 6)
     d = rng(9).uniform(1, 10, size=shape)
