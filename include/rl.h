@@ -204,11 +204,19 @@ rl_status rl_iterate_batch(rl_plan p, const float* const* observed, float* const
  *     the volume's shape): 20 log10(max g - min g) - 10 log10(mean squared
  *     residual of the least-squares affine fit of u to g); stops at k >= 1 when
  *     psnr_k - psnr_{k-1} < threshold (dB; k + 1 iterations done).
+ *   RL_STOP_SSIM: mean SSIM of u_{k+1} against `reference` (see rl_ssim); stops at
+ *     k >= 1 when ssim_k - ssim_{k-1} < threshold (k + 1 iterations done).  Runs
+ *     three window-sum passes after each update (about 170 bytes per voxel).
  * No stop happens before min_iter iterations are done.  The metric is
  * accumulated in FP64 inside the passes (no extra pass over the volume; PSNR
  * reads the reference, 4 bytes per voxel per iteration).
  */
-typedef enum { RL_STOP_LOGLIK = 1, RL_STOP_CHANGE = 2, RL_STOP_PSNR = 3 } rl_stop_metric;
+typedef enum {
+  RL_STOP_LOGLIK = 1,
+  RL_STOP_CHANGE = 2,
+  RL_STOP_PSNR = 3,
+  RL_STOP_SSIM = 4
+} rl_stop_metric;
 
 typedef struct {
   int metric;              /* rl_stop_metric */
@@ -235,6 +243,17 @@ rl_status rl_iterate_stop(rl_plan p, const float* observed, float* estimate, int
  * iteration done).  Synchronises the plan's stream.
  */
 rl_status rl_plan_get_stop(rl_plan p, int* n_done, double* history, int cap, int* n_history);
+
+/*
+ * Structural similarity (paper §4.3 lists SSIM against ground truth among its
+ * metrics; Wang et al. 2004) of u against `reference` (device, the plan's volume
+ * shape, every dimension >= 7, else RL_E_UNSUPPORTED): 7x7x7 uniform windows
+ * lying inside the volume, sample (co)variances (normalised by 342),
+ * C1 = (0.01 L)^2, C2 = (0.03 L)^2 with L = max - min of the reference;
+ * *value = mean over the windows.  Window sums in FP64; buffers of about
+ * 80 bytes per voxel are allocated on first use.  Synchronous.
+ */
+rl_status rl_ssim(rl_plan p, const float* u, const float* reference, double* value);
 
 /*
  * Fourier shell correlation (paper §3 and §4.3: FRC/FSC and a single-image

@@ -10,3 +10,4 @@ from .boundary_oracle import (  # noqa: F401,E402
 )
 from .stop_oracle import psnr_si, rel_change, rl_stop  # noqa: F401,E402
 from .fsc_oracle import fsc, fsc_sums, resolution, split_diagonal  # noqa: F401,E402
+from .ssim_oracle import ssim  # noqa: F401,E402

@@ -27,6 +27,9 @@ reasons in the design notes):
   two diagonal half-size sub-volumes, frequency where it first drops below
   `fsc_threshold`, default 1/7); improvement r_k - r_{k-1} (cycles per voxel,
   none at k = 0); stop once it is below the threshold, returning u_{k+1}.
+* "ssim": mean SSIM of u_{k+1} against the reference (``ssim_oracle``);
+  improvement ssim_k - ssim_{k-1} (none at k = 0); stop once it is below the
+  threshold, returning u_{k+1}.
 * No stop before `min_iter` iterations have been carried out; at most
   `max_iter` iterations.
 """
@@ -35,10 +38,10 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import fsc_oracle
+from . import fsc_oracle, ssim_oracle
 from .rl_oracle import EPS, adjoint, forward, loglik, otf, ratio
 
-METRICS = ("loglik", "change", "psnr", "fsc")
+METRICS = ("loglik", "change", "psnr", "fsc", "ssim")
 
 
 def fsc_resolution(u, nbins: int = 64, fsc_threshold: float = 1.0 / 7.0) -> float:
@@ -78,8 +81,8 @@ def rl_stop(d, h, u0, max_iter: int, metric: str, threshold: float, reference=No
     """
     if metric not in METRICS:
         raise ValueError(f"metric must be one of {METRICS}")
-    if metric == "psnr" and reference is None:
-        raise ValueError("psnr needs a reference volume")
+    if metric in ("psnr", "ssim") and reference is None:
+        raise ValueError(f"{metric} needs a reference volume")
     d = np.asarray(d, dtype=np.float64)
     u = np.array(u0, dtype=np.float64, copy=True)
     K = otf(h)
@@ -100,6 +103,9 @@ def rl_stop(d, h, u0, max_iter: int, metric: str, threshold: float, reference=No
             stop = hist[-1] < threshold
         elif metric == "psnr":
             hist.append(psnr_si(u_new, reference))
+            stop = k >= 1 and hist[k] - hist[k - 1] < threshold
+        elif metric == "ssim":
+            hist.append(ssim_oracle.ssim(u_new, reference))
             stop = k >= 1 and hist[k] - hist[k - 1] < threshold
         elif metric == "fsc":
             hist.append(fsc_resolution(u_new, nbins, fsc_threshold))

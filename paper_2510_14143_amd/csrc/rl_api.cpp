@@ -275,6 +275,11 @@ struct rl_plan_s {
   double* fsc_part = nullptr;     // shell partials, fsc_cap shells
   double* fsc_out = nullptr;
   int fsc_cap = 0;
+  // structural similarity (allocated on first use)
+  double* ssim_a = nullptr;       // X window sums, 5 channels
+  double* ssim_b = nullptr;       // X and Y window sums
+  double* ssim_part = nullptr;    // per-work-group sums of window SSIMs
+  double* ssim_range = nullptr;   // [0] range of the reference, then range partials
   // batched volumes of this shape (a class of a batch plan); 1 for a single plan
   int count = 1;
   const float** d_tab = nullptr;  // device tables of per-volume pointers (count each)
@@ -395,6 +400,10 @@ void release(rl_plan p) {
   (void)hipFree(p->spec2);
   (void)hipFree(p->fsc_part);
   (void)hipFree(p->fsc_out);
+  (void)hipFree(p->ssim_a);
+  (void)hipFree(p->ssim_b);
+  (void)hipFree(p->ssim_part);
+  (void)hipFree(p->ssim_range);
   for (rl_plan c : p->classes) release(c);
   if (p->graph_full) (void)hipGraphExecDestroy(p->graph_full);
   if (p->graph_last) (void)hipGraphExecDestroy(p->graph_last);
@@ -1330,6 +1339,77 @@ rl_status iterate_impl(rl_plan p, const float* observed, float* estimate, int n_
   return enqueue_flux_reduce(p, n_iter, p->stream);
 }
 
+constexpr int kSsimRangeBlocks = 512;
+
+struct SsimGeom {
+  int64_t nxo, nyo, nzo, blocks;  // valid window positions; work-groups of the last pass
+};
+
+SsimGeom ssim_geom(rl_plan p) {
+  SsimGeom g;
+  g.nxo = p->vx - 6;
+  g.nyo = p->vy - 6;
+  g.nzo = p->vz - 6;
+  g.blocks = ((g.nxo + 255) / 256) * g.nyo * g.nzo;
+  return g;
+}
+
+rl_status ssim_buffers(rl_plan p) {
+  if (p->vz < 7 || p->vy < 7 || p->vx < 7)
+    return fail(RL_E_UNSUPPORTED, "SSIM needs every dimension >= 7 (7x7x7 windows)");
+  if (p->vy > 65535 + 6 || p->vz > 65535 + 6)
+    return fail(RL_E_UNSUPPORTED, "SSIM needs ny, nz <= 65541");
+  if (p->ssim_a) return RL_OK;
+  const SsimGeom g = ssim_geom(p);
+  hipError_t e;
+  if ((e = hipMalloc(&p->ssim_a, 5 * (size_t)p->vz * p->vy * g.nxo * sizeof(double))) !=
+          hipSuccess ||
+      (e = hipMalloc(&p->ssim_b, 5 * (size_t)p->vz * g.nyo * g.nxo * sizeof(double))) !=
+          hipSuccess ||
+      (e = hipMalloc(&p->ssim_part, (size_t)g.blocks * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&p->ssim_range, (1 + 2 * (size_t)kSsimRangeBlocks) * sizeof(double))) !=
+          hipSuccess) {
+    (void)hipFree(p->ssim_a);
+    (void)hipFree(p->ssim_b);
+    (void)hipFree(p->ssim_part);
+    p->ssim_a = p->ssim_b = p->ssim_part = nullptr;
+    return hip_fail(e, "hipMalloc(SSIM buffers)");
+  }
+  return RL_OK;
+}
+
+rl_status enqueue_ssim(rl_plan p, const float* u, const float* ref, bool want_range) {
+  hipError_t e = rlmi::launch_ssim(u, ref, (int)p->vz, (int)p->vy, (int)p->vx, p->ssim_a, p->ssim_b,
+                                   p->ssim_range + 1, kSsimRangeBlocks, p->ssim_range,
+                                   p->ssim_part, want_range, p->active_stop, p->stream);
+  return e == hipSuccess ? RL_OK : hip_fail(e, "SSIM launch");
+}
+
+rl_status ssim_impl(rl_plan p, const float* u, const float* ref, double* value) {
+  rl_status st = check_plan(p);
+  if (st != RL_OK) return st;
+  if (p->is_batch) return fail(RL_E_UNSUPPORTED, "rl_ssim takes a single-volume plan");
+  if (!value) return fail(RL_E_INVALID, "value is NULL");
+  const size_t bytes = (size_t)p->vnvox * sizeof(float);
+  int dev = p->device;
+  if ((st = check_dev_ptr(u, bytes, &dev, "u")) != RL_OK) return st;
+  if ((st = check_dev_ptr(ref, bytes, &dev, "reference")) != RL_OK) return st;
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if ((st = ssim_buffers(p)) != RL_OK) return st;
+  if ((st = enqueue_ssim(p, u, ref, true)) != RL_OK) return st;
+  const SsimGeom g = ssim_geom(p);
+  std::vector<double> h((size_t)g.blocks);
+  if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return hip_fail(e, "execution");
+  if ((e = hipMemcpy(h.data(), p->ssim_part, h.size() * sizeof(double), hipMemcpyDeviceToHost)) !=
+      hipSuccess)
+    return hip_fail(e, "hipMemcpy(SSIM)");
+  double t = 0.0;
+  for (double v : h) t += v;  // fixed order
+  *value = t / (double)(g.nxo * g.nyo * g.nzo);
+  return RL_OK;
+}
+
 // Metric-guided stopping: every launch of the call reads the plan's stop flag
 // and does nothing once the metric kernel has set it, so the whole call is
 // enqueued at once and ends early on the device without a host round trip.
@@ -1342,7 +1422,7 @@ rl_status iterate_stop_impl(rl_plan p, const float* observed, float* estimate, i
     return fail(RL_E_UNSUPPORTED, "stop rules are not available with extrapolation");
   if (!rule) return fail(RL_E_INVALID, "rule is NULL");
   if (rule->metric != RL_STOP_LOGLIK && rule->metric != RL_STOP_CHANGE &&
-      rule->metric != RL_STOP_PSNR)
+      rule->metric != RL_STOP_PSNR && rule->metric != RL_STOP_SSIM)
     return fail(RL_E_INVALID, "unknown stop metric");
   if (!std::isfinite(rule->threshold)) return fail(RL_E_INVALID, "threshold must be finite");
   if (rule->min_iter < 0) return fail(RL_E_INVALID, "min_iter must be >= 0");
@@ -1351,11 +1431,12 @@ rl_status iterate_stop_impl(rl_plan p, const float* observed, float* estimate, i
   int dev = p->device;
   if ((st = check_dev_ptr(observed, bytes, &dev, "observed")) != RL_OK) return st;
   if ((st = check_dev_ptr(estimate, bytes, &dev, "estimate")) != RL_OK) return st;
-  if (rule->metric == RL_STOP_PSNR &&
+  if ((rule->metric == RL_STOP_PSNR || rule->metric == RL_STOP_SSIM) &&
       (st = check_dev_ptr(rule->reference, bytes, &dev, "reference")) != RL_OK)
     return st;
   hipError_t e = hipSetDevice(p->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if (rule->metric == RL_STOP_SSIM && (st = ssim_buffers(p)) != RL_OK) return st;
   if ((st = ensure_flux_capacity(p, max_iter > 0 ? max_iter : 1, nullptr)) != RL_OK) return st;
   if ((e = hipMemsetAsync(p->stop, 0, 4 * sizeof(int), p->stream)) != hipSuccess)
     return hip_fail(e, "hipMemsetAsync(stop)");
@@ -1365,10 +1446,14 @@ rl_status iterate_stop_impl(rl_plan p, const float* observed, float* estimate, i
   if (max_iter == 0) return RL_OK;
   const int metric = rule->metric;
   const int groups = (int)p->x_grid.x;
+  const SsimGeom sg = ssim_geom(p);
   auto decide = [&](int it) -> rl_status {
-    hipError_t me = rlmi::launch_metric(p->met_partials, groups, metric, it, rule->threshold,
-                                        rule->min_iter, (long long)p->vnvox, p->mhist, p->stop,
-                                        p->stream);
+    const bool ssim = metric == RL_STOP_SSIM;
+    hipError_t me = rlmi::launch_metric(
+        ssim ? p->ssim_part : p->met_partials, ssim ? (int)sg.blocks : groups,
+        ssim ? rlmi::MET_SSIM : metric, it, rule->threshold, rule->min_iter,
+        ssim ? (long long)(sg.nxo * sg.nyo * sg.nzo) : (long long)p->vnvox, p->mhist, p->stop,
+        p->stream);
     return me == hipSuccess ? RL_OK : hip_fail(me, "metric launch");
   };
   p->active_stop = p->stop;
@@ -1390,13 +1475,17 @@ rl_status iterate_stop_impl(rl_plan p, const float* observed, float* estimate, i
     w.partials = p->partials;
     w.iter = it;
     w.do_fwd = it + 1 < max_iter ? 1 : 0;
-    if (metric != RL_STOP_LOGLIK) {
+    const bool fused = metric == RL_STOP_CHANGE || metric == RL_STOP_PSNR;
+    if (fused) {
       w.metric = metric == RL_STOP_CHANGE ? rlmi::MET_CHANGE : rlmi::MET_PSNR;
       w.met_partials = p->met_partials;
       w.ref = rule->reference;
     }
-    if ((st = run_x(p, metric == RL_STOP_LOGLIK ? rlmi::XM_UPDATE : rlmi::XM_UPDATE_MET, w,
-                    RL_KERNEL_X_UPDATE)) != RL_OK)
+    if ((st = run_x(p, fused ? rlmi::XM_UPDATE_MET : rlmi::XM_UPDATE, w, RL_KERNEL_X_UPDATE)) !=
+        RL_OK)
+      break;
+    if (metric == RL_STOP_SSIM &&
+        (st = enqueue_ssim(p, estimate, rule->reference, it == 0)) != RL_OK)
       break;
     if (metric != RL_STOP_LOGLIK && (st = decide(it)) != RL_OK) break;
     if (w.do_fwd && (st = run_yz_filter(p, false)) != RL_OK) break;
@@ -1845,6 +1934,14 @@ rl_status rl_plan_get_flux(rl_plan p, double* flux, int cap, int* n_written) {
     if (!std::isfinite(h[(size_t)i]))
       return fail(RL_E_NUMERIC, "non-finite flux at entry " + std::to_string(i));
   return RL_OK;
+}
+
+rl_status rl_ssim(rl_plan p, const float* u, const float* reference, double* value) {
+  try {
+    return ssim_impl(p, u, reference, value);
+  } catch (...) {
+    return fail(RL_E_INTERNAL, "unexpected exception in rl_ssim");
+  }
 }
 
 rl_status rl_fsc(rl_plan p, const float* a, const float* b, int nbins, double threshold,

@@ -57,7 +57,7 @@ struct PencilArgs {
 
 enum PencilMode { PM_FWD = 0, PM_INV = 1, PM_FKI = 2, PM_FCKI = 3 };
 // Stopping metrics (values of rl_stop_metric).
-enum Metric { MET_NONE = 0, MET_LOGLIK = 1, MET_CHANGE = 2, MET_PSNR = 3 };
+enum Metric { MET_NONE = 0, MET_LOGLIK = 1, MET_CHANGE = 2, MET_PSNR = 3, MET_SSIM = 4 };
 constexpr int kMetRows = 7;
 // XM_PREDICT and XM_UPDATE_ACC are the two X passes of the extrapolated
 // (Biggs-Andrews) iteration: the prediction y = max(x + alpha h, 0) transformed
@@ -153,12 +153,22 @@ hipError_t launch_accel_alpha(const double* acc_partials, int groups, int it, fl
                               hipEvent_t ev1 = nullptr);
 // Metric of iteration `it` from the work-group partials (rows: LOGLIK: sum of
 // d log q - q; CHANGE: sum (u' - u)^2, sum u^2; PSNR: sum u', u'^2, u' g, g, g^2,
-// min g, max g), stored in hist[it]; then the stop decision (see rl.h):
-// stop[0] = 1 and stop[1] = iterations carried out.  stop[2] = entries of hist.
+// min g, max g; SSIM: sum of window SSIMs, nvox = number of windows), stored in
+// hist[it]; then the stop decision (see rl.h): stop[0] = 1 and stop[1] =
+// iterations carried out.  stop[2] = entries of hist.
 // Does nothing once stop[0] is set.
 hipError_t launch_metric(const double* met_partials, int groups, int metric, int it,
                          double threshold, int min_iter, long long nvox, double* hist, int* stop,
                          hipStream_t s);
+// Mean-SSIM partials of u against g (dense nz x ny x nx, every dimension >= 7):
+// window sums along X into buf_a (5 * nz * ny * (nx-6) doubles), along Y into buf_b
+// (5 * nz * (ny-6) * (nx-6)), then along Z with the SSIM of each window summed per
+// work-group into part (ceil((nx-6)/256) * (ny-6) * (nz-6) doubles).  With
+// want_range, *range = max(g) - min(g) first (range_part: 2 * range_blocks).
+// If stop is non-null and *stop != 0 the kernels do nothing.
+hipError_t launch_ssim(const float* u, const float* g, int nz, int ny, int nx, double* buf_a,
+                       double* buf_b, double* range_part, int range_blocks, double* range,
+                       double* part, bool want_range, const int* stop, hipStream_t s);
 // a = u[0::2, 0::2, 0::2], b = u[1::2, 1::2, 1::2] of a dense nz x ny x nx volume
 // (even dimensions; a and b hold (nz/2)(ny/2)(nx/2) floats each).
 hipError_t launch_split_diag(const float* u, int nz, int ny, int nx, float* a, float* b,

@@ -869,7 +869,9 @@ __global__ void __launch_bounds__(256) k_metric(const double* __restrict__ mp, i
                                                 double* __restrict__ hist, int* __restrict__ stop) {
   if (stop[0]) return;
   const int tid = threadIdx.x;
-  const int rows = metric == MET_LOGLIK ? 1 : metric == MET_CHANGE ? 2 : kMetRows;
+  const int rows = (metric == MET_LOGLIK || metric == MET_SSIM) ? 1
+                   : metric == MET_CHANGE                        ? 2
+                                                                 : kMetRows;
   __shared__ double ws[kMetRows][4];
   for (int r = 0; r < rows; ++r) {
     const int op = (metric == MET_PSNR && r == 5) ? 1 : (metric == MET_PSNR && r == 6) ? 2 : 0;
@@ -906,6 +908,9 @@ __global__ void __launch_bounds__(256) k_metric(const double* __restrict__ mp, i
   } else if (metric == MET_CHANGE) {
     m = sqrt(s[0] / s[1]);
     halt = done >= min_iter && m < threshold;
+  } else if (metric == MET_SSIM) {
+    m = s[0] / (double)nvox;  // nvox: number of windows
+    halt = it >= 1 && done >= min_iter && m - hist[it - 1] < threshold;
   } else {
     const double n = (double)nvox;
     const double cuu = s[1] - s[0] * s[0] / n, cug = s[2] - s[0] * s[3] / n;
@@ -1079,6 +1084,142 @@ __global__ void __launch_bounds__(256) k_fsc_final(const double* __restrict__ pa
       }
     }
     out[4 * nb1] = res;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Structural similarity (7x7x7 windows lying inside the volume)
+// ---------------------------------------------------------------------------
+constexpr int kSsimWin = 7;
+
+// Per-block min and max of g; part[2 * block] = min, part[2 * block + 1] = max.
+__global__ void __launch_bounds__(256) k_range(const float* __restrict__ g, long long n,
+                                               double* __restrict__ part) {
+  double mn = 1.0e300, mx = -1.0e300;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (long long)gridDim.x * blockDim.x) {
+    const double v = g[t];
+    mn = fmin(mn, v);
+    mx = fmax(mx, v);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mn = fmin(mn, __shfl_xor(mn, off, 64));
+    mx = fmax(mx, __shfl_xor(mx, off, 64));
+  }
+  __shared__ double ws[2][4];
+  const int tid = threadIdx.x;
+  if ((tid & 63) == 0) {
+    ws[0][tid >> 6] = mn;
+    ws[1][tid >> 6] = mx;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) {
+      ws[0][0] = fmin(ws[0][0], ws[0][q]);
+      ws[1][0] = fmax(ws[1][0], ws[1][q]);
+    }
+    part[2 * blockIdx.x] = ws[0][0];
+    part[2 * blockIdx.x + 1] = ws[1][0];
+  }
+}
+
+// range[0] = max - min over the block partials (one thread, fixed order).
+__global__ void k_range_final(const double* __restrict__ part, int blocks,
+                              double* __restrict__ range) {
+  if (threadIdx.x != 0) return;
+  double mn = part[0], mx = part[1];
+  for (int b = 1; b < blocks; ++b) {
+    mn = fmin(mn, part[2 * b]);
+    mx = fmax(mx, part[2 * b + 1]);
+  }
+  range[0] = mx - mn;
+}
+
+// X window sums of u, g, u^2, g^2, u g (FP64) for every row and every x0 whose
+// window [x0, x0 + 7) lies inside the row: out[c][z][y][x0], c = 0..4.
+__global__ void __launch_bounds__(256) k_ssim_x(const float* __restrict__ u,
+                                                const float* __restrict__ g, int nz, int ny,
+                                                int nx, double* __restrict__ out,
+                                                const int* stop) {
+  if (stop && *stop) return;
+  const int nxo = nx - kSsimWin + 1;
+  const int x0 = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+  if (x0 >= nxo) return;
+  const long long row = ((long long)z * ny + y) * nx + x0;
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < kSsimWin; ++k) {
+    const double a = u[row + k], b = g[row + k];
+    s[0] += a;
+    s[1] += b;
+    s[2] += a * a;
+    s[3] += b * b;
+    s[4] += a * b;
+  }
+  const long long plane = (long long)nz * ny * nxo;
+  const long long o = ((long long)z * ny + y) * nxo + x0;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) out[c * plane + o] = s[c];
+}
+
+// Y window sums of the five X sums: in[c][z][y][x0] (ny rows) -> out[c][z][y0][x0].
+__global__ void __launch_bounds__(256) k_ssim_y(const double* __restrict__ in, int nz, int ny,
+                                                int nxo, double* __restrict__ out,
+                                                const int* stop) {
+  if (stop && *stop) return;
+  const int nyo = ny - kSsimWin + 1;
+  const int x0 = blockIdx.x * blockDim.x + threadIdx.x, y0 = blockIdx.y, z = blockIdx.z;
+  if (x0 >= nxo) return;
+  const long long pin = (long long)nz * ny * nxo, pout = (long long)nz * nyo * nxo;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < kSsimWin; ++k) t += in[c * pin + ((long long)z * ny + y0 + k) * nxo + x0];
+    out[c * pout + ((long long)z * nyo + y0) * nxo + x0] = t;
+  }
+}
+
+// Z window sums, then the SSIM of each window (sample statistics, W = 343,
+// C1 = (0.01 L)^2, C2 = (0.03 L)^2 with L = *range) and a per-block FP64 partial
+// sum into part[block].
+__global__ void __launch_bounds__(256) k_ssim_z(const double* __restrict__ in, int nz, int nyo,
+                                                int nxo, const double* __restrict__ range,
+                                                double* __restrict__ part, const int* stop) {
+  if (stop && *stop) return;
+  const int nzo = nz - kSsimWin + 1;
+  const int x0 = blockIdx.x * blockDim.x + threadIdx.x, y0 = blockIdx.y, z0 = blockIdx.z;
+  const long long pin = (long long)nz * nyo * nxo;
+  double val = 0.0;
+  if (x0 < nxo) {
+    double s[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < kSsimWin; ++k)
+        t += in[c * pin + ((long long)(z0 + k) * nyo + y0) * nxo + x0];
+      s[c] = t;
+    }
+    const double W = (double)(kSsimWin * kSsimWin * kSsimWin), cn = W / (W - 1.0);
+    const double mu = s[0] / W, mg = s[1] / W;
+    const double vu = cn * (s[2] / W - mu * mu), vg = cn * (s[3] / W - mg * mg);
+    const double cug = cn * (s[4] / W - mu * mg);
+    const double L = range[0], c1 = (0.01 * L) * (0.01 * L), c2 = (0.03 * L) * (0.03 * L);
+    val = ((2.0 * mu * mg + c1) * (2.0 * cug + c2)) / ((mu * mu + mg * mg + c1) * (vu + vg + c2));
+  }
+  (void)nzo;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) val += __shfl_xor(val, off, 64);
+  __shared__ double ws[4];
+  const int tid = threadIdx.x;
+  if ((tid & 63) == 0) ws[tid >> 6] = val;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += ws[q];
+    part[((long long)z0 * nyo + y0) * gridDim.x + blockIdx.x] = t;
   }
 }
 
@@ -1353,6 +1494,30 @@ hipError_t launch_metric(const double* met_partials, int groups, int metric, int
                          hipStream_t s) {
   hipLaunchKernelGGL(k_metric, dim3(1), dim3(256), 0, s, met_partials, groups, metric, it,
                      threshold, min_iter, nvox, hist, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_ssim(const float* u, const float* g, int nz, int ny, int nx, double* buf_a,
+                       double* buf_b, double* range_part, int range_blocks, double* range,
+                       double* part, bool want_range, const int* stop, hipStream_t s) {
+  const long long n = (long long)nz * ny * nx;
+  const int nxo = nx - kSsimWin + 1, nyo = ny - kSsimWin + 1, nzo = nz - kSsimWin + 1;
+  const unsigned bx = (unsigned)((nxo + 255) / 256);
+  hipError_t e;
+  if (want_range) {
+    hipLaunchKernelGGL(k_range, dim3((unsigned)range_blocks), dim3(256), 0, s, g, n, range_part);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_range_final, dim3(1), dim3(64), 0, s, range_part, range_blocks, range);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_ssim_x, dim3(bx, (unsigned)ny, (unsigned)nz), dim3(256), 0, s, u, g, nz, ny,
+                     nx, buf_a, stop);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ssim_y, dim3(bx, (unsigned)nyo, (unsigned)nz), dim3(256), 0, s, buf_a, nz,
+                     ny, nxo, buf_b, stop);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ssim_z, dim3(bx, (unsigned)nyo, (unsigned)nzo), dim3(256), 0, s, buf_b, nz,
+                     nyo, nxo, range, part, stop);
   return hipGetLastError();
 }
 

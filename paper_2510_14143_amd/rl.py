@@ -27,8 +27,9 @@ RL_PRECISION_FP32, RL_PRECISION_SPLIT_BF16, RL_PRECISION_SPLIT_FP16 = 0, 1, 2
 _PRECISIONS = {"fp32": RL_PRECISION_FP32, "split_bf16": RL_PRECISION_SPLIT_BF16,
                "split_fp16": RL_PRECISION_SPLIT_FP16}
 RL_ACCEL_NONE, RL_ACCEL_BIGGS_ANDREWS = 0, 1
-RL_STOP_LOGLIK, RL_STOP_CHANGE, RL_STOP_PSNR = 1, 2, 3
-_STOP_METRICS = {"loglik": RL_STOP_LOGLIK, "change": RL_STOP_CHANGE, "psnr": RL_STOP_PSNR}
+RL_STOP_LOGLIK, RL_STOP_CHANGE, RL_STOP_PSNR, RL_STOP_SSIM = 1, 2, 3, 4
+_STOP_METRICS = {"loglik": RL_STOP_LOGLIK, "change": RL_STOP_CHANGE, "psnr": RL_STOP_PSNR,
+                 "ssim": RL_STOP_SSIM}
 _ACCELS = {"none": RL_ACCEL_NONE, "biggs_andrews": RL_ACCEL_BIGGS_ANDREWS}
 KERNEL_KINDS = ("x_r2c", "x_c2r", "x_ratio", "x_update", "y", "z_otf", "z", "other")
 
@@ -83,6 +84,7 @@ def lib() -> ctypes.CDLL:
         "rl_plan_get_info": ([vp, i64p, i64p], ctypes.c_int),
         "rl_plan_get_grid": ([vp, i64p], ctypes.c_int),
         "rl_iterate_stop": ([vp, vp, vp, ctypes.c_int, ctypes.POINTER(_StopRule)], ctypes.c_int),
+        "rl_ssim": ([vp, vp, vp, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "rl_fsc": ([vp, vp, vp, ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                     ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "rl_split_diagonal": ([vp, i64p, vp, vp, vp], ctypes.c_int),
@@ -229,6 +231,13 @@ def rl_plan_get_stop(plan: int):
     _check(lib().rl_plan_get_stop(ctypes.c_void_p(plan), ctypes.byref(n_done), buf, n_hist.value,
                                   ctypes.byref(n_hist)))
     return n_done.value, np.array(buf[: n_hist.value], dtype=np.float64)
+
+
+def rl_ssim(plan: int, u_ptr: int, ref_ptr: int) -> float:
+    v = ctypes.c_double(0.0)
+    _check(lib().rl_ssim(ctypes.c_void_p(plan), ctypes.c_void_p(u_ptr), ctypes.c_void_p(ref_ptr),
+                         ctypes.byref(v)))
+    return v.value
 
 
 def rl_fsc(plan: int, a_ptr: int, b_ptr: int, nbins: int = 64, threshold: float = 1.0 / 7.0):
@@ -383,16 +392,16 @@ class Plan:
     def iterate_until(self, observed, estimate, max_iter: int, metric: str, threshold: float,
                       min_iter: int = 0, reference=None) -> None:
         """At most max_iter iterations, stopped on the device by `metric` ("loglik",
-        "change" or "psnr" against `reference`); results via stop() and flux()."""
+        "change", or "psnr" / "ssim" against `reference`); results via stop() and flux()."""
         self._live()
         _check_volume(observed, self.shape, self.device, "observed")
         _check_volume(estimate, self.shape, self.device, "estimate")
         if metric not in _STOP_METRICS:
             raise ValueError(f"metric must be one of {sorted(_STOP_METRICS)}")
         ref_ptr = 0
-        if metric == "psnr":
+        if metric in ("psnr", "ssim"):
             if reference is None:
-                raise ValueError("psnr needs a reference volume")
+                raise ValueError(f"{metric} needs a reference volume")
             _check_volume(reference, self.shape, self.device, "reference")
             ref_ptr = reference.data_ptr()
         self._bind_stream()
@@ -432,6 +441,14 @@ class Plan:
         self._live()
         self._bind_stream()
         return rl_plan_get_stop(self.handle)
+
+    def ssim(self, u, reference) -> float:
+        """Mean SSIM (7x7x7 windows) of u against the reference (synchronises)."""
+        self._live()
+        _check_volume(u, self.shape, self.device, "u")
+        _check_volume(reference, self.shape, self.device, "reference")
+        self._bind_stream()
+        return rl_ssim(self.handle, u.data_ptr(), reference.data_ptr())
 
     def fsc(self, a, b, nbins: int = 64, threshold: float = 1.0 / 7.0):
         """FSC curve of volumes a and b and the resolution crossing (synchronises)."""

@@ -157,6 +157,12 @@ def test_fsc_and_split_validation():
     assert L.rl_split_diagonal(None, None, None, None, None) == rl.RL_E_INVALID
 
 
+def test_ssim_checks_handle():
+    L = rl.lib()
+    v = ctypes.c_double()
+    assert L.rl_ssim(ctypes.c_void_p(0x1234560), None, None, ctypes.byref(v)) == rl.RL_E_INVALID
+
+
 def test_alpha_query_checks_handle():
     L = rl.lib()
     n = ctypes.c_int()
