@@ -1350,7 +1350,7 @@ SsimGeom ssim_geom(rl_plan p) {
   g.nxo = p->vx - 6;
   g.nyo = p->vy - 6;
   g.nzo = p->vz - 6;
-  g.blocks = ((g.nxo + 255) / 256) * g.nyo * g.nzo;
+  g.blocks = ((g.nxo + 255) / 256) * g.nyo * ((g.nzo + 31) / 32);
   return g;
 }
 

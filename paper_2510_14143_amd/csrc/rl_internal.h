@@ -163,7 +163,7 @@ hipError_t launch_metric(const double* met_partials, int groups, int metric, int
 // Mean-SSIM partials of u against g (dense nz x ny x nx, every dimension >= 7):
 // window sums along X into buf_a (5 * nz * ny * (nx-6) doubles), along Y into buf_b
 // (5 * nz * (ny-6) * (nx-6)), then along Z with the SSIM of each window summed per
-// work-group into part (ceil((nx-6)/256) * (ny-6) * (nz-6) doubles).  With
+// work-group into part (ceil((nx-6)/256) * (ny-6) * ceil((nz-6)/32) doubles).  With
 // want_range, *range = max(g) - min(g) first (range_part: 2 * range_blocks).
 // If stop is non-null and *stop != 0 the kernels do nothing.
 hipError_t launch_ssim(const float* u, const float* g, int nz, int ny, int nx, double* buf_a,

@@ -1164,52 +1164,69 @@ __global__ void __launch_bounds__(256) k_ssim_x(const float* __restrict__ u,
 }
 
 // Y window sums of the five X sums: in[c][z][y][x0] (ny rows) -> out[c][z][y0][x0].
+// Each thread slides a window over kSsimChunk consecutive outputs (running sums),
+// so each input is read about once instead of seven times.
+constexpr int kSsimChunk = 32;
 __global__ void __launch_bounds__(256) k_ssim_y(const double* __restrict__ in, int nz, int ny,
                                                 int nxo, double* __restrict__ out,
                                                 const int* stop) {
   if (stop && *stop) return;
   const int nyo = ny - kSsimWin + 1;
-  const int x0 = blockIdx.x * blockDim.x + threadIdx.x, y0 = blockIdx.y, z = blockIdx.z;
+  const int x0 = blockIdx.x * blockDim.x + threadIdx.x, z = blockIdx.z;
+  const int ya = blockIdx.y * kSsimChunk, yb = min(ya + kSsimChunk, nyo);
   if (x0 >= nxo) return;
   const long long pin = (long long)nz * ny * nxo, pout = (long long)nz * nyo * nxo;
-#pragma unroll
   for (int c = 0; c < 5; ++c) {
+    const double* src = in + c * pin + (long long)z * ny * nxo + x0;
+    double* dst = out + c * pout + (long long)z * nyo * nxo + x0;
     double t = 0.0;
-#pragma unroll
-    for (int k = 0; k < kSsimWin; ++k) t += in[c * pin + ((long long)z * ny + y0 + k) * nxo + x0];
-    out[c * pout + ((long long)z * nyo + y0) * nxo + x0] = t;
+    for (int k = 0; k < kSsimWin; ++k) t += src[(long long)(ya + k) * nxo];
+    dst[(long long)ya * nxo] = t;
+    for (int y0 = ya + 1; y0 < yb; ++y0) {
+      t += src[(long long)(y0 + kSsimWin - 1) * nxo] - src[(long long)(y0 - 1) * nxo];
+      dst[(long long)y0 * nxo] = t;
+    }
   }
 }
 
-// Z window sums, then the SSIM of each window (sample statistics, W = 343,
-// C1 = (0.01 L)^2, C2 = (0.03 L)^2 with L = *range) and a per-block FP64 partial
-// sum into part[block].
+// Z window sums (sliding over kSsimChunk outputs per thread), then the SSIM of
+// each window (sample statistics, W = 343, C1 = (0.01 L)^2, C2 = (0.03 L)^2 with
+// L = *range) summed per work-group into
+// part[(blockIdx.z * nyo + y0) * gridDim.x + blockIdx.x].
 __global__ void __launch_bounds__(256) k_ssim_z(const double* __restrict__ in, int nz, int nyo,
                                                 int nxo, const double* __restrict__ range,
                                                 double* __restrict__ part, const int* stop) {
   if (stop && *stop) return;
   const int nzo = nz - kSsimWin + 1;
-  const int x0 = blockIdx.x * blockDim.x + threadIdx.x, y0 = blockIdx.y, z0 = blockIdx.z;
-  const long long pin = (long long)nz * nyo * nxo;
+  const int x0 = blockIdx.x * blockDim.x + threadIdx.x, y0 = blockIdx.y;
+  const int za = blockIdx.z * kSsimChunk, zb = min(za + kSsimChunk, nzo);
+  const long long pin = (long long)nz * nyo * nxo, zs = (long long)nyo * nxo;
   double val = 0.0;
   if (x0 < nxo) {
+    const double* src = in + (long long)y0 * nxo + x0;
     double s[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       double t = 0.0;
-#pragma unroll
-      for (int k = 0; k < kSsimWin; ++k)
-        t += in[c * pin + ((long long)(z0 + k) * nyo + y0) * nxo + x0];
+      for (int k = 0; k < kSsimWin; ++k) t += src[c * pin + (long long)(za + k) * zs];
       s[c] = t;
     }
     const double W = (double)(kSsimWin * kSsimWin * kSsimWin), cn = W / (W - 1.0);
-    const double mu = s[0] / W, mg = s[1] / W;
-    const double vu = cn * (s[2] / W - mu * mu), vg = cn * (s[3] / W - mg * mg);
-    const double cug = cn * (s[4] / W - mu * mg);
     const double L = range[0], c1 = (0.01 * L) * (0.01 * L), c2 = (0.03 * L) * (0.03 * L);
-    val = ((2.0 * mu * mg + c1) * (2.0 * cug + c2)) / ((mu * mu + mg * mg + c1) * (vu + vg + c2));
+    for (int z0 = za; z0 < zb; ++z0) {
+      if (z0 > za) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c)
+          s[c] += src[c * pin + (long long)(z0 + kSsimWin - 1) * zs] -
+                  src[c * pin + (long long)(z0 - 1) * zs];
+      }
+      const double mu = s[0] / W, mg = s[1] / W;
+      const double vu = cn * (s[2] / W - mu * mu), vg = cn * (s[3] / W - mg * mg);
+      const double cug = cn * (s[4] / W - mu * mg);
+      val += ((2.0 * mu * mg + c1) * (2.0 * cug + c2)) /
+             ((mu * mu + mg * mg + c1) * (vu + vg + c2));
+    }
   }
-  (void)nzo;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) val += __shfl_xor(val, off, 64);
   __shared__ double ws[4];
@@ -1219,7 +1236,7 @@ __global__ void __launch_bounds__(256) k_ssim_z(const double* __restrict__ in, i
   if (tid == 0) {
     double t = 0.0;
     for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += ws[q];
-    part[((long long)z0 * nyo + y0) * gridDim.x + blockIdx.x] = t;
+    part[((long long)blockIdx.z * nyo + y0) * gridDim.x + blockIdx.x] = t;
   }
 }
 
@@ -1513,11 +1530,13 @@ hipError_t launch_ssim(const float* u, const float* g, int nz, int ny, int nx, d
   hipLaunchKernelGGL(k_ssim_x, dim3(bx, (unsigned)ny, (unsigned)nz), dim3(256), 0, s, u, g, nz, ny,
                      nx, buf_a, stop);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_ssim_y, dim3(bx, (unsigned)nyo, (unsigned)nz), dim3(256), 0, s, buf_a, nz,
-                     ny, nxo, buf_b, stop);
+  const unsigned cy = (unsigned)((nyo + kSsimChunk - 1) / kSsimChunk);
+  const unsigned cz = (unsigned)((nzo + kSsimChunk - 1) / kSsimChunk);
+  hipLaunchKernelGGL(k_ssim_y, dim3(bx, cy, (unsigned)nz), dim3(256), 0, s, buf_a, nz, ny, nxo,
+                     buf_b, stop);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_ssim_z, dim3(bx, (unsigned)nyo, (unsigned)nzo), dim3(256), 0, s, buf_b, nz,
-                     nyo, nxo, range, part, stop);
+  hipLaunchKernelGGL(k_ssim_z, dim3(bx, (unsigned)nyo, cz), dim3(256), 0, s, buf_b, nz, nyo, nxo,
+                     range, part, stop);
   return hipGetLastError();
 }
 
