@@ -1481,8 +1481,10 @@ rl_status iterate_stop_impl(rl_plan p, const float* observed, float* estimate, i
       w.met_partials = p->met_partials;
       w.ref = rule->reference;
     }
-    if ((st = run_x(p, fused ? rlmi::XM_UPDATE_MET : rlmi::XM_UPDATE, w, RL_KERNEL_X_UPDATE)) !=
-        RL_OK)
+    const int umode = !fused                    ? rlmi::XM_UPDATE
+                      : metric == RL_STOP_CHANGE ? rlmi::XM_UPDATE_CHG
+                                                 : rlmi::XM_UPDATE_PSNR;
+    if ((st = run_x(p, umode, w, RL_KERNEL_X_UPDATE)) != RL_OK)
       break;
     if (metric == RL_STOP_SSIM &&
         (st = enqueue_ssim(p, estimate, rule->reference, it == 0)) != RL_OK)

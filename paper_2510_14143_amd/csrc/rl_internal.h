@@ -69,8 +69,9 @@ enum XMode {
   XM_UPDATE = 3,
   XM_PREDICT = 4,
   XM_UPDATE_ACC = 5,
-  XM_RATIO_LL = 6,   // XM_RATIO that also accumulates the log-likelihood (MET_LOGLIK)
-  XM_UPDATE_MET = 7  // XM_UPDATE that also accumulates MET_CHANGE or MET_PSNR sums
+  XM_RATIO_LL = 6,    // XM_RATIO that also accumulates the log-likelihood (MET_LOGLIK)
+  XM_UPDATE_CHG = 7,  // XM_UPDATE that also accumulates the MET_CHANGE sums
+  XM_UPDATE_PSNR = 8  // XM_UPDATE that also accumulates the MET_PSNR sums
 };
 
 // Arguments of an X-row pass (contiguous axis, real <-> half spectrum).
@@ -104,8 +105,8 @@ struct XArgs {
   double* acc_partials;  // XM_UPDATE_ACC: [2][work-group] FP64 partials of
                          // <g_k, g_{k-1}> and <g_{k-1}, g_{k-1}>
   // Metric-guided stopping (single volume): if stop is non-null and *stop != 0
-  // the launch does nothing.  XM_RATIO_LL (log-likelihood) and XM_UPDATE_MET
-  // (metric = MET_CHANGE or MET_PSNR) accumulate FP64 work-group partials into
+  // the launch does nothing.  XM_RATIO_LL, XM_UPDATE_CHG and XM_UPDATE_PSNR
+  // accumulate their metric's work-group partials (FP64) into
   // met_partials[row * gridDim.x + work-group] (rows as for launch_metric).
   const int* stop;
   int metric;

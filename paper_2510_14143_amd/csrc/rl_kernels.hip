@@ -693,7 +693,7 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
     // the metric variants of the ratio and update passes are separate kernels so
     // that the plain ones keep their register budget
     constexpr bool kRatio = MODE == XM_RATIO || MODE == XM_RATIO_LL;
-    constexpr bool kUpdate = MODE == XM_UPDATE || MODE == XM_UPDATE_MET;
+    constexpr bool kUpdate = MODE == XM_UPDATE || MODE == XM_UPDATE_CHG || MODE == XM_UPDATE_PSNR;
     float2 w[(kRatio || kUpdate || kAcc) ? E : 1];
     float2 hv[kAcc ? E : 1], gv[kAcc ? E : 1];
 #pragma unroll
@@ -731,24 +731,24 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
 #pragma unroll
       for (int m = 0; m < E; ++m) store_pair(rout, i + P * m, vx, rv, v[m]);
     } else if constexpr (kRatio) {
-      double ll = 0.0;  // Poisson log-likelihood of the caller's voxels (XM_RATIO_LL)
+      // Poisson log-likelihood of the caller's voxels (XM_RATIO_LL): FP32 terms and
+      // per-thread sums, FP64 across threads
+      float ll = 0.f;
       constexpr bool want_ll = MODE == XM_RATIO_LL;
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const float2 q = v[m];
         if (want_ll && rv) {
           const int x0 = 2 * (i + P * m);
-          if (x0 < vx && q.x > 1e-12f)
-            ll += (w[m].x > 0.f ? (double)w[m].x * log((double)q.x) : 0.0) - (double)q.x;
-          if (x0 + 1 < vx && q.y > 1e-12f)
-            ll += (w[m].y > 0.f ? (double)w[m].y * log((double)q.y) : 0.0) - (double)q.y;
+          if (x0 < vx && q.x > 1e-12f) ll += (w[m].x > 0.f ? w[m].x * logf(q.x) : 0.f) - q.x;
+          if (x0 + 1 < vx && q.y > 1e-12f) ll += (w[m].y > 0.f ? w[m].y * logf(q.y) : 0.f) - q.y;
         }
         v[m] = make_float2(q.x > 1e-12f ? w[m].x / q.x : 0.f, q.y > 1e-12f ? w[m].y / q.y : 0.f);
       }
       wave_sync();  // row buffer reuse
       r2c_store<E, PREC>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
       if constexpr (want_ll) {
-        double r[1] = {ll};
+        double r[1] = {(double)ll};
         constexpr int ops[1] = {0};
         wg_reduce_rows<1>(r, ops, a.met_partials);
       }
@@ -800,11 +800,9 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
     } else {  // XM_UPDATE
       float* ur = (a.u_tab ? a.u_tab[vol] : a.u) + rr * vx;
       double acc = 0.0;
-      // stopping metrics of the new estimate (MET_CHANGE / MET_PSNR)
-      double met[kMetRows] = {0.0, 0.0, 0.0, 0.0, 0.0, 1.0e300, -1.0e300};
-      constexpr bool kMet = MODE == XM_UPDATE_MET;
-      const bool want_change = kMet && a.metric == MET_CHANGE;
-      const bool want_psnr = kMet && a.metric == MET_PSNR;
+      // stopping metrics of the new estimate: FP32 per-thread sums, FP64 across threads
+      constexpr bool want_change = MODE == XM_UPDATE_CHG, want_psnr = MODE == XM_UPDATE_PSNR;
+      float met[kMetRows] = {0.f, 0.f, 0.f, 0.f, 0.f, 3.0e38f, -3.0e38f};
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const float2 c = v[m];
@@ -814,24 +812,26 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
                                       w[m].y * (c.y < 0.f ? 0.f : c.y));
         store_pair(ur, i + P * m, vx, rv, un);
         acc += (double)un.x + (double)un.y;
-        if (want_change) {
-          const double dx = (double)un.x - (double)w[m].x, dy = (double)un.y - (double)w[m].y;
+        if constexpr (want_change) {
+          const float dx = un.x - w[m].x, dy = un.y - w[m].y;
           met[0] += dx * dx + dy * dy;
-          met[1] += (double)w[m].x * (double)w[m].x + (double)w[m].y * (double)w[m].y;
-        } else if (want_psnr && rv) {
-          const float2 g = load_pair(a.ref + rr * vx, i + P * m, vx, true);
-          const int x0 = 2 * (i + P * m);
+          met[1] += w[m].x * w[m].x + w[m].y * w[m].y;
+        } else if constexpr (want_psnr) {
+          if (rv) {
+            const float2 g = load_pair(a.ref + rr * vx, i + P * m, vx, true);
+            const int x0 = 2 * (i + P * m);
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            if (x0 + h < vx) {
-              const double uu = h ? un.y : un.x, gg = h ? g.y : g.x;
-              met[0] += uu;
-              met[1] += uu * uu;
-              met[2] += uu * gg;
-              met[3] += gg;
-              met[4] += gg * gg;
-              met[5] = fmin(met[5], gg);
-              met[6] = fmax(met[6], gg);
+            for (int h = 0; h < 2; ++h) {
+              if (x0 + h < vx) {
+                const float uu = h ? un.y : un.x, gg = h ? g.y : g.x;
+                met[0] += uu;
+                met[1] += uu * uu;
+                met[2] += uu * gg;
+                met[3] += gg;
+                met[4] += gg * gg;
+                met[5] = fminf(met[5], gg);
+                met[6] = fmaxf(met[6], gg);
+              }
             }
           }
         }
@@ -854,9 +854,18 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
         const int it = a.iter_ptr ? *a.iter_ptr : a.iter;
         a.partials[((long long)it * a.nvol + vol) * gridDim.x + blockIdx.x] = t;
       }
-      if constexpr (kMet) {
+      if constexpr (want_change) {
+        double r[2] = {(double)met[0], (double)met[1]};
+        constexpr int ops[2] = {0, 0};
+        wg_reduce_rows<2>(r, ops, a.met_partials);
+      } else if constexpr (want_psnr) {
+        double r[kMetRows];
+#pragma unroll
+        for (int q = 0; q < kMetRows; ++q) r[q] = (double)met[q];
+        r[5] = met[5] >= 3.0e38f ? 1.0e300 : r[5];
+        r[6] = met[6] <= -3.0e38f ? -1.0e300 : r[6];
         constexpr int ops[kMetRows] = {0, 0, 0, 0, 0, 1, 2};
-        wg_reduce_rows<kMetRows>(met, ops, a.met_partials);
+        wg_reduce_rows<kMetRows>(r, ops, a.met_partials);
       }
     }
   }
@@ -1497,8 +1506,10 @@ hipError_t launch_xrow(int mode, int E, int prec, dim3 grid, dim3 block, size_t 
     case XM_UPDATE: return xrow_e<XM_UPDATE>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
     case XM_RATIO_LL:
       return xrow_e<XM_RATIO_LL>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
-    case XM_UPDATE_MET:
-      return xrow_e<XM_UPDATE_MET>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
+    case XM_UPDATE_CHG:
+      return xrow_e<XM_UPDATE_CHG>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
+    case XM_UPDATE_PSNR:
+      return xrow_e<XM_UPDATE_PSNR>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
     case XM_PREDICT: return xrow_e<XM_PREDICT>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
     case XM_UPDATE_ACC:
       return xrow_e<XM_UPDATE_ACC>(E, prec, grid, block, lds, s, a, sc, tw, ev0, ev1);
