@@ -107,3 +107,37 @@ def test_small_psf_with_odd_lengths(torch):
     with rl.Plan(dev(torch, h), shape=shape) as p:
         got = p.conv(dev(torch, x)).cpu().numpy()
     assert oracle.rel_l2(got, bo.conv_periodic(x, h)) <= 1e-5
+
+
+@pytest.mark.parametrize("shape", [(2, 1024, 2048), (1024, 2, 2048), (1, 4, 3072), (3, 960, 8),
+                                   (2, 2, 2560)])
+def test_conv_maximum_lengths_sampled(torch, shape):
+    # the longest transforms per axis (nx 2048, 3072 = 24 * 128, 2560 = 20 * 128 split over
+    # 64 threads; ny, nz 1024 and 960 = 15 * 64), sampled voxels by the direct sum
+    say("max conv", shape)
+    x = synth.uniform_volume(shape, 407)
+    rng = np.random.default_rng(408)
+    psf = np.zeros(shape, np.float32)
+    for _ in range(40):  # a sparse, asymmetric PSF keeps the direct sums cheap
+        psf[tuple(int(rng.integers(0, n)) for n in shape)] += float(rng.uniform(0.1, 1.0))
+    with rl.Plan(dev(torch, psf)) as p:
+        got = p.conv(dev(torch, x)).cpu().numpy()
+    pts = [tuple(int(rng.integers(0, n)) for n in shape) for _ in range(8)]
+    pts += [(0, 0, 0), tuple(n - 1 for n in shape)]
+    ref = oracle.conv_direct_at(x, psf, pts)
+    g = np.array([got[q] for q in pts])
+    assert np.max(np.abs(g - ref) / np.abs(ref)) <= 1e-5
+
+
+def test_batch_with_odd_radix_shapes(torch):
+    shapes = [(10, 20, 40), (7, 14, 28), (10, 20, 40), (9, 18, 36)]
+    say("batch odd radices")
+    cases = [synth.small_case(s, sigma_xyz=(1.2, 1.2, 2.0), seed=409 + k) for k, s in enumerate(shapes)]
+    with rl.BatchPlan([dev(torch, c["psf"]) for c in cases]) as b:
+        ds = [dev(torch, c["d"]) for c in cases]
+        us = [dev(torch, c["u0"]) for c in cases]
+        b.iterate(ds, us, 12)
+        got = [u.cpu().numpy() for u in us]
+    for c, g in zip(cases, got):
+        ref, _, _ = oracle.rl(c["d"], c["psf"], c["u0"], 12)
+        assert oracle.rel_l2(g, ref) <= 1e-4
