@@ -744,11 +744,14 @@ rl_status time_ms(rl_plan p, F fn, float* ms) {
     (void)hipEventDestroy(a);
     return hip_fail(hipGetLastError(), "hipEventCreate");
   }
+  // bursts of back-to-back launches: an event pair around a single short launch
+  // mostly measures the events themselves
+  constexpr int kBurst = 8;
   rl_status st = fn();  // warm-up
   float t[3] = {0, 0, 0};
   for (int r = 0; r < 3 && st == RL_OK; ++r) {
     (void)hipEventRecord(a, p->stream);
-    st = fn();
+    for (int k = 0; k < kBurst && st == RL_OK; ++k) st = fn();
     (void)hipEventRecord(b, p->stream);
     if (hipEventSynchronize(b) != hipSuccess) st = hip_fail(hipGetLastError(), "tuning run");
     else (void)hipEventElapsedTime(&t[r], a, b);
