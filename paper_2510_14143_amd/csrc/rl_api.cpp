@@ -622,6 +622,8 @@ bool configure_x(rl_plan p, int x_e) {
   if (ax.P > 64 || 64 % ax.P != 0) return false;
   const int rows_per_wave = 64 / ax.P;
   const int rs = (int)(p->M + 1 + ((p->M + 1) >> rlmi::kXPad) + 1);  // padded row
+  // split precision stages 16-byte granules in each wave's rows: keep them aligned
+  if (p->precision != RL_PRECISION_FP32 && (rows_per_wave * rs) % 2 != 0) return false;
   auto lds_for = [&](int w) {
     return (size_t)(2 * p->M + (int64_t)w * rows_per_wave * rs) * sizeof(float2);
   };

@@ -265,8 +265,17 @@ struct SplitT<2> {  // FP16 hi/lo with a power-of-two scale per DFT
   }
 };
 
+// Staging slot (in float4 units) of 16-byte granule G (0..7) of row t: rows of 32
+// floats, granules XOR-swizzled by f(t) = (t ^ t >> 3) & 7, which takes distinct
+// values on every 8 consecutive rows and, within 16 consecutive rows, on the even
+// and on the odd ones.  A row's granules, and one granule across 8 or 16 rows, thus
+// fall into distinct LDS banks with 128-byte and with 256-byte bank spans.
+// Granules 0..3 hold the real parts of a 16-point pencil, 4..7 the imaginary ones.
+__device__ __forceinline__ int stg_q(int t, int G) { return 8 * t + (G ^ ((t ^ (t >> 3)) & 7)); }
+
 // y[0..15] of every thread of the wavefront <- its 16-point DFT (sign S).
-// `stg` is a wave-private LDS area of 64 * 32 floats; all 64 lanes must call.
+// `stg` is a wave-private, 16-byte aligned LDS area of 64 * 32 floats; all 64
+// lanes must call.
 template <int PREC, int S>
 __device__ __forceinline__ void dft16_mfma(float2 (&y)[16], float* stg) {
   typedef SplitT<PREC> ST;
@@ -288,22 +297,22 @@ __device__ __forceinline__ void dft16_mfma(float2 (&y)[16], float* stg) {
     aim_hi[q] = aih;
     aim_lo[q] = (T)(ai - (float)aih);
   }
-  // stage the inputs: thread t's (re_0..15, im_0..15) at stg[32 t ..]
-  float* mine = stg + 32 * l;
+  float4* s4 = reinterpret_cast<float4*>(stg);
+  // stage the inputs: thread t's (re_0..15, im_0..15) in row t
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    mine[j] = y[j].x;
-    mine[16 + j] = y[j].y;
+  for (int G = 0; G < 4; ++G) {
+    s4[stg_q(l, G)] = make_float4(y[4 * G].x, y[4 * G + 1].x, y[4 * G + 2].x, y[4 * G + 3].x);
+    s4[stg_q(l, 4 + G)] = make_float4(y[4 * G].y, y[4 * G + 1].y, y[4 * G + 2].y, y[4 * G + 3].y);
   }
   wave_sync();
   f32x4 dr[4], di[4];
   float inv[4];
 #pragma unroll
   for (int grp = 0; grp < 4; ++grp) {
-    const float* src = stg + 32 * (16 * grp + n) + 8 * g;
-    float x[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) x[q] = src[q];
+    const int row = 16 * grp + n;
+    // K = 8g .. 8g+7 of pencil `row`: granules 2g and 2g+1
+    const float4 lo4 = s4[stg_q(row, 2 * g)], hi4 = s4[stg_q(row, 2 * g + 1)];
+    const float x[8] = {lo4.x, lo4.y, lo4.z, lo4.w, hi4.x, hi4.y, hi4.z, hi4.w};
     float sc = 1.f;
     inv[grp] = 1.f;
     if constexpr (ST::kScale) {
@@ -339,18 +348,24 @@ __device__ __forceinline__ void dft16_mfma(float2 (&y)[16], float* stg) {
     di[grp] = ST::mma(aim_lo, bh, im);
   }
   wave_sync();  // every lane has read its operands
+  // outputs 4g .. 4g+3 of pencil `row`: real parts in granule g, imaginary in 4 + g
 #pragma unroll
   for (int grp = 0; grp < 4; ++grp) {
-    float* dst = stg + 32 * (16 * grp + n);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      dst[4 * g + q] = dr[grp][q] * inv[grp];
-      dst[16 + 4 * g + q] = di[grp][q] * inv[grp];
-    }
+    const int row = 16 * grp + n;
+    const float s = inv[grp];
+    s4[stg_q(row, g)] = make_float4(dr[grp][0] * s, dr[grp][1] * s, dr[grp][2] * s, dr[grp][3] * s);
+    s4[stg_q(row, 4 + g)] =
+        make_float4(di[grp][0] * s, di[grp][1] * s, di[grp][2] * s, di[grp][3] * s);
   }
   wave_sync();
 #pragma unroll
-  for (int j = 0; j < 16; ++j) y[j] = make_float2(mine[j], mine[16 + j]);
+  for (int G = 0; G < 4; ++G) {
+    const float4 re = s4[stg_q(l, G)], im = s4[stg_q(l, 4 + G)];
+    y[4 * G] = make_float2(re.x, im.x);
+    y[4 * G + 1] = make_float2(re.y, im.y);
+    y[4 * G + 2] = make_float2(re.z, im.z);
+    y[4 * G + 3] = make_float2(re.w, im.w);
+  }
   wave_sync();
 }
 
@@ -471,7 +486,7 @@ __global__ void __launch_bounds__(MAXT, (MAXT == 1024 && E == 8) ? 8 : 1)
     k_pencil(float2* __restrict__ data, const float2* __restrict__ otf,
              const float2* __restrict__ twg, PencilArgs a, Sched sc) {
   if (a.stop && *a.stop) return;  // stopped: the whole work-group leaves together
-  extern __shared__ float2 lds[];
+  extern __shared__ __attribute__((aligned(16))) float2 lds[];
   const int tid = threadIdx.x;
   // twiddle table (L entries) after the exchange buffer
   float2* tw = lds + (size_t)a.L * a.TXP;
@@ -636,7 +651,7 @@ __device__ __forceinline__ void wg_reduce_rows(double (&v)[K], const int (&op)[K
 template <int E, int MODE, int PREC = 0>
 __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const float2* __restrict__ twg) {
   if (a.stop && *a.stop) return;  // stopped: the whole work-group leaves together
-  extern __shared__ float2 lds[];
+  extern __shared__ __attribute__((aligned(16))) float2 lds[];
   const int M = a.M, P = a.P;
   const int tid = threadIdx.x;
   float2* tw = lds;  // 2M entries: exp(-2 pi i k / (2M))
@@ -649,7 +664,8 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
   const bool inrow = rowi < a.nrows;
   const long long rix = inrow ? rowi : 0;
   float2* row = lds + 2 * M + lrow * a.RS;
-  // split-precision stages: the wave's rows double as its staging area (>= 64 * 32 floats)
+  // split-precision stages: the wave's rows double as its staging area (>= 64 * 32
+  // floats, 16-byte aligned: the host admits only even rows-per-wave * RS there)
   float* stg = reinterpret_cast<float*>(lds + 2 * M + wave * rpw * a.RS);
   const int vol = blockIdx.y;
   const int zz = (int)(rix / a.ny), yy = (int)(rix - (long long)zz * a.ny);
