@@ -5,25 +5,31 @@
  * deconvolution under a Poisson noise model.  One iteration of the estimate u
  * against the observed volume d with the PSF h is
  *
- *     q = H u                      forward blur  (circular convolution with h)
+ *     q = H u                      forward blur  (convolution with h, see rl_boundary)
  *     r = d / q  where q > 1e-12, else 0
  *     c = H^T r                    back-projection with the mirrored PSF
  *     u = u * max(c, 0)
  *
  * where H uses the PSF normalised to unit sum (in FP64) with its centre at
- * voxel floor(n/2) on each axis, and H^T is the exact adjoint of H (circular
+ * voxel floor(p/2) on each axis, and H^T is the exact adjoint of H (the
  * correlation; in the frequency domain a multiplication by the conjugate
- * transfer function).  Image and PSF have the same ZYX shape, as in the
- * paper's experiment (§4.3, paragraph "Dataset description").
+ * transfer function).  By default image and PSF have the same ZYX shape, as in
+ * the paper's experiment (§4.3, paragraph "Dataset description");
+ * rl_options.psf_shape admits a smaller PSF.
  *
  * Conventions shared by every call:
  *   - Volumes are dense, C-ordered float32 arrays [Z][Y][X], X contiguous,
  *     shape given as {nz, ny, nx}.
  *   - Every data pointer is a DEVICE pointer on the plan's GPU, owned by the
  *     caller, at least 16-byte aligned, covering nz*ny*nx floats.
- *   - Supported axis lengths: nx in {2^a, 3*2^a} with 4 <= nx <= 2048,
- *     ny and nz in {1, 2^a, 3*2^a} up to 1024.  Other lengths return
- *     RL_E_UNSUPPORTED.
+ *   - Transform lengths: o * 2^a with o in {1, 3, 5, 7, 9, 15}.  nx must be
+ *     even with nx/2 such a length (4 <= nx <= 2048, and 2560 or 3072); ny and
+ *     nz such lengths <= 1024.  A transform of length L splits over a
+ *     power-of-two number of threads (at most 64 for nx/2, 1024 for ny, nz),
+ *     each holding E in {1..10, 12, 14, 15, 16, 18, 20, 24, 30} elements that
+ *     carry every odd factor of L, in at most 8 radix stages (16, 8, 4, 2, then
+ *     7, 5, 3).  Other lengths return RL_E_UNSUPPORTED (for the zero boundary
+ *     the rule applies to the padded transform grid).
  *   - All argument checks run before any device work; a failing call leaves
  *     every buffer untouched.  No call aborts, exits or throws.
  *   - Work is enqueued on the plan's stream (default: the null stream) and
@@ -103,7 +109,8 @@ typedef struct {
                      pass only); 0 = library default; out of range = RL_E_INVALID */
   int x_elems;    /* elements per thread of the X-pass transforms (length nx/2); 0 =
                      default; must divide nx/2 leaving a power-of-two thread count
-                     <= 64, and hold every factor 3 of nx/2 (else RL_E_INVALID) */
+                     <= 64, carry every odd factor of nx/2 and be even when
+                     nx/2 is (else RL_E_INVALID) */
   int yz_elems;   /* the same for the Y and Z transforms (lengths ny and nz) */
   int autotune;   /* 1: at plan creation, time candidate elements-per-thread and
                      work-group widths for each pass on this GPU and keep the
@@ -130,9 +137,8 @@ typedef struct {
  * positive sum (else RL_E_INVALID); it is normalised to unit sum in FP64 and
  * its transfer function is stored in the plan (plan-owned device memory, about
  * 8 bytes per voxel of the transform grid including the spectrum workspace).
- * Periodic boundary: each dimension must be a transform length: nx even with
- * nx/2 in {2^a, 3*2^a}, nx <= 2048; ny, nz in {1, 2^a, 3*2^a}, <= 1024 (else
- * RL_E_UNSUPPORTED).  Zero boundary: those limits apply to the padded grid.
+ * Periodic boundary: each dimension must be a transform length as stated
+ * above (else RL_E_UNSUPPORTED).  Zero boundary: those limits apply to the padded grid.
  * Synchronous: returns after all device work is done.  On success *out
  * receives the plan; on failure *out is set to NULL.
  */
@@ -222,7 +228,7 @@ typedef struct {
   int metric;              /* rl_stop_metric */
   double threshold;        /* finite */
   int min_iter;            /* >= 0 */
-  const float* reference;  /* RL_STOP_PSNR only */
+  const float* reference;  /* RL_STOP_PSNR and RL_STOP_SSIM: device, the volume's shape */
 } rl_stop_rule;
 
 /*
@@ -239,8 +245,8 @@ rl_status rl_iterate_stop(rl_plan p, const float* observed, float* estimate, int
 /*
  * After rl_iterate_stop (else RL_E_INVALID): iterations carried out in
  * *n_done, and the metric value of every check in history[0 .. min(cap, n) - 1]
- * with n in *n_history (LOGLIK: l_0 .. l_k; CHANGE and PSNR: one value per
- * iteration done).  Synchronises the plan's stream.
+ * with n in *n_history (LOGLIK: l_0 .. l_k; CHANGE, PSNR and SSIM: one value
+ * per iteration done).  Synchronises the plan's stream.
  */
 rl_status rl_plan_get_stop(rl_plan p, int* n_done, double* history, int cap, int* n_history);
 
