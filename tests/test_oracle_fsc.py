@@ -7,7 +7,9 @@
   voxels, all energy sits in the shell of k0 and the FSC there is
   cos(2 pi k0 . s / n).
 * The shell map against numpy.fft.fftfreq (an independent library).
-* The resolution crossing on hand-made curves.
+* The resolution crossing on hand-made curves; shell 0 never counts as a crossing.
+* The last block plants plausible mistakes in the oracle and checks that a pin
+  catches each.
 """
 
 import numpy as np
@@ -79,3 +81,57 @@ def test_split_diagonal():
     a, b = fo.split_diagonal(u)
     assert a.shape == (2, 3, 4) and b.shape == (2, 3, 4)
     assert a[1, 2, 3] == u[2, 4, 6] and b[1, 2, 3] == u[3, 5, 7]
+
+
+def test_dc_shell_is_not_a_crossing():
+    # shell 0 holds the mean; a low value there is not a resolution crossing
+    nb = 8
+    f = (np.arange(nb) + 0.5) * 0.5 / nb
+    curve = np.array([0.0, 0.9, 0.05, 0.0, 0.0, 0.0, 0.0, 0.0])
+    t = (0.9 - 1 / 7) / (0.9 - 0.05)
+    assert abs(fo.resolution(curve, nb) - (f[1] + t * (f[2] - f[1]))) <= 1e-15
+
+
+# ---------------------------------------------------------------------------
+# Planted mistakes: each must make one of the pins above fail.
+# ---------------------------------------------------------------------------
+from mutation import mutate  # noqa: E402
+
+
+def _pins_hold():
+    """Re-run a compact set of the pins; False if any fails."""
+    tests = [lambda: test_identity_sign_scale((5, 7, 9)), test_parseval,
+             test_single_frequency_shift_closed_form, test_shell_map_against_fftfreq,
+             test_resolution_crossing, test_dc_shell_is_not_a_crossing, test_split_diagonal]
+    try:
+        for t in tests:
+            t()
+    except Exception:
+        return False
+    return True
+
+
+def test_pins_hold_on_clean_oracle():
+    assert _pins_hold()
+
+
+@pytest.mark.parametrize("func,old,new", [
+    # unsigned frequency index: the upper half of each axis lands in far shells
+    ("signed_index", "j < (n + 1) // 2, j, j - n", "j < n, j, j - n"),
+    # shells twice as wide (rho * nbins)
+    ("shell_index", "four = 4 * nbins * nbins", "four = nbins * nbins"),
+    # a frequency on a shell boundary put into the inner shell
+    ("shell_index", "math.isqrt((four * int(v)) // (L * L))",
+     "math.isqrt(max((four * int(v) - 1) // (L * L), 0))"),
+    ("fsc_sums", "np.real(F * np.conj(G))", "np.real(F * G)"),
+    ("fsc_sums", "np.real(F * np.conj(G))", "np.imag(F * np.conj(G))"),
+    ("fsc_sums", "(np.abs(G) ** 2)", "(np.abs(F) ** 2)"),
+    ("fsc", "np.sqrt(d1 * d2)", "0.5 * (d1 + d2)"),
+    ("resolution", "range(1, nbins)", "range(0, nbins)"),
+    ("resolution", "f[s - 1] + t * (f[s] - f[s - 1])", "f[s]"),
+    ("resolution", "(np.arange(nbins) + 0.5)", "np.arange(nbins)"),
+    ("split_diagonal", "u[1::2, 1::2, 1::2]", "u[1::2, 1::2, 0::2]"),
+])
+def test_planted_mistake_is_caught(monkeypatch, func, old, new):
+    monkeypatch.setattr(fo, func, mutate(fo, func, old, new))
+    assert not _pins_hold(), (func, new)
