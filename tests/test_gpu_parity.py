@@ -361,3 +361,22 @@ def test_full_size_config1_rl_properties(torch):
     total = float(c["d"].sum(dtype=np.float64))
     assert np.all(np.abs(flux - total) / total <= 1e-6), flux[:3]
     assert np.all(u >= 0) and np.all(np.isfinite(u))
+
+
+def test_full_size_config1_rl_matches_oracle_autotuned(torch):
+    # full size, element by element, in the benchmark's launch configuration (an
+    # autotuned plan); three iterations keep the FP64 oracle to a few seconds
+    c = synth.make_config(1)
+    n = 3
+    say("full-size rl vs oracle, autotuned", c["shape"])
+    with rl.Plan(dev(torch, c["psf"]), autotune=True) as p:
+        u = dev(torch, c["u0"])
+        p.iterate(dev(torch, c["d"]), u, n)
+        got = u.cpu().numpy().astype(np.float64)
+        say("  launch", p.launch())
+    ref = oracle.rl(c["d"], c["psf"], c["u0"], n)[0]
+    err = oracle.rel_l2(got, ref)
+    worst = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    say("  rel L2", err, "max abs error / peak", worst)
+    assert err <= 1e-5
+    assert worst <= 1e-5
