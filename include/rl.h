@@ -117,7 +117,10 @@ typedef struct {
                      fastest (adds tens of ms; needs 8 bytes per voxel of
                      temporary device memory).  With RLMI_TUNE_CACHE naming a
                      text file, results are read from / appended to it, keyed
-                     by GPU architecture, HIP runtime version and shape. */
+                     by GPU architecture, HIP runtime version and shape; the
+                     last line of a key wins, and a line whose configuration
+                     does not fit the shape is ignored (the plan tunes afresh
+                     and appends a new line). */
   int accel;      /* rl_accel.  RL_ACCEL_BIGGS_ANDREWS keeps two more plan-owned
                      volumes (8 bytes per voxel: the last step h and change g) and
                      costs one more X pass and a one-work-group reduction per

@@ -711,21 +711,24 @@ std::string tune_key(rl_plan p) {
   return s;
 }
 
+// The last line with this key wins, so a line appended after re-tuning
+// supersedes an earlier one.
 bool cache_lookup(const std::string& key, Choice* c) {
   const char* path = std::getenv("RLMI_TUNE_CACHE");
   if (!path || !*path) return false;
   std::ifstream f(path);
   std::string line;
+  bool found = false;
   while (std::getline(f, line)) {
     std::istringstream ls(line);
     std::string k;
     Choice t;
     if ((ls >> k >> t.x_e >> t.y_e >> t.y_txb >> t.z_e >> t.z_txb >> t.z_swap) && k == key) {
       *c = t;
-      return true;
+      found = true;
     }
   }
-  return false;
+  return found;
 }
 
 void cache_store(const std::string& key, const Choice& c) {
@@ -1133,16 +1136,21 @@ rl_status build_class(const Geometry& geo, int count, const float* const* psfs, 
   if (want_tune) {
     const std::string key = tune_key(p);
     Choice tuned = choice;
-    if (!cache_lookup(key, &tuned)) {
+    bool cached = cache_lookup(key, &tuned);
+    if (cached && !configure(p, tuned)) {  // a stale or edited line: tune afresh
+      cached = false;
+      tuned = choice;
+    }
+    if (!cached) {
       if ((st = autotune(p, &tuned)) != RL_OK) {
         release(p);
         return st;
       }
       cache_store(key, tuned);
-    }
-    if (!configure(p, tuned)) {
-      release(p);
-      return fail(RL_E_INTERNAL, "tuned configuration does not apply");
+      if (!configure(p, tuned)) {
+        release(p);
+        return fail(RL_E_INTERNAL, "tuned configuration does not apply");
+      }
     }
     p->tuned = true;
   }

@@ -149,6 +149,31 @@ def test_tuning_cache_choices_apply(torch, tmp_path, monkeypatch, z_swap):
     assert oracle.rel_l2(got, oracle.conv3d(x, psf)) <= CONV_TOL
 
 
+def test_stale_tuning_cache_line_is_retuned(torch, tmp_path, monkeypatch):
+    # a cached configuration that does not fit the shape (y_e = 30 does not divide
+    # ny = 32) is ignored: the plan tunes afresh and appends a line that
+    # supersedes the stale one
+    shape = (16, 32, 64)
+    say("stale tuning cache line")
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("RLMI_TUNE_CACHE", str(cache))
+    x = synth.uniform_volume(shape, 106)
+    psf = rand_psf(shape, 17)
+    with rl.Plan(dev(torch, psf), autotune=True):
+        pass
+    key, *good = cache.read_text().split()
+    cache.write_text(key + " 2 30 16 16 32 0\n")
+    with rl.Plan(dev(torch, psf), autotune=True) as p:
+        assert p.launch()["tuned"]
+        got = p.conv(dev(torch, x)).cpu().numpy()
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 2 and lines[1].split()[0] == key
+    assert oracle.rel_l2(got, oracle.conv3d(x, psf)) <= CONV_TOL
+    with rl.Plan(dev(torch, psf), autotune=True):  # the appended line now applies
+        pass
+    assert len(cache.read_text().splitlines()) == 2
+
+
 @pytest.mark.parametrize("tile_x", [3, 24, 48])
 def test_odd_tile_width_requests(torch, tile_x):
     # non-power-of-two requests round down to a power of two
