@@ -63,6 +63,33 @@ def test_batch_matches_oracle_and_single_plans(torch):
         assert torch.equal(us, u[i]), i
 
 
+def test_full_size_batch_workload(torch):
+    # the benchmark's batch: 96 uneven volumes (about 1e8 voxels, five shape
+    # classes) in one plan as it is timed; the first volume of every class element
+    # by element against the oracle, and every volume's flux against its data
+    vols = synth.make_batch(96)
+    n_iter = 2
+    say("full-size batch", len(vols), "volumes")
+    first = {}
+    for i, v in enumerate(vols):
+        first.setdefault(tuple(v["shape"]), i)
+    with rl.BatchPlan([dev(torch, v["psf"]) for v in vols]) as bp:
+        d = [dev(torch, v["d"]) for v in vols]
+        u = [dev(torch, v["u0"]) for v in vols]
+        bp.iterate(d, u, n_iter)
+        flux = bp.flux()
+        got = {i: u[i].cpu().numpy() for i in first.values()}
+    assert flux.shape == (len(vols), n_iter)
+    for i, v in enumerate(vols):
+        total = float(v["d"].sum(dtype=np.float64))
+        assert np.all(np.abs(flux[i] - total) / total <= 1e-6), (i, flux[i], total)
+    for shp, i in first.items():
+        ref = oracle.rl(vols[i]["d"], vols[i]["psf"], vols[i]["u0"], n_iter)[0]
+        err = oracle.rel_l2(got[i], ref)
+        say("  class", shp, "volume", i, "relL2", err)
+        assert err <= 1e-5
+
+
 def test_batch_graph_replays_and_resume(torch):
     say("batch graph replays")
     cs = cases()

@@ -378,6 +378,25 @@ def test_full_size_config1_conv_sampled(torch):
     assert np.max(np.abs(g - ref) / np.abs(ref)) <= 1e-5
 
 
+def test_full_size_config2_conv_sampled_autotuned(torch):
+    # the 256x512x512 volume with an autotuned plan (the benchmark's launch
+    # configuration); sampled voxels by the direct sum
+    c = synth.CONFIGS[2]
+    shape = c["shape"]
+    say("full-size conv, autotuned", shape)
+    x = synth.uniform_volume(shape, 2 + 100)
+    psf = synth.gaussian_psf(shape, c["sigma"])
+    with rl.Plan(dev(torch, psf), autotune=True) as p:
+        got = p.conv(dev(torch, x)).cpu().numpy()
+        say("  launch", p.launch())
+    rng = np.random.default_rng(1)
+    pts = [tuple(int(rng.integers(0, n)) for n in shape) for _ in range(5)]
+    pts += [(0, 0, 0), tuple(n - 1 for n in shape)]
+    ref = oracle.conv_direct_at(x, psf, pts)
+    g = np.array([got[p] for p in pts])
+    assert np.max(np.abs(g - ref) / np.abs(ref)) <= 1e-5
+
+
 def test_full_size_config1_rl_properties(torch):
     c = synth.make_config(1)
     say("full-size rl properties", c["shape"])
