@@ -213,9 +213,23 @@ def run_batched(torch, rl, synth, steps: int, warmup: int, count: int = 96, n_it
             "speedup_vs_plain": round(out["plain"] / out["batched"], 3), "flux_drift": drift}
 
 
+GOLDEN_512 = os.path.join(ROOT, "tests", "golden", "rl_512x512x256_samples.txt")
+
+
+def oracle_samples():
+    """The FP64 oracle's estimate of the 512x512x256 workload after 10 and 50
+    iterations at stored sample voxels (written once by the script beside the
+    file, which calls only the oracle); None if the file is absent."""
+    if not os.path.exists(GOLDEN_512):
+        return None
+    a = np.loadtxt(GOLDEN_512, comments="#")
+    return a[:, :3].astype(np.int64), {10: a[:, 3], 50: a[:, 4]}
+
+
 def run_split(torch, rl, synth, steps: int, cfg: int = 2):
     """Split-precision forms on the organoid-scale volume: time per step against the
-    plain FP32 form, and relative L2 to the FP32 result after 10 and 50 iterations."""
+    plain FP32 form, relative L2 to the FP32 result after 10 and 50 iterations, and
+    relative L2 to the FP64 oracle over its stored sample voxels."""
     c = synth.make_config(cfg)
     n_iter = c["n_iter"]
     dev = torch.device("cuda:0")
@@ -224,6 +238,7 @@ def run_split(torch, rl, synth, steps: int, cfg: int = 2):
     u0 = torch.from_numpy(c["u0"]).to(dev)
     nvox = int(np.prod(c["shape"]))
     res, ref = {}, {}
+    samples = oracle_samples()
     for prec in ("fp32", "split_bf16", "split_fp16"):
         plan = rl.Plan(psf, precision=prec)
         u = u0.clone()
@@ -250,6 +265,14 @@ def run_split(torch, rl, synth, steps: int, cfg: int = 2):
                 entry[f"rel_l2_vs_fp32_at_{k}"] = float(
                     (torch.linalg.vector_norm(uu.double() - ref[k]) /
                      torch.linalg.vector_norm(ref[k])).item())
+        if samples is not None:
+            pts, vals = samples
+            idx = torch.from_numpy(pts).to(dev)
+            for k, uu in ((10, u10), (50, u50)):
+                g = uu[idx[:, 0], idx[:, 1], idx[:, 2]].double().cpu().numpy()
+                entry[f"rel_l2_vs_oracle_at_{k}"] = float(
+                    np.linalg.norm(g - vals[k]) / np.linalg.norm(vals[k]))
+            entry["oracle_samples"] = int(len(pts))
         res[prec] = entry
     for prec in ("split_bf16", "split_fp16"):
         res[prec]["speedup_vs_fp32"] = round(res["fp32"]["ms_per_step"] /

@@ -2,9 +2,13 @@
 BF16 or FP16 hi/lo operands, against the FP64 oracle.
 
 Bars: Richardson-Lucy after 10 and 50 iterations within 5e-4 relative L2 of the
-oracle (both splits).  A single convolution: BF16 split within 1e-4 (its
-operands carry ~16 significant bits), FP16 split within 1e-5 (~22 bits)."""
+oracle (both splits; the plain FP32 form within 1e-4).  A single convolution:
+BF16 split within 1e-4 (its operands carry ~16 significant bits), FP16 split
+within 1e-5 (~22 bits).  At the full 512x512x256 size the oracle's values come
+from tests/golden/rl_512x512x256_samples.txt (written by the script beside it,
+which calls only the oracle), compared at its sample voxels."""
 
+import os
 import sys
 
 import numpy as np
@@ -103,3 +107,38 @@ def test_split_rl_larger_volume(torch, precision):
     err = oracle.rel_l2(got, ref)
     say("  relL2 at 10:", err)
     assert err <= RL_TOL
+
+
+GOLDEN_512 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                          "rl_512x512x256_samples.txt")
+
+
+@pytest.fixture(scope="module")
+def organoid():
+    return synth.make_config(2)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("split_bf16", RL_TOL),
+                                           ("split_fp16", RL_TOL)])
+def test_full_size_512_against_oracle_samples(torch, organoid, precision, tol):
+    # the 512x512x256 workload as the benchmark runs it (FP32 autotuned, the splits
+    # with their default shapes); relative L2 over the oracle's sample voxels
+    a = np.loadtxt(GOLDEN_512, comments="#")
+    pts, ref = a[:, :3].astype(np.int64), {10: a[:, 3], 50: a[:, 4]}
+    c = organoid
+    assert tuple(c["shape"]) == (256, 512, 512)
+    say("full-size 512x512x256 vs oracle samples", precision)
+    idx = torch.from_numpy(pts).to("cuda:0")
+    with rl.Plan(dev(torch, c["psf"]), precision=precision,
+                 autotune=precision == "fp32") as p:
+        d, u = dev(torch, c["d"]), dev(torch, c["u0"])
+        got = {}
+        done = 0
+        for n in (10, 50):
+            p.iterate(d, u, n - done)
+            done = n
+            got[n] = u[idx[:, 0], idx[:, 1], idx[:, 2]].double().cpu().numpy()
+    for n in (10, 50):
+        err = float(np.linalg.norm(got[n] - ref[n]) / np.linalg.norm(ref[n]))
+        say(f"  after {n}: relative L2 over {len(pts)} voxels {err:.3e}")
+        assert err <= tol
