@@ -150,3 +150,20 @@ def test_accel_errors(torch):
         with pytest.raises(rl.RLError) as ei:
             p.flux()
         assert ei.value.status == rl.RL_E_NUMERIC
+
+
+def test_full_size_accel_as_benchmarked(torch):
+    # the benchmark's extrapolated workload: the 128x256x256 volume, an autotuned
+    # plan; four iterations (alpha is live from the third) element by element
+    c = synth.make_config(1)
+    n = 4
+    say("full-size accel", c["shape"])
+    u, flux, alpha = gpu_accel(torch, c, n, autotune=True)
+    ref, rflux, ralpha = oracle.rl_accel(c["d"], c["psf"], c["u0"], n)
+    err = oracle.rel_l2(u, ref)
+    say("  relL2", err, "alpha", alpha, "oracle", ralpha)
+    assert err <= 1e-5
+    assert np.all(alpha[:2] == 0) and np.all(ralpha[2:] > 0)
+    assert np.max(np.abs(alpha - ralpha)) <= ALPHA_TOL
+    total = float(c["d"].sum(dtype=np.float64))
+    assert np.all(np.abs(flux - total) / total <= 1e-5)

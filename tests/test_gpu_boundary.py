@@ -184,3 +184,35 @@ def test_boundary_errors(torch):
     with rl.Plan(h, shape=(9, 10, 10), boundary="zero") as p:
         with pytest.raises(ValueError):
             p.conv(dev(torch, np.ones((5, 5, 5))))  # wrong volume shape
+
+
+def test_full_size_zero_boundary_as_benchmarked(torch):
+    # the benchmark's zero-boundary workload: the 128x256x256 volume with its
+    # Gaussian PSF cut to +-4 sigma (41x17x17), an autotuned plan; sampled voxels
+    # of one convolution by the direct sum (corners and faces included), and two
+    # iterations element by element against the oracle
+    c = synth.make_config(1)
+    shape = c["shape"]
+    sx, sy, sz = c["sigma"]
+    pshape = tuple(2 * int(np.ceil(4 * s)) + 1 for s in (sz, sy, sx))
+    h = synth.gaussian_psf(pshape, (sx, sy, sz))
+    say("full-size zero boundary", shape, pshape)
+    x = synth.uniform_volume(shape, 150)
+    n = 2
+    with rl.Plan(dev(torch, h), shape=shape, boundary="zero", autotune=True) as p:
+        say("  grid", p.grid(), "launch", p.launch())
+        conv = p.conv(dev(torch, x)).cpu().numpy()
+        u = dev(torch, c["u0"])
+        p.iterate(dev(torch, c["d"]), u, n)
+        got = u.cpu().numpy()
+    rng = np.random.default_rng(151)
+    pts = [tuple(int(rng.integers(0, m)) for m in shape) for _ in range(6)]
+    pts += [(0, 0, 0), tuple(m - 1 for m in shape), (0, shape[1] // 2, shape[2] - 1),
+            (shape[0] - 1, 0, shape[2] // 2)]
+    ref = bo.conv_zero_at(x, h, pts)
+    g = np.array([conv[q] for q in pts])
+    assert np.max(np.abs(g - ref) / np.abs(ref)) <= CONV_TOL
+    ref_u, _ = bo.rl_general(c["d"], h, c["u0"], n, boundary="zero")
+    err = oracle.rel_l2(got, ref_u)
+    say("  relL2 after", n, err)
+    assert err <= 1e-5

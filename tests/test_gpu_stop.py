@@ -142,3 +142,24 @@ def test_stop_errors(torch):
         with pytest.raises(rl.RLError) as ei:
             p.iterate_until(d, u, 5, "change", 0.1)
         assert ei.value.status == rl.RL_E_UNSUPPORTED
+
+
+def test_full_size_loglik_stop_as_benchmarked(torch):
+    # the benchmark's stopping workload: the 128x256x256 volume, an autotuned plan,
+    # the log-likelihood rule; the threshold sits halfway between two consecutive
+    # improvements of the oracle's history so that the decision is unambiguous
+    c = synth.make_config(1)
+    say("full-size loglik stop", c["shape"])
+    m = 7
+    _, _, full = so.rl_stop(c["d"], c["psf"], c["u0"], m, "loglik", -1e300)
+    tau = _threshold("loglik", full, 5)
+    ref_u, ref_n, ref_hist = so.rl_stop(c["d"], c["psf"], c["u0"], m, "loglik", tau)
+    with rl.Plan(dev(torch, c["psf"]), autotune=True) as p:
+        u = dev(torch, c["u0"])
+        p.iterate_until(dev(torch, c["d"]), u, m, "loglik", tau)
+        n, hist = p.stop()
+        got = u.cpu().numpy()
+    say("  oracle n", ref_n, "gpu n", n, "tau", tau)
+    assert n == ref_n
+    assert np.max(np.abs(hist - ref_hist) / np.abs(ref_hist)) <= 1e-6
+    assert oracle.rel_l2(got, ref_u) <= 1e-5
