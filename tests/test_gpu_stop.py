@@ -163,3 +163,25 @@ def test_full_size_loglik_stop_as_benchmarked(torch):
     assert n == ref_n
     assert np.max(np.abs(hist - ref_hist) / np.abs(ref_hist)) <= 1e-6
     assert oracle.rel_l2(got, ref_u) <= 1e-5
+
+
+@pytest.mark.parametrize("metric", ["change", "psnr", "ssim"])
+def test_full_size_metric_histories_as_benchmarked(torch, metric):
+    # the other benchmarked rules on the 128x256x256 volume (autotuned plan): with a
+    # threshold that never fires, the metric after each of three iterations against
+    # the oracle's (PSNR and SSIM against the ground truth, as the benchmark does)
+    c = synth.make_config(1)
+    truth = c["truth"].astype(np.float32)
+    ref = truth if metric in ("psnr", "ssim") else None
+    n = 3
+    say("full-size history", metric)
+    _, _, ref_hist = so.rl_stop(c["d"], c["psf"], c["u0"], n, metric, -1e300, reference=ref)
+    with rl.Plan(dev(torch, c["psf"]), autotune=True) as p:
+        u = dev(torch, c["u0"])
+        p.iterate_until(dev(torch, c["d"]), u, n, metric, -1e300,
+                        reference=dev(torch, truth) if ref is not None else None)
+        k, hist = p.stop()
+    say("  gpu", hist, "oracle", ref_hist)
+    assert k == n and len(hist) == n
+    tol = {"change": 1e-6, "psnr": 1e-3, "ssim": 1e-6}[metric]
+    assert np.max(np.abs(hist - ref_hist)) <= tol
