@@ -117,3 +117,21 @@ def test_fsc_guided_stop_matches_oracle(torch):
     assert n == ref_n
     assert np.max(np.abs(hist - ref_hist)) <= 1e-4
     assert np.max(np.abs(got - ref_u)) / np.max(np.abs(ref_u)) <= 1e-4
+
+
+def test_full_size_single_image_fsc_as_benchmarked(torch):
+    # the benchmark's FSC: the 128x256x256 observed volume split into its two
+    # diagonal 64x128x128 halves, 64 shells, against the oracle
+    c = synth.make_config(1)
+    say("full-size single-image fsc", c["shape"])
+    d = dev(torch, c["d"])
+    a, b = rl.split_diagonal(d)
+    half = tuple(n // 2 for n in c["shape"])
+    with rl.Plan(dev(torch, synth.gaussian_psf(half, (1.0, 1.0, 1.0)))) as q:
+        curve, res = q.fsc(a, b, 64)
+    ra, rb = fo.split_diagonal(c["d"])
+    ref = fo.fsc(ra, rb, 64)
+    err = float(np.max(np.abs(curve - ref)))
+    say("  max |d curve|", err, "resolution", res, fo.resolution(ref, 64))
+    assert err <= 1e-5
+    assert abs(res - fo.resolution(ref, 64)) <= 1e-4
