@@ -216,3 +216,33 @@ def test_full_size_zero_boundary_as_benchmarked(torch):
     err = oracle.rel_l2(got, ref_u)
     say("  relL2 after", n, err)
     assert err <= 1e-5
+
+
+def test_full_size_ragged_zero_boundary(torch):
+    # a volume of the benchmark's size with ragged extents on every axis (odd, and
+    # no transform length), the same cut PSF, a default plan: the library pads the
+    # grid itself; sampled voxels by the direct sum and two iterations element by
+    # element
+    shape = (123, 250, 254)
+    sigma = (2.0, 2.0, 5.0)
+    pshape = tuple(2 * int(np.ceil(4 * s)) + 1 for s in (sigma[2], sigma[1], sigma[0]))
+    h = synth.gaussian_psf(pshape, sigma)
+    c = synth.small_case(shape, sigma_xyz=sigma, seed=152, density=0.05)
+    x = synth.uniform_volume(shape, 153)
+    say("ragged full-size zero boundary", shape, pshape)
+    n = 2
+    with rl.Plan(dev(torch, h), shape=shape, boundary="zero") as p:
+        say("  grid", p.grid())
+        conv = p.conv(dev(torch, x)).cpu().numpy()
+        u = dev(torch, c["u0"])
+        p.iterate(dev(torch, c["d"]), u, n)
+        got = u.cpu().numpy()
+    pts = [(0, 0, 0), tuple(m - 1 for m in shape), (shape[0] - 1, 0, 0), (0, shape[1] - 1, 0),
+           (0, 0, shape[2] - 1), (61, 125, 127), (5, 249, 3)]
+    ref = bo.conv_zero_at(x, h, pts)
+    g = np.array([conv[q] for q in pts])
+    assert np.max(np.abs(g - ref) / np.abs(ref)) <= CONV_TOL
+    ref_u, _ = bo.rl_general(c["d"], h, c["u0"], n, boundary="zero")
+    err = oracle.rel_l2(got, ref_u)
+    say("  relL2 after", n, err)
+    assert err <= 1e-5
