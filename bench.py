@@ -159,9 +159,14 @@ def run_workload(torch, rl, synth, cfg: int, steps: int, warmup: int, workload: 
                 bytes_per_vi=round(model_bytes / (nvox * n_iter), 2))
 
 
-def run_batched(torch, rl, synth, steps: int, warmup: int, count: int = 96, n_iter: int = 50):
+def run_batched(torch, rl, synth, steps: int, warmup: int, count: int = 96, n_iter: int = 50,
+                autotune: bool = True):
     """Batched form: `count` uneven volumes with their own PSFs, one graph launch per
-    iteration, against the same volumes run one plain plan at a time."""
+    iteration, against the same volumes run one plain plan at a time.  With
+    `autotune`, the batch plan tunes each shape class once and the plain plans reuse
+    those choices through a temporary tuning cache (both sides tuned alike; plan
+    creation is outside the timed region)."""
+    import tempfile
     vols = synth.make_batch(count)
     dev = torch.device("cuda:0")
     psfs = [torch.from_numpy(v["psf"]).to(dev) for v in vols]
@@ -169,14 +174,27 @@ def run_batched(torch, rl, synth, steps: int, warmup: int, count: int = 96, n_it
     u0 = [torch.from_numpy(v["u0"]).to(dev) for v in vols]
     u = [t.clone() for t in u0]
     nvox = sum(int(np.prod(v["shape"])) for v in vols)
-    bp = rl.BatchPlan(psfs)
+    saved = os.environ.get("RLMI_TUNE_CACHE")
+    cache = tempfile.mkdtemp()
+    if autotune:
+        os.environ["RLMI_TUNE_CACHE"] = os.path.join(cache, "tune.txt")
+    try:
+        bp = rl.BatchPlan(psfs, autotune=autotune)
+        plans = [rl.Plan(h, autotune=autotune) for h in psfs]
+    finally:
+        if saved is None:
+            os.environ.pop("RLMI_TUNE_CACHE", None)
+        else:
+            os.environ["RLMI_TUNE_CACHE"] = saved
+        if os.path.exists(os.path.join(cache, "tune.txt")):
+            os.remove(os.path.join(cache, "tune.txt"))
+        os.rmdir(cache)
+    launch = bp.launch()
 
     def step_batched():
         for a, b in zip(u, u0):
             a.copy_(b)
         bp.iterate(d, u, n_iter)
-
-    plans = [rl.Plan(h) for h in psfs]
 
     def step_plain():
         for a, b in zip(u, u0):
@@ -210,7 +228,8 @@ def run_batched(torch, rl, synth, steps: int, warmup: int, count: int = 96, n_it
             "value": round(nvox * n_iter / (out["batched"] * 1e-3) / 1e9, 3),
             "unit": "Gvoxel-iter/s", "ms_per_step": round(out["batched"], 3),
             "plain_one_plan_per_volume_ms": round(out["plain"], 3),
-            "speedup_vs_plain": round(out["plain"] / out["batched"], 3), "flux_drift": drift}
+            "speedup_vs_plain": round(out["plain"] / out["batched"], 3), "flux_drift": drift,
+            "autotuned": autotune, "launch": launch}
 
 
 GOLDEN_512 = os.path.join(ROOT, "tests", "golden", "rl_512x512x256_samples.txt")

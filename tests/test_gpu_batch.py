@@ -63,17 +63,24 @@ def test_batch_matches_oracle_and_single_plans(torch):
         assert torch.equal(us, u[i]), i
 
 
-def test_full_size_batch_workload(torch):
+@pytest.fixture(scope="module")
+def batch96():
+    return synth.make_batch(96)
+
+
+@pytest.mark.parametrize("autotune", [True, False])
+def test_full_size_batch_workload(torch, batch96, autotune):
     # the benchmark's batch: 96 uneven volumes (about 1e8 voxels, five shape
-    # classes) in one plan as it is timed; the first volume of every class element
-    # by element against the oracle, and every volume's flux against its data
-    vols = synth.make_batch(96)
+    # classes) in one plan as it is timed (autotuned; the default shapes too); the
+    # first volume of every class element by element against the oracle, and every
+    # volume's flux against its data
+    vols = batch96
     n_iter = 2
-    say("full-size batch", len(vols), "volumes")
+    say("full-size batch", len(vols), "volumes, autotune", autotune)
     first = {}
     for i, v in enumerate(vols):
         first.setdefault(tuple(v["shape"]), i)
-    with rl.BatchPlan([dev(torch, v["psf"]) for v in vols]) as bp:
+    with rl.BatchPlan([dev(torch, v["psf"]) for v in vols], autotune=autotune) as bp:
         d = [dev(torch, v["d"]) for v in vols]
         u = [dev(torch, v["u0"]) for v in vols]
         bp.iterate(d, u, n_iter)
