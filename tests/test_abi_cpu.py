@@ -167,3 +167,13 @@ def test_alpha_query_checks_handle():
     L = rl.lib()
     n = ctypes.c_int()
     assert L.rl_plan_get_alpha(ctypes.c_void_p(0x1234560), None, 0, ctypes.byref(n)) == rl.RL_E_INVALID
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    # with the HIP library absent, the binding raises; there is no fallback path
+    monkeypatch.setattr(rl, "_lib", None)
+    monkeypatch.setattr(rl, "LIB_PATH", str(tmp_path / "librlmi.so"))
+    with pytest.raises(RuntimeError, match="is not built"):
+        rl.lib()
+    with pytest.raises(RuntimeError, match="is not built"):
+        rl.rl_plan_create((8, 8, 8), 4096)
