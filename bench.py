@@ -426,7 +426,9 @@ def run_stop(torch, rl, synth, steps: int, cfg: int = 1):
 
     out = {"workload": "rl_stop_128x256x256", "max_iter": n_max,
            "fixed_ms": round(timed(lambda: plan.iterate(d, u, n_max)), 3)}
-    rules = {"loglik": (1e-4, None), "change": (2e-3, None), "psnr": (0.01, truth),
+    # the log-likelihood threshold lies between two consecutive relative improvements
+    # of the FP64 oracle on this volume (1.50e-4 and 1.00e-4), clear of both
+    rules = {"loglik": (1.2e-4, None), "change": (2e-3, None), "psnr": (0.01, truth),
              "ssim": (1e-3, truth)}
     for name, (tau, ref) in rules.items():
         ms = timed(lambda: plan.iterate_until(d, u, n_max, name, tau, reference=ref))
