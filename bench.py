@@ -2,14 +2,24 @@
 
 A step is one complete deconvolution of one synthetic volume: reset the
 estimate to u0 = mean(d) and run the configured number of RL iterations
-(rl_iterate through the C ABI).  The headline workload is the 128x256x256
-widefield-like volume with 100 iterations; the 256x512x512 organoid-scale volume
-(50 iterations, larger than the on-chip caches) is reported beside it.
+(rl_iterate through the C ABI).  The headline workload is the 256x512x512
+organoid-scale volume with 50 iterations, whose working set (about 1.1 GB) is
+larger than the chip's 256 MB last-level cache, so its passes stream from HBM.
+The 128x256x256 widefield-like volume (100 iterations) fits that cache; it is
+reported beside the headline as `mall_resident`, not as an HBM figure.
 
 Printed: one JSON line with value = voxel-iterations per second (whole job,
-inputs resident in HBM), a roofline object for the dominant kernel (per-launch
-algorithmic bytes / its average duration, measured here with HIP events), and
-the FP64 oracle timed on the host cores on a bounded sample.
+inputs resident in HBM), a roofline object for the dominant kernel, and the FP64
+oracle timed on the host cores on a bounded sample of the headline workload.
+The roofline's kernel duration is the average of that kernel's back-to-back
+launches in a committed rocprofv3 kernel trace of this benchmark (used only
+while the trace was taken on the current kernel source); the duration measured
+live here with HIP events around every launch is reported beside it.
+
+`python bench.py --rocprof-summary TRACE_DIR [FETCH_DIR WRITE_DIR] --out FILE`
+turns the CSV output of rocprofv3 runs of this benchmark (a kernel trace, and
+optionally FETCH_SIZE and WRITE_SIZE counter runs) into the summary table that
+the roofline reads.
 """
 
 from __future__ import annotations
@@ -60,18 +70,174 @@ def source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(kind: str, workload: str):
-    """Per-launch HBM bytes from a committed rocprofv3 counter summary, if it was
-    taken on the current kernel source; else None."""
-    path = os.path.join(PROFILES, f"traffic_{kind}_{workload}.md")
+# ---------------------------------------------------------------------------
+# rocprofv3 summaries
+# ---------------------------------------------------------------------------
+B2B_GAP_NS = 1000  # a launch starting less than this after the previous kernel ended
+COPY_BYTES = 1 << 30  # the copy probe moves this many bytes each way per launch
+_ROW = re.compile(r"^\| `(?P<name>[^`]+)` \| (?P<threads>\d+) \| (?P<n>\d+) \| "
+                  r"(?P<avg>[0-9.]+) \| (?P<nb>\d+) \| (?P<bavg>[0-9.]+|nan) \| "
+                  r"(?P<rd>[0-9.eE+]+|nan) \| (?P<wr>[0-9.eE+]+|nan) \|$")
+
+
+def kernel_short_name(name: str) -> str:
+    """'void rlmi::k_pencil<8, 0, 1024, 0>(HIP_vector_type<float, 2u>*, ...)' ->
+    'k_pencil<8, 0, 1024, 0>' (namespaces, return type and parameter list dropped)."""
+    n = name.strip().strip('"')
+    if n.startswith("void "):
+        n = n[5:]
+    depth = 0
+    for i, ch in enumerate(n):  # cut at the parameter list (outside template brackets)
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            n = n[:i]
+            break
+    head, sep, tail = n.partition("<")
+    return head.split("::")[-1] + sep + tail
+
+
+def _csv_rows(directory: str, suffix: str) -> list:
+    import csv
+    rows = []
+    for root, _, files in os.walk(directory):
+        for f in sorted(files):
+            if f.endswith(suffix):
+                with open(os.path.join(root, f), newline="") as fh:
+                    rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def _threads(row: dict) -> int:
+    if row.get("Grid_Size") not in (None, ""):
+        return int(row["Grid_Size"])
+    return (int(row.get("Grid_Size_X") or 1) * int(row.get("Grid_Size_Y") or 1)
+            * int(row.get("Grid_Size_Z") or 1))
+
+
+def trace_table(trace_dir: str) -> dict:
+    """Per (kernel, threads): launch count, average duration, and the same over the
+    back-to-back launches (started < B2B_GAP_NS after the previous kernel on the queue
+    ended), from a rocprofv3 kernel-trace CSV."""
+    rows = _csv_rows(trace_dir, "kernel_trace.csv")
+    if not rows:
+        raise FileNotFoundError(f"no *kernel_trace.csv under {trace_dir}")
+    by_queue = {}
+    for r in rows:
+        q = r.get("Queue_Id") or r.get("Stream_Id") or "0"
+        by_queue.setdefault(q, []).append(
+            (int(r["Start_Timestamp"]), int(r["End_Timestamp"]),
+             kernel_short_name(r["Kernel_Name"]), _threads(r)))
+    out = {}
+    for launches in by_queue.values():
+        launches.sort()
+        prev_end = None
+        for start, end, name, threads in launches:
+            e = out.setdefault((name, threads), {"n": 0, "ns": 0, "nb": 0, "bns": 0})
+            e["n"] += 1
+            e["ns"] += end - start
+            if prev_end is not None and start - prev_end < B2B_GAP_NS:
+                e["nb"] += 1
+                e["bns"] += end - start
+            prev_end = end if prev_end is None else max(prev_end, end)
+    return out
+
+
+def counter_table(pmc_dir: str, counter: str) -> dict:
+    """Per (kernel, threads): mean value of one rocprofv3 counter per dispatch."""
+    acc = {}
+    for r in _csv_rows(pmc_dir, "counter_collection.csv"):
+        if r.get("Counter_Name") != counter:
+            continue
+        k = (kernel_short_name(r["Kernel_Name"]), _threads(r))
+        s, n = acc.get(k, (0.0, 0))
+        acc[k] = (s + float(r["Counter_Value"]), n + 1)
+    return {k: s / n for k, (s, n) in acc.items()}
+
+
+def rocprof_summary(trace_dir: str, fetch_dir=None, write_dir=None, title: str = "",
+                    commands=()) -> str:
+    """Markdown summary of one profiled benchmark command: per kernel and thread
+    count, launches and durations from the kernel trace, and HBM read / write bytes
+    per launch from FETCH_SIZE / WRITE_SIZE (KiB per dispatch), each scaled so that
+    the library's copy kernel reads and writes exactly its known 1 GiB."""
+    tt = trace_table(trace_dir)
+    fetch = counter_table(fetch_dir, "FETCH_SIZE") if fetch_dir else {}
+    write = counter_table(write_dir, "WRITE_SIZE") if write_dir else {}
+
+    def calib(tab):
+        copy = [v for (n, _), v in tab.items() if n == "k_copy"]
+        return COPY_BYTES / (copy[0] * 1024.0) if copy and copy[0] > 0 else float("nan")
+
+    fcal, wcal = calib(fetch), calib(write)
+    lines = [f"# rocprofv3 kernel trace: {title}", "",
+             "Commands (run from the repository root on one MI355X, ROCm 7.2, after "
+             "`cd /tmp && export TMPDIR=/tmp`):", ""]
+    lines += [f"    {c}" for c in commands]
+    lines += ["", f"Kernel source sha256[:16]: `{source_hash()}`.", "",
+              "Durations from the kernel trace.  Back-to-back launches started less than "
+              f"{B2B_GAP_NS / 1000:g} µs after the previous kernel on their queue ended (the "
+              "iteration sequence of the timed steps); the others follow an idle gap (launches "
+              "bracketed by timing events, bursts, plan creation).  HBM bytes per launch = "
+              "counter (KiB x 1024) x calibration from the library's copy kernel moving 1 GiB "
+              f"each way in the same command (FETCH_SIZE x{fcal:.3f}, WRITE_SIZE x{wcal:.3f}); "
+              "nan where the counter run has no dispatch of that kernel.", "",
+              "| kernel | threads | launches | avg µs | back-to-back launches | back-to-back avg µs "
+              "| HBM read B/launch | HBM write B/launch |",
+              "|---|---|---|---|---|---|---|---|"]
+    for (name, threads), e in sorted(tt.items(), key=lambda kv: -kv[1]["ns"]):
+        rd = fetch.get((name, threads))
+        wr = write.get((name, threads))
+        lines.append(
+            f"| `{name}` | {threads} | {e['n']} | {e['ns'] / e['n'] / 1e3:.3f} | {e['nb']} | "
+            + (f"{e['bns'] / e['nb'] / 1e3:.3f}" if e["nb"] else "nan") + " | "
+            + (f"{rd * 1024 * fcal:.0f}" if rd is not None else "nan") + " | "
+            + (f"{wr * 1024 * wcal:.0f}" if wr is not None else "nan") + " |")
+    return "\n".join(lines) + "\n"
+
+
+def read_summary(path: str):
+    """Rows of a committed summary {(kernel, threads): dict}, or None if the file is
+    absent or was taken on another kernel source."""
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    h = re.search(r"kernel source sha256\[:16\]:\s*`?([0-9a-f]{16})", text, re.I)
-    v = re.search(r"per-launch HBM bytes \(calibrated\):\s*([0-9.eE+]+)", text, re.I)
-    if not h or not v or h.group(1) != source_hash():
+    h = re.search(r"Kernel source sha256\[:16\]:\s*`([0-9a-f]{16})`", text)
+    if not h or h.group(1) != source_hash():
         return None
-    return float(v.group(1))
+    rows = {}
+    for line in text.splitlines():
+        m = _ROW.match(line.strip())
+        if m:
+            rows[(m["name"], int(m["threads"]))] = dict(
+                n=int(m["n"]), avg_us=float(m["avg"]), nb=int(m["nb"]),
+                b2b_us=float(m["bavg"]), read=float(m["rd"]), write=float(m["wr"]))
+    return rows
+
+
+def trace_figures(path: str, names, threads: int):
+    """Launch-weighted back-to-back duration and HBM bytes of the named kernels (at
+    `threads` threads per launch) from a committed summary; None when unavailable."""
+    rows = read_summary(path)
+    if not rows:
+        return None
+    sel = [rows[(n, threads)] for n in names if (n, threads) in rows]
+    if not sel or sum(r["nb"] for r in sel) == 0:
+        return None
+    nb = sum(r["nb"] for r in sel)
+    n = sum(r["n"] for r in sel)
+    out = {"b2b_us": sum(r["b2b_us"] * r["nb"] for r in sel if r["nb"]) / nb,
+           "avg_us": sum(r["avg_us"] * r["n"] for r in sel) / n, "launches": n,
+           "b2b_launches": nb}
+    if all(np.isfinite(r["read"]) and np.isfinite(r["write"]) for r in sel):
+        out["traffic"] = sum((r["read"] + r["write"]) * r["n"] for r in sel) / n
+    return out
+
+
+def summary_path(workload: str) -> str:
+    return os.path.join(PROFILES, f"kernel_trace_{workload}.md")
 
 
 def run_workload(torch, rl, synth, cfg: int, steps: int, warmup: int, workload: str):
@@ -109,9 +275,10 @@ def run_workload(torch, rl, synth, cfg: int, steps: int, warmup: int, workload: 
     # The timed region gives the throughput.  The same steps are then repeated with
     # every launch of the plan bracketed by a pair of HIP events on the plan's
     # stream, stamped by the launch itself: each pass's duration comes from the
-    # real iteration sequence.  The events lengthen the gaps between launches (not
-    # the launches), so the throughput is taken without them.
+    # real iteration sequence.  The events leave idle gaps between launches (not
+    # inside them), so the throughput is taken without them.
     ms, _ = timed(False)
+    u_final = u.clone()  # the estimate after n_iter iterations (last timed step)
     ms_events, live = timed(True)
     value = nvox * n_iter / (ms * 1e-3) / 1e9
 
@@ -121,8 +288,8 @@ def run_workload(torch, rl, synth, cfg: int, steps: int, warmup: int, workload: 
 
     kb = kernel_bytes(shape)
     # per-pass durations from the timed region; beside them, a burst of 20
-    # back-to-back launches of the same pass (faster: each launch follows one of
-    # its own kind, not the pass before it in the iteration)
+    # back-to-back launches of the same pass (each launch follows one of its own
+    # kind, not the pass before it in the iteration)
     scratch = u0.clone()
     per_kind = {}
     for kind in ("x_ratio", "x_update", "y", "z_otf"):
@@ -130,19 +297,31 @@ def run_workload(torch, rl, synth, cfg: int, steps: int, warmup: int, workload: 
         avg_us = kms / cnt * 1e3
         byts = kb[kind]
         burst_us = plan.time_pass(kind, d, scratch, reps=20) * 1e3
+        names, threads = plan.pass_kernel(kind)
         per_kind[kind] = dict(launches_per_step=cnt / steps, avg_us=round(avg_us, 3),
                               total_ms=round(kms / steps, 4), bytes_per_launch=byts,
                               gbs=round(byts / (avg_us * 1e-6) / 1e9, 1),
-                              burst_us=round(burst_us, 3))
+                              burst_us=round(burst_us, 3), kernels=names, threads=threads)
     dom = max(per_kind, key=lambda k: per_kind[k]["total_ms"])
     dk = per_kind[dom]
-    achieved = dk["bytes_per_launch"] / (dk["avg_us"] * 1e-6) / 1e9
-    traffic = measured_traffic(dom, workload)
-    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-            "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-            "traffic": traffic, "bytes_per_launch": dk["bytes_per_launch"],
-            "avg_launch_us": dk["avg_us"],
-            "duration_source": "HIP events around every launch over a repeat of the timed steps"}
+    events_gbs = dk["bytes_per_launch"] / (dk["avg_us"] * 1e-6) / 1e9
+    tr = trace_figures(summary_path(workload), dk["kernels"], dk["threads"])
+    if tr is not None:
+        dur_us = tr["b2b_us"]
+        source = (f"rocprofv3 kernel trace of this benchmark ({os.path.basename(summary_path(workload))}): "
+                  f"average of the kernel's {tr['b2b_launches']} back-to-back launches")
+    else:
+        dur_us = dk["avg_us"]
+        source = "HIP events around every launch over a repeat of the timed steps (no current trace)"
+    achieved = dk["bytes_per_launch"] / (dur_us * 1e-6) / 1e9
+    roof = {"bound": "hbm", "kernel": dom, "kernels": dk["kernels"], "threads": dk["threads"],
+            "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": round(tr["traffic"]) if tr and "traffic" in tr else None,
+            "bytes_per_launch": dk["bytes_per_launch"], "avg_launch_us": round(dur_us, 3),
+            "duration_source": source,
+            "events_avg_launch_us": dk["avg_us"], "events_achieved": round(events_gbs, 1),
+            "events_frac": round(events_gbs / PEAK_HBM_GBS, 4)}
     # whole-iteration effective bandwidth over all passes (the prologue's X r2c, and
     # the last update, which skips the forward transform, included); kernel time is
     # every timed launch of the plan, flux reductions included
@@ -153,10 +332,11 @@ def run_workload(torch, rl, synth, cfg: int, steps: int, warmup: int, workload: 
     plan.close()
     return dict(shape=shape, n_iter=n_iter, nvox=nvox, ms=ms, value=value, roofline=roof,
                 ms_events=ms_events, per_kind=per_kind, flux_drift=drift,
-                launch=launch_cfg,
+                launch=launch_cfg, u=u_final,
                 launches_per_step={k: cnt / steps for k, (cnt, _) in live.items() if cnt},
                 all_kernels_gbs=round(model_bytes / (kernel_ms * 1e-3) / 1e9, 1),
-                bytes_per_vi=round(model_bytes / (nvox * n_iter), 2))
+                bytes_per_vi=round(model_bytes / (nvox * n_iter), 2),
+                model_effective_gbs=round(model_bytes / (nvox * n_iter) * value, 1))
 
 
 def run_batched(torch, rl, synth, steps: int, warmup: int, count: int = 96, n_iter: int = 50,
@@ -428,8 +608,9 @@ def run_stop(torch, rl, synth, steps: int, cfg: int = 1):
            "fixed_ms": round(timed(lambda: plan.iterate(d, u, n_max)), 3)}
     # the log-likelihood threshold lies between two consecutive relative improvements
     # of the FP64 oracle on this volume (1.50e-4 and 1.00e-4), clear of both
+    # fsc: stop once the single-image FSC resolution no longer improves (threshold 0)
     rules = {"loglik": (1.2e-4, None), "change": (2e-3, None), "psnr": (0.01, truth),
-             "ssim": (1e-3, truth)}
+             "ssim": (1e-3, truth), "fsc": (0.0, None)}
     for name, (tau, ref) in rules.items():
         ms = timed(lambda: plan.iterate_until(d, u, n_max, name, tau, reference=ref))
         n, hist = plan.stop()
@@ -462,17 +643,9 @@ def run_stop(torch, rl, synth, steps: int, cfg: int = 1):
     fb = np.fft.rfftn(un[1::2, 1::2, 1::2])
     _ = np.real(fa * np.conj(fb)).sum(), (np.abs(fa) ** 2).sum(), (np.abs(fb) ** 2).sum()
     host_ms = (time.perf_counter() - t) * 1e3
-    # FSC-guided stop: stop when the resolution no longer improves (threshold 0)
-    u.copy_(u0)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    n_fsc, hist = plan.iterate_until_fsc(d, u, n_max, 0.0, nbins=64)
-    fsc_stop_ms = (time.perf_counter() - t) * 1e3
-    out["fsc"] = {"single_image_fsc_ms": round(fsc_ms, 3), "resolution_cycles_per_voxel": res,
-                  "numpy_fft_only_ms_context": round(host_ms, 1),
-                  "guided_stop_threshold": 0.0, "guided_stop_iterations": n_fsc,
-                  "guided_stop_ms": round(fsc_stop_ms, 2),
-                  "guided_stop_last_resolution": float(hist[-1])}
+    out["fsc"].update({"single_image_fsc_ms": round(fsc_ms, 3),
+                       "resolution_cycles_per_voxel": res,
+                       "numpy_fft_only_ms_context": round(host_ms, 1)})
     plan.close()
     return out
 
@@ -496,9 +669,10 @@ def copy_probe(torch, rl, nbytes: int = 1 << 30, reps: int = 20) -> float:
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(synth, n_iter_sample: int = 16):
-    """The FP64 oracle on the host cores, bounded sample of the headline workload.
-    Returns the record and the oracle's estimate after the sample's iterations."""
+def cpu_baseline(c: dict, n_iter_sample: int = 1):
+    """The FP64 oracle on the host cores, on a bounded sample of the headline
+    workload (its first iteration(s)).  Returns the record and the oracle's estimate
+    after the sample's iterations."""
     import oracle
     try:
         from threadpoolctl import threadpool_info
@@ -506,15 +680,16 @@ def cpu_baseline(synth, n_iter_sample: int = 16):
                        if i.get("internal_api") in ("openblas", "mkl", "blis")] or [1])
     except Exception:
         threads = os.cpu_count() or 1
-    c = synth.make_config(1)
     nvox = int(np.prod(c["shape"]))
     t = time.perf_counter()
     u, _, _ = oracle.rl(c["d"], c["psf"], c["u0"], n_iter_sample)
     dt = time.perf_counter() - t
+    shp = "x".join(str(n) for n in reversed(c["shape"]))
     return ({"value": round(nvox * n_iter_sample / dt / 1e9, 6), "unit": "Gvoxel-iter/s",
              "cores": threads, "kind": "oracle",
-             "sample": f"{n_iter_sample} FP64 RL iterations of the 128x256x256 volume "
-                       f"(naive per-axis DFT by BLAS matrix products), {dt:.1f} s"}, u)
+             "sample": f"{n_iter_sample} FP64 RL iteration(s) of the {shp} volume, transfer "
+                       f"function included (naive per-axis DFT by BLAS matrix products), "
+                       f"{dt:.1f} s"}, u)
 
 
 def cpu_fft_context(synth, n_iter: int = 4) -> dict:
@@ -540,21 +715,88 @@ def cpu_fft_context(synth, n_iter: int = 4) -> dict:
             "sample": f"{n_iter} iterations of the 128x256x256 volume, {dt:.1f} s"}
 
 
-def gpu_estimate_after(torch, rl, synth, cfg: int, n_iter: int) -> np.ndarray:
-    c = synth.make_config(cfg)
+def gpu_estimate_after(torch, rl, c: dict, n_iter: int) -> np.ndarray:
     with rl.Plan(torch.from_numpy(c["psf"]).to("cuda:0"), autotune=True) as p:
         u = torch.from_numpy(c["u0"]).to("cuda:0")
         p.iterate(torch.from_numpy(c["d"]).to("cuda:0"), u, n_iter)
         return u.cpu().numpy()
 
 
+def sample_rel_l2(u, samples, n_iter: int):
+    """Relative L2 distance of the estimate u (device tensor) to the oracle's stored
+    values at its sample voxels after n_iter iterations; None if not stored."""
+    if samples is None or n_iter not in samples[1]:
+        return None
+    pts, vals = samples
+    g = u[tuple(pts.T)].double().cpu().numpy() if hasattr(u, "cpu") else u[tuple(pts.T)]
+    return float(np.linalg.norm(g - vals[n_iter]) / np.linalg.norm(vals[n_iter]))
+
+
+def summarize_main(argv):
+    ap = argparse.ArgumentParser(prog="bench.py --rocprof-summary")
+    ap.add_argument("--rocprof-summary", nargs="+", metavar="DIR", required=True,
+                    help="kernel-trace directory, then optionally FETCH_SIZE and WRITE_SIZE "
+                         "counter directories")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--title", default="")
+    ap.add_argument("--cmd", action="append", default=[],
+                    help="the profiled command(s), recorded in the summary")
+    a = ap.parse_args(argv)
+    dirs = a.rocprof_summary + [None] * (3 - len(a.rocprof_summary))
+    text = rocprof_summary(dirs[0], dirs[1], dirs[2], a.title, a.cmd)
+    with open(a.out, "w") as f:
+        f.write(text)
+    print(f"wrote {a.out}")
+
+
+class _CachedInputs:
+    """The seeded generator with each configuration drawn once per process."""
+
+    def __init__(self, synth):
+        self._synth = synth
+        self._cache = {}
+
+    def make_config(self, cfg: int) -> dict:
+        if cfg not in self._cache:
+            self._cache[cfg] = self._synth.make_config(cfg)
+        return self._cache[cfg]
+
+    def __getattr__(self, name):
+        return getattr(self._synth, name)
+
+
+GOLDEN_256 = os.path.join(ROOT, "tests", "golden", "rl_256x256x128_samples.txt")
+
+
+def oracle_samples_cfg1():
+    """The FP64 oracle's estimate of the 256x256x128 workload after 50 and 100
+    iterations at stored sample voxels (written by the script beside the file)."""
+    if not os.path.exists(GOLDEN_256):
+        return None
+    a = np.loadtxt(GOLDEN_256, comments="#")
+    return a[:, :3].astype(np.int64), {50: a[:, 3], 100: a[:, 4]}
+
+
+def record(run: dict, workload: str, sigma) -> dict:
+    return {"workload": workload, "shape_zyx": list(run["shape"]), "n_iter": run["n_iter"],
+            "psf_sigma_xyz": list(sigma), "value": round(run["value"], 3),
+            "unit": "Gvoxel-iter/s", "ms_per_step": round(run["ms"], 4),
+            "ms_per_step_with_launch_events": round(run["ms_events"], 4),
+            "roofline": run["roofline"], "all_kernels_gbs": run["all_kernels_gbs"],
+            "bytes_per_vi": run["bytes_per_vi"], "model_effective_gbs": run["model_effective_gbs"],
+            "per_kind": run["per_kind"], "launch": run["launch"], "flux_drift": run["flux_drift"]}
+
+
 def main():
+    if "--rocprof-summary" in sys.argv:
+        return summarize_main(sys.argv[1:])
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-large", action="store_true", help="skip the 256x512x512 workload")
+    ap.add_argument("--no-mall", action="store_true",
+                    help="skip the 256x256x128 (last-level-cache resident) workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 96-volume workload")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision forms")
     ap.add_argument("--no-accel", action="store_true", help="skip the extrapolated form")
@@ -568,25 +810,26 @@ def main():
     rank = int(os.environ.get("RANK", "0"))
 
     import torch
-    from paper_2510_14143_amd import rl, synth
+    from paper_2510_14143_amd import rl, synth as synth_mod
+    synth = _CachedInputs(synth_mod)
 
     copy_gbs = copy_probe(torch, rl)
     log(f"copy probe: {copy_gbs:.1f} GB/s (read + write)")
-    log("workload: config 1 (128x256x256, 100 it)")
-    main_run = run_workload(torch, rl, synth, 1, args.steps, args.warmup, "cfg1")
-    log(json.dumps({"cfg1_per_kind": main_run["per_kind"]}))
-    large = None
-    if not args.no_large:
-        log("workload: config 2 (256x512x512, 50 it)")
-        lr = run_workload(torch, rl, synth, 2, max(1, args.steps // 2), 1, "cfg2")
-        log(json.dumps({"cfg2_per_kind": lr["per_kind"]}))
-        large = {"workload": "rl_fp32_256x512x512_50it", "value": round(lr["value"], 3),
-                 "unit": "Gvoxel-iter/s", "ms_per_step": round(lr["ms"], 3),
-                 "ms_per_step_with_launch_events": round(lr["ms_events"], 3),
-                 "roofline": lr["roofline"], "all_kernels_gbs": lr["all_kernels_gbs"],
-                 "model_effective_gbs": round(lr["bytes_per_vi"] * lr["value"], 1),
-                 "launch": lr["launch"],
-                 "bytes_per_vi": lr["bytes_per_vi"], "flux_drift": lr["flux_drift"]}
+    log("workload: 256x512x512 volume, 50 iterations (headline)")
+    head_w = "rl_fp32_256x512x512_50it"
+    main_run = run_workload(torch, rl, synth, 2, args.steps, args.warmup, head_w)
+    head_rel50 = sample_rel_l2(main_run.pop("u"), oracle_samples(), 50)
+    log(json.dumps({"headline_per_kind": main_run["per_kind"]}))
+    mall = None
+    if not args.no_mall:
+        log("workload: 128x256x256 volume, 100 iterations (fits the last-level cache)")
+        w1 = "rl_fp32_128x256x256_100it"
+        r1 = run_workload(torch, rl, synth, 1, args.steps, args.warmup, w1)
+        mall = record(r1, w1, synth.CONFIGS[1]["sigma"])
+        mall["note"] = ("working set about 135 MB, inside the 256 MB last-level cache: its "
+                        "bandwidth figures include cache hits and are not HBM figures")
+        mall["rel_l2_vs_oracle_samples_at_100"] = sample_rel_l2(r1["u"], oracle_samples_cfg1(), 100)
+        log(json.dumps({"mall_resident": mall}))
     batched = None
     if not args.no_batch:
         log("workload: batched, 96 uneven volumes, 50 it")
@@ -614,13 +857,15 @@ def main():
         log(json.dumps({"split": split}))
     cpu = cpu_ctx = None
     if rank == 0 and not args.no_cpu:
-        log("cpu baseline (oracle)")
-        cpu, u_ref = cpu_baseline(synth)
-        n_s = 16
-        u_gpu = gpu_estimate_after(torch, rl, synth, 1, n_s)
+        log("cpu baseline (oracle, first iteration of the headline volume)")
+        c2 = synth.make_config(2)
+        n_s = 1
+        cpu, u_ref = cpu_baseline(c2, n_s)
+        u_gpu = gpu_estimate_after(torch, rl, c2, n_s)
         import oracle
         cpu["gpu_rel_l2_vs_oracle"] = float(oracle.rel_l2(u_gpu, u_ref))
         cpu["gpu_rel_l2_iterations"] = n_s
+        del u_ref, u_gpu
         log("cpu FFT context (scipy)")
         cpu_ctx = cpu_fft_context(synth)
 
@@ -638,18 +883,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "rl_fp32_128x256x256_100it", "shape_zyx": list(main_run["shape"]),
-                   "n_iter": main_run["n_iter"], "psf_sigma_xyz": [2.0, 2.0, 5.0],
+        "config": {"workload": head_w, "shape_zyx": list(main_run["shape"]),
+                   "n_iter": main_run["n_iter"], "psf_sigma_xyz": list(synth.CONFIGS[2]["sigma"]),
                    "boundary": "periodic", "parallelism": "single_gpu",
                    "launch": main_run["launch"]},
         "roofline": main_run["roofline"],
         "cpu_baseline": cpu,
         "cpu_fft_context": cpu_ctx,
+        "rel_l2_vs_oracle_samples_at_50": head_rel50,
         "all_kernels_gbs": main_run["all_kernels_gbs"],
         "bytes_per_vi": main_run["bytes_per_vi"],
-        "model_effective_gbs": round(main_run["bytes_per_vi"] * main_run["value"], 1),
+        "model_effective_gbs": main_run["model_effective_gbs"],
         "flux_drift": main_run["flux_drift"],
-        "large": large,
+        "per_kind": main_run["per_kind"],
+        "mall_resident": mall,
         "batched": batched,
         "split": split,
         "accel": accel,

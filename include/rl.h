@@ -216,6 +216,17 @@ rl_status rl_iterate_batch(rl_plan p, const float* const* observed, float* const
  *   RL_STOP_SSIM: mean SSIM of u_{k+1} against `reference` (see rl_ssim); stops at
  *     k >= 1 when ssim_k - ssim_{k-1} < threshold (k + 1 iterations done).  Runs
  *     three window-sum passes after each update (about 170 bytes per voxel).
+ *   RL_STOP_FSC: single-image Fourier shell correlation resolution of u_{k+1}
+ *     (no reference; paper §4.3 lists FRC/FSC among its metrics): the FSC of the
+ *     two diagonal half-size sub-volumes u[0::2, 0::2, 0::2] and u[1::2, 1::2, 1::2]
+ *     (rl_split_diagonal) with fsc_bins shells and crossing threshold
+ *     fsc_threshold (rl_fsc), in cycles per voxel of the half-size volumes; stops
+ *     at k >= 1 when res_k - res_{k-1} < threshold (k + 1 iterations done).  Needs
+ *     a periodic plan with even dimensions whose halves are transform lengths
+ *     (else RL_E_UNSUPPORTED).  After each update the split, two half-size
+ *     forward transforms and the shell sums run on the device (about 10 bytes per
+ *     voxel); a transform-only plan of the half shape and its buffers (about 3.5
+ *     bytes per voxel) are allocated on first use and kept with the plan.
  * No stop happens before min_iter iterations are done.  The metric is
  * accumulated in FP64 inside the passes (no extra pass over the volume; PSNR
  * reads the reference, 4 bytes per voxel per iteration).
@@ -224,7 +235,8 @@ typedef enum {
   RL_STOP_LOGLIK = 1,
   RL_STOP_CHANGE = 2,
   RL_STOP_PSNR = 3,
-  RL_STOP_SSIM = 4
+  RL_STOP_SSIM = 4,
+  RL_STOP_FSC = 5
 } rl_stop_metric;
 
 typedef struct {
@@ -232,6 +244,8 @@ typedef struct {
   double threshold;        /* finite */
   int min_iter;            /* >= 0 */
   const float* reference;  /* RL_STOP_PSNR and RL_STOP_SSIM: device, the volume's shape */
+  int fsc_bins;            /* RL_STOP_FSC: shells, 0 = 64, else in [2, 1024] */
+  double fsc_threshold;    /* RL_STOP_FSC: FSC crossing level, 0 = 1/7, else finite */
 } rl_stop_rule;
 
 /*
@@ -248,7 +262,7 @@ rl_status rl_iterate_stop(rl_plan p, const float* observed, float* estimate, int
 /*
  * After rl_iterate_stop (else RL_E_INVALID): iterations carried out in
  * *n_done, and the metric value of every check in history[0 .. min(cap, n) - 1]
- * with n in *n_history (LOGLIK: l_0 .. l_k; CHANGE, PSNR and SSIM: one value
+ * with n in *n_history (LOGLIK: l_0 .. l_k; CHANGE, PSNR, SSIM and FSC: one value
  * per iteration done).  Synchronises the plan's stream.
  */
 rl_status rl_plan_get_stop(rl_plan p, int* n_done, double* history, int cap, int* n_history);
@@ -363,6 +377,18 @@ rl_status rl_plan_get_timing(rl_plan p, int count[RL_KERNEL_KINDS], double ms[RL
  */
 rl_status rl_plan_time_pass(rl_plan p, int kind, const float* observed, float* estimate,
                             int reps, double* ms_per_launch);
+
+/*
+ * Kernels of one pass kind as a profiler names them (measurement support):
+ * writes the kernel template name(s) used for kind RL_KERNEL_X_RATIO,
+ * RL_KERNEL_X_UPDATE, RL_KERNEL_Y or RL_KERNEL_Z_OTF into name[0 .. cap-1]
+ * (NUL-terminated; two names joined by '|' where the pass has a forward and an
+ * inverse, or a plain and a conjugate, variant, e.g.
+ * "k_pencil<8, 0, 1024, 0>|k_pencil<8, 1, 1024, 0>") and the number of threads
+ * one launch runs (work-groups times work-group size) into *threads.
+ * RL_E_INVALID if cap is too small.  Single-volume plans only.
+ */
+rl_status rl_plan_get_pass_kernel(rl_plan p, int kind, char* name, size_t cap, int64_t* threads);
 
 /*
  * Bandwidth probe (measurement support): copy `bytes` bytes (multiple of 16)

@@ -276,6 +276,11 @@ struct rl_plan_s {
   double* fsc_part = nullptr;     // shell partials, fsc_cap shells
   double* fsc_out = nullptr;
   int fsc_cap = 0;
+  // FSC-guided stopping (allocated on first use): transform-only plan of the half
+  // shape, which owns the two half-size sub-volumes and the FSC buffers
+  rl_plan fsc_sub = nullptr;
+  float* fsc_a = nullptr;
+  float* fsc_b = nullptr;
   // structural similarity (allocated on first use)
   double* ssim_a = nullptr;       // X window sums, 5 channels
   double* ssim_b = nullptr;       // X and Y window sums
@@ -405,6 +410,9 @@ void release(rl_plan p) {
   (void)hipFree(p->ssim_b);
   (void)hipFree(p->ssim_part);
   (void)hipFree(p->ssim_range);
+  (void)hipFree(p->fsc_a);
+  (void)hipFree(p->fsc_b);
+  if (p->fsc_sub) release(p->fsc_sub);
   for (rl_plan c : p->classes) release(c);
   if (p->graph_full) (void)hipGraphExecDestroy(p->graph_full);
   if (p->graph_last) (void)hipGraphExecDestroy(p->graph_last);
@@ -977,7 +985,9 @@ rl_status check_device_present() {
 }
 
 // Build the plan of `count` volumes of one (validated) shape on `device`;
-// psfs[i] is volume i's PSF (validated device pointers).  Synchronous.
+// psfs[i] is volume i's PSF (validated device pointers).  psfs == nullptr builds
+// a transform-only plan (no transfer function; used for the half-size transforms
+// of the single-image FSC).  Synchronous.
 rl_status build_class(const Geometry& geo, int count, const float* const* psfs, int device,
                       const rl_options* opt, hipStream_t stream, rl_plan* out) {
   rl_status st;
@@ -1034,13 +1044,13 @@ rl_status build_class(const Geometry& geo, int count, const float* const* psfs, 
     delete p;
     return hip_fail(e, "hipSetDevice");
   }
-  p->flux_cap = 128;
+  p->flux_cap = psfs ? 128 : 1;
   // >= any X grid times the iteration capacity times the volumes
   p->n_partials = (size_t)p->nrows * p->flux_cap * count;
   if (p->n_partials < 3 * (size_t)kStatBlocks) p->n_partials = 3 * kStatBlocks;
   const size_t spec_bytes = p->spec_elems * sizeof(float2) * (size_t)count;
   if ((e = hipMalloc(&p->spec, spec_bytes)) != hipSuccess ||
-      (e = hipMalloc(&p->otf, spec_bytes)) != hipSuccess ||
+      (psfs && (e = hipMalloc(&p->otf, spec_bytes)) != hipSuccess) ||
       (e = hipMalloc(&p->tw_x, (size_t)nx * sizeof(float2))) != hipSuccess ||
       (e = hipMalloc(&p->tw_y, (size_t)ny * sizeof(float2))) != hipSuccess ||
       (e = hipMalloc(&p->tw_z, (size_t)nz * sizeof(float2))) != hipSuccess ||
@@ -1089,7 +1099,7 @@ rl_status build_class(const Geometry& geo, int count, const float* const* psfs, 
   RL_TRY(rlmi::launch_twiddles(p->tw_x, (int)nx, p->stream));
   RL_TRY(rlmi::launch_twiddles(p->tw_y, (int)ny, p->stream));
   RL_TRY(rlmi::launch_twiddles(p->tw_z, (int)nz, p->stream));
-  for (int v = 0; v < count; ++v) {
+  for (int v = 0; psfs && v < count; ++v) {
     const float* psf = psfs[v];
     RL_TRY(rlmi::launch_psf_stats(psf, p->psf_z * p->psf_y * p->psf_x, p->partials,
                                   kStatBlocks, p->counter, p->stats, p->stream));
@@ -1424,6 +1434,70 @@ rl_status ssim_impl(rl_plan p, const float* u, const float* ref, double* value) 
   return RL_OK;
 }
 
+rl_status fsc_lcm(rl_plan p, int64_t* lcm);
+rl_status fsc_buffers(rl_plan p, int nbins);
+rl_status enqueue_fsc(rl_plan p, const float* a, const float* b, int nbins, double threshold,
+                      int64_t lcm);
+
+// Shape rules of FSC-guided stopping (no device work): a periodic plan with even
+// dimensions whose halves are transform lengths.
+rl_status fsc_stop_check(rl_plan p, const rl_stop_rule* rule, int* nbins, double* fthr) {
+  if (p->boundary != RL_BOUNDARY_PERIODIC)
+    return fail(RL_E_UNSUPPORTED, "FSC-guided stopping needs a periodic plan");
+  *nbins = rule->fsc_bins == 0 ? 64 : rule->fsc_bins;
+  if (*nbins < 2 || *nbins > 1024) return fail(RL_E_INVALID, "fsc_bins must be 0 or in [2, 1024]");
+  if (!std::isfinite(rule->fsc_threshold)) return fail(RL_E_INVALID, "fsc_threshold must be finite");
+  *fthr = rule->fsc_threshold == 0.0 ? 1.0 / 7.0 : rule->fsc_threshold;
+  const int64_t half[3] = {p->nz / 2, p->ny / 2, p->nx / 2};
+  if (p->nz % 2 || p->ny % 2 || p->nx % 2 || half[0] < 1 || half[1] < 1)
+    return fail(RL_E_UNSUPPORTED, "FSC-guided stopping needs even dimensions");
+  rl_status st = check_shape(half);
+  if (st != RL_OK)
+    return fail(RL_E_UNSUPPORTED, "FSC-guided stopping: the half-size transforms are not "
+                                  "supported (" + g_err + ")");
+  return RL_OK;
+}
+
+// Transform-only plan of the half shape with its FSC buffers, and the two half-size
+// sub-volumes (first use; kept with the plan).
+rl_status fsc_stop_setup(rl_plan p, int nbins, int64_t* lcm) {
+  if (!p->fsc_sub) {
+    Geometry geo;
+    geo.boundary = RL_BOUNDARY_PERIODIC;
+    const int64_t half[3] = {p->nz / 2, p->ny / 2, p->nx / 2};
+    for (int i = 0; i < 3; ++i) geo.grid[i] = geo.vol[i] = geo.psf[i] = half[i];
+    rl_plan sub = nullptr;
+    rl_status st = build_class(geo, 1, nullptr, p->device, nullptr, p->stream, &sub);
+    if (st != RL_OK) return st;
+    p->fsc_sub = sub;
+  }
+  rl_plan sub = p->fsc_sub;
+  sub->stream = p->stream;
+  hipError_t e;
+  const size_t hb = (size_t)sub->nvox * sizeof(float);
+  if (!p->fsc_a && (e = hipMalloc(&p->fsc_a, hb)) != hipSuccess)
+    return hip_fail(e, "hipMalloc(FSC half volume)");
+  if (!p->fsc_b && (e = hipMalloc(&p->fsc_b, hb)) != hipSuccess)
+    return hip_fail(e, "hipMalloc(FSC half volume)");
+  rl_status st = fsc_lcm(sub, lcm);
+  if (st != RL_OK) return st;
+  return fsc_buffers(sub, nbins);
+}
+
+// Single-image FSC resolution of u into the half-size plan's fsc_out, guarded by
+// the plan's stop flag: diagonal split, two forward transforms, shell sums.
+rl_status enqueue_fsc_stop(rl_plan p, const float* u, int nbins, double fthr, int64_t lcm) {
+  rl_plan sub = p->fsc_sub;
+  hipError_t e = rlmi::launch_split_diag(u, (int)p->nz, (int)p->ny, (int)p->nx, p->fsc_a,
+                                         p->fsc_b, p->stream, p->active_stop);
+  if (e != hipSuccess) return hip_fail(e, "split launch");
+  sub->stream = p->stream;
+  sub->active_stop = p->active_stop;
+  rl_status st = enqueue_fsc(sub, p->fsc_a, p->fsc_b, nbins, fthr, lcm);
+  sub->active_stop = nullptr;
+  return st;
+}
+
 // Metric-guided stopping: every launch of the call reads the plan's stop flag
 // and does nothing once the metric kernel has set it, so the whole call is
 // enqueued at once and ends early on the device without a host round trip.
@@ -1436,7 +1510,8 @@ rl_status iterate_stop_impl(rl_plan p, const float* observed, float* estimate, i
     return fail(RL_E_UNSUPPORTED, "stop rules are not available with extrapolation");
   if (!rule) return fail(RL_E_INVALID, "rule is NULL");
   if (rule->metric != RL_STOP_LOGLIK && rule->metric != RL_STOP_CHANGE &&
-      rule->metric != RL_STOP_PSNR && rule->metric != RL_STOP_SSIM)
+      rule->metric != RL_STOP_PSNR && rule->metric != RL_STOP_SSIM &&
+      rule->metric != RL_STOP_FSC)
     return fail(RL_E_INVALID, "unknown stop metric");
   if (!std::isfinite(rule->threshold)) return fail(RL_E_INVALID, "threshold must be finite");
   if (rule->min_iter < 0) return fail(RL_E_INVALID, "min_iter must be >= 0");
@@ -1448,9 +1523,16 @@ rl_status iterate_stop_impl(rl_plan p, const float* observed, float* estimate, i
   if ((rule->metric == RL_STOP_PSNR || rule->metric == RL_STOP_SSIM) &&
       (st = check_dev_ptr(rule->reference, bytes, &dev, "reference")) != RL_OK)
     return st;
+  int fsc_bins = 0;
+  double fsc_thr = 0.0;
+  int64_t fsc_l = 0;
+  if (rule->metric == RL_STOP_FSC && (st = fsc_stop_check(p, rule, &fsc_bins, &fsc_thr)) != RL_OK)
+    return st;
   hipError_t e = hipSetDevice(p->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   if (rule->metric == RL_STOP_SSIM && (st = ssim_buffers(p)) != RL_OK) return st;
+  if (rule->metric == RL_STOP_FSC && (st = fsc_stop_setup(p, fsc_bins, &fsc_l)) != RL_OK)
+    return st;
   if ((st = ensure_flux_capacity(p, max_iter > 0 ? max_iter : 1, nullptr)) != RL_OK) return st;
   if ((e = hipMemsetAsync(p->stop, 0, 4 * sizeof(int), p->stream)) != hipSuccess)
     return hip_fail(e, "hipMemsetAsync(stop)");
@@ -1462,12 +1544,14 @@ rl_status iterate_stop_impl(rl_plan p, const float* observed, float* estimate, i
   const int groups = (int)p->x_grid.x;
   const SsimGeom sg = ssim_geom(p);
   auto decide = [&](int it) -> rl_status {
-    const bool ssim = metric == RL_STOP_SSIM;
+    const bool ssim = metric == RL_STOP_SSIM, fsc = metric == RL_STOP_FSC;
+    const double* mp = ssim  ? p->ssim_part
+                       : fsc ? p->fsc_sub->fsc_out + 4 * (size_t)(fsc_bins + 1)  // resolution
+                             : p->met_partials;
     hipError_t me = rlmi::launch_metric(
-        ssim ? p->ssim_part : p->met_partials, ssim ? (int)sg.blocks : groups,
-        ssim ? rlmi::MET_SSIM : metric, it, rule->threshold, rule->min_iter,
-        ssim ? (long long)(sg.nxo * sg.nyo * sg.nzo) : (long long)p->vnvox, p->mhist, p->stop,
-        p->stream);
+        mp, ssim ? (int)sg.blocks : fsc ? 1 : groups, metric, it, rule->threshold,
+        rule->min_iter, ssim ? (long long)(sg.nxo * sg.nyo * sg.nzo) : (long long)p->vnvox,
+        p->mhist, p->stop, p->stream);
     return me == hipSuccess ? RL_OK : hip_fail(me, "metric launch");
   };
   p->active_stop = p->stop;
@@ -1503,6 +1587,9 @@ rl_status iterate_stop_impl(rl_plan p, const float* observed, float* estimate, i
     if (metric == RL_STOP_SSIM &&
         (st = enqueue_ssim(p, estimate, rule->reference, it == 0)) != RL_OK)
       break;
+    if (metric == RL_STOP_FSC &&
+        (st = enqueue_fsc_stop(p, estimate, fsc_bins, fsc_thr, fsc_l)) != RL_OK)
+      break;
     if (metric != RL_STOP_LOGLIK && (st = decide(it)) != RL_OK) break;
     if (w.do_fwd && (st = run_yz_filter(p, false)) != RL_OK) break;
   }
@@ -1534,22 +1621,30 @@ rl_status forward3(rl_plan p, const float* x, float2* spec) {
   return st;
 }
 
-rl_status fsc_impl(rl_plan p, const float* a, const float* b, int nbins, double threshold,
-                   double* curve, double* resolution) {
-  rl_status st = check_plan(p);
-  if (st != RL_OK) return st;
-  if (p->is_batch) return fail(RL_E_UNSUPPORTED, "rl_fsc takes a single-volume plan");
-  if (p->boundary != RL_BOUNDARY_PERIODIC)
-    return fail(RL_E_UNSUPPORTED, "rl_fsc needs a periodic plan (its grid is the volume)");
-  if (nbins < 2 || nbins > 1024) return fail(RL_E_INVALID, "nbins must be in [2, 1024]");
-  if (!std::isfinite(threshold)) return fail(RL_E_INVALID, "threshold must be finite");
-  if (!curve) return fail(RL_E_INVALID, "curve is NULL");
-  const size_t bytes = (size_t)p->vnvox * sizeof(float);
-  int dev = p->device;
-  if ((st = check_dev_ptr(a, bytes, &dev, "a")) != RL_OK) return st;
-  if ((st = check_dev_ptr(b, bytes, &dev, "b")) != RL_OK) return st;
-  hipError_t e = hipSetDevice(p->device);
-  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+// lcm of the grid dimensions, the common denominator of the exact shell index
+// (below 2^21 keeps its integer arithmetic inside 64 bits).
+rl_status fsc_lcm(rl_plan p, int64_t* lcm) {
+  auto gcd = [](int64_t x, int64_t y) {
+    while (y) {
+      const int64_t t = x % y;
+      x = y;
+      y = t;
+    }
+    return x;
+  };
+  int64_t l = p->nz;
+  l = l / gcd(l, p->ny) * p->ny;
+  l = l / gcd(l, p->nx) * p->nx;
+  if (l >= ((int64_t)1 << 21))
+    return fail(RL_E_UNSUPPORTED, "FSC: lcm of the dimensions must be below 2^21");
+  *lcm = l;
+  return RL_OK;
+}
+
+// Second spectrum and shell-sum buffers of a plan for nbins shells (first use or
+// more shells than before).
+rl_status fsc_buffers(rl_plan p, int nbins) {
+  hipError_t e;
   if (!p->spec2 &&
       (e = hipMalloc(&p->spec2, p->spec_elems * sizeof(float2))) != hipSuccess)
     return hip_fail(e, "hipMalloc(second spectrum)");
@@ -1568,25 +1663,42 @@ rl_status fsc_impl(rl_plan p, const float* a, const float* b, int nbins, double 
       return hip_fail(e, "hipMalloc(shell sums)");
     p->fsc_cap = nbins + 1;
   }
-  auto gcd = [](int64_t x, int64_t y) {
-    while (y) {
-      const int64_t t = x % y;
-      x = y;
-      y = t;
-    }
-    return x;
-  };
-  int64_t lcm = p->nz;
-  lcm = lcm / gcd(lcm, p->ny) * p->ny;
-  lcm = lcm / gcd(lcm, p->nx) * p->nx;
-  if (lcm >= ((int64_t)1 << 21))
-    return fail(RL_E_UNSUPPORTED, "rl_fsc: lcm of the dimensions must be below 2^21");
+  return RL_OK;
+}
+
+// FSC of volumes a and b of the plan's shape into p->fsc_out (curve, sums,
+// resolution); every launch honours the plan's active stop flag.
+rl_status enqueue_fsc(rl_plan p, const float* a, const float* b, int nbins, double threshold,
+                      int64_t lcm) {
+  rl_status st;
   if ((st = forward3(p, a, p->spec)) != RL_OK) return st;
   if ((st = forward3(p, b, p->spec2)) != RL_OK) return st;
-  if ((e = rlmi::launch_fsc(p->spec, p->spec2, (int)p->nz, (int)p->ny, (int)p->nx, (int)p->xt,
-                            nbins, (long long)lcm, threshold, p->fsc_part, p->fsc_out,
-                            p->stream)) != hipSuccess)
-    return hip_fail(e, "shell correlation launch");
+  hipError_t e = rlmi::launch_fsc(p->spec, p->spec2, (int)p->nz, (int)p->ny, (int)p->nx,
+                                  (int)p->xt, nbins, (long long)lcm, threshold, p->fsc_part,
+                                  p->fsc_out, p->stream, p->active_stop);
+  return e == hipSuccess ? RL_OK : hip_fail(e, "shell correlation launch");
+}
+
+rl_status fsc_impl(rl_plan p, const float* a, const float* b, int nbins, double threshold,
+                   double* curve, double* resolution) {
+  rl_status st = check_plan(p);
+  if (st != RL_OK) return st;
+  if (p->is_batch) return fail(RL_E_UNSUPPORTED, "rl_fsc takes a single-volume plan");
+  if (p->boundary != RL_BOUNDARY_PERIODIC)
+    return fail(RL_E_UNSUPPORTED, "rl_fsc needs a periodic plan (its grid is the volume)");
+  if (nbins < 2 || nbins > 1024) return fail(RL_E_INVALID, "nbins must be in [2, 1024]");
+  if (!std::isfinite(threshold)) return fail(RL_E_INVALID, "threshold must be finite");
+  if (!curve) return fail(RL_E_INVALID, "curve is NULL");
+  const size_t bytes = (size_t)p->vnvox * sizeof(float);
+  int dev = p->device;
+  if ((st = check_dev_ptr(a, bytes, &dev, "a")) != RL_OK) return st;
+  if ((st = check_dev_ptr(b, bytes, &dev, "b")) != RL_OK) return st;
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  int64_t lcm = 0;
+  if ((st = fsc_lcm(p, &lcm)) != RL_OK) return st;
+  if ((st = fsc_buffers(p, nbins)) != RL_OK) return st;
+  if ((st = enqueue_fsc(p, a, b, nbins, threshold, lcm)) != RL_OK) return st;
   std::vector<double> h(4 * (size_t)(nbins + 1) + 1);
   if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return hip_fail(e, "execution");
   if ((e = hipMemcpy(h.data(), p->fsc_out, h.size() * sizeof(double), hipMemcpyDeviceToHost)) !=
@@ -2161,6 +2273,42 @@ rl_status rl_plan_time_pass(rl_plan p, int kind, const float* observed, float* e
   p->timing = timing;
   if (st == RL_OK) *ms_per_launch = (double)ms / reps;
   return st;
+}
+
+rl_status rl_plan_get_pass_kernel(rl_plan p, int kind, char* name, size_t cap, int64_t* threads) {
+  rl_status st = check_plan(p);
+  if (st != RL_OK) return st;
+  if (p->is_batch) return fail(RL_E_UNSUPPORTED, "pass kernels of a single-volume plan");
+  if (!name || !threads) return fail(RL_E_INVALID, "name or threads is NULL");
+  std::string s;
+  int64_t n = 0;
+  auto pencil = [&](const Pencil& pc, int m0, int m1) {
+    // the instantiation launch_pencil picks for this shape and precision
+    const int maxt = (int)pc.block.x > rlmi::kPencilMaxThreads ? 1024 : rlmi::kPencilMaxThreads;
+    const int prec = (pc.ax.E == 16 && pc.block.x % 64 == 0) ? p->precision : 0;
+    for (int m : {m0, m1}) {
+      if (!s.empty()) s += "|";
+      s += "k_pencil<" + std::to_string(pc.ax.E) + ", " + std::to_string(m) + ", " +
+           std::to_string(maxt) + ", " + std::to_string(prec) + ">";
+    }
+    n = (int64_t)pc.grid.x * pc.grid.y * pc.block.x;
+  };
+  switch (kind) {
+    case RL_KERNEL_X_RATIO:
+    case RL_KERNEL_X_UPDATE:
+      s = "k_xrow<" + std::to_string(p->axx.E) + ", " +
+          std::to_string(kind == RL_KERNEL_X_RATIO ? (int)rlmi::XM_RATIO : (int)rlmi::XM_UPDATE) +
+          ", " + std::to_string(p->axx.E == 16 ? p->precision : 0) + ">";
+      n = (int64_t)p->x_grid.x * p->x_block.x;
+      break;
+    case RL_KERNEL_Y: pencil(p->py, rlmi::PM_FWD, rlmi::PM_INV); break;
+    case RL_KERNEL_Z_OTF: pencil(p->pz, rlmi::PM_FKI, rlmi::PM_FCKI); break;
+    default: return fail(RL_E_INVALID, "kind must be X_RATIO, X_UPDATE, Y or Z_OTF");
+  }
+  if (s.size() + 1 > cap) return fail(RL_E_INVALID, "name buffer too small");
+  std::memcpy(name, s.c_str(), s.size() + 1);
+  *threads = n;
+  return RL_OK;
 }
 
 rl_status rl_plan_set_timing(rl_plan p, int enable) {

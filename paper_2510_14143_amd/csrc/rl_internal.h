@@ -57,7 +57,8 @@ struct PencilArgs {
 
 enum PencilMode { PM_FWD = 0, PM_INV = 1, PM_FKI = 2, PM_FCKI = 3 };
 // Stopping metrics (values of rl_stop_metric).
-enum Metric { MET_NONE = 0, MET_LOGLIK = 1, MET_CHANGE = 2, MET_PSNR = 3, MET_SSIM = 4 };
+enum Metric { MET_NONE = 0, MET_LOGLIK = 1, MET_CHANGE = 2, MET_PSNR = 3, MET_SSIM = 4,
+              MET_FSC = 5 };
 constexpr int kMetRows = 7;
 // XM_PREDICT and XM_UPDATE_ACC are the two X passes of the extrapolated
 // (Biggs-Andrews) iteration: the prediction y = max(x + alpha h, 0) transformed
@@ -154,7 +155,8 @@ hipError_t launch_accel_alpha(const double* acc_partials, int groups, int it, fl
                               hipEvent_t ev1 = nullptr);
 // Metric of iteration `it` from the work-group partials (rows: LOGLIK: sum of
 // d log q - q; CHANGE: sum (u' - u)^2, sum u^2; PSNR: sum u', u'^2, u' g, g, g^2,
-// min g, max g; SSIM: sum of window SSIMs, nvox = number of windows), stored in
+// min g, max g; SSIM: sum of window SSIMs, nvox = number of windows; FSC: one row
+// holding the resolution, groups = 1), stored in
 // hist[it]; then the stop decision (see rl.h): stop[0] = 1 and stop[1] =
 // iterations carried out.  stop[2] = entries of hist.
 // Does nothing once stop[0] is set.
@@ -172,15 +174,17 @@ hipError_t launch_ssim(const float* u, const float* g, int nz, int ny, int nx, d
                        double* part, bool want_range, const int* stop, hipStream_t s);
 // a = u[0::2, 0::2, 0::2], b = u[1::2, 1::2, 1::2] of a dense nz x ny x nx volume
 // (even dimensions; a and b hold (nz/2)(ny/2)(nx/2) floats each).
+// If stop is non-null and *stop != 0 the kernel does nothing.
 hipError_t launch_split_diag(const float* u, int nz, int ny, int nx, float* a, float* b,
-                             hipStream_t s);
+                             hipStream_t s, const int* stop = nullptr);
 // Fourier shell correlation of two half spectra (tiled layout of an nz x ny x nx
 // grid with xt tiles; lcm = lcm(nz, ny, nx) < 2^21): part holds
 // nz * xt * (nbins + 1) * 3 doubles, out 4 * (nbins + 1) + 1 (curve, the three
-// sums per shell, resolution).
+// sums per shell, resolution).  If stop is non-null and *stop != 0 the kernels
+// do nothing.
 hipError_t launch_fsc(const float2* F, const float2* G, int nz, int ny, int nx, int xt, int nbins,
                       long long lcm, double threshold, double* part, double* out,
-                      hipStream_t s);
+                      hipStream_t s, const int* stop = nullptr);
 // *counter += 1 (one thread); used to advance a device-side iteration index.
 hipError_t launch_advance(int* counter, hipStream_t s);
 // *counter = value (one thread).

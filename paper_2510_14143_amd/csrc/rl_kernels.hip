@@ -894,9 +894,9 @@ __global__ void __launch_bounds__(256) k_metric(const double* __restrict__ mp, i
                                                 double* __restrict__ hist, int* __restrict__ stop) {
   if (stop[0]) return;
   const int tid = threadIdx.x;
-  const int rows = (metric == MET_LOGLIK || metric == MET_SSIM) ? 1
-                   : metric == MET_CHANGE                        ? 2
-                                                                 : kMetRows;
+  const int rows = (metric == MET_LOGLIK || metric == MET_SSIM || metric == MET_FSC) ? 1
+                   : metric == MET_CHANGE                                            ? 2
+                                                                                     : kMetRows;
   __shared__ double ws[kMetRows][4];
   for (int r = 0; r < rows; ++r) {
     const int op = (metric == MET_PSNR && r == 5) ? 1 : (metric == MET_PSNR && r == 6) ? 2 : 0;
@@ -935,6 +935,9 @@ __global__ void __launch_bounds__(256) k_metric(const double* __restrict__ mp, i
     halt = done >= min_iter && m < threshold;
   } else if (metric == MET_SSIM) {
     m = s[0] / (double)nvox;  // nvox: number of windows
+    halt = it >= 1 && done >= min_iter && m - hist[it - 1] < threshold;
+  } else if (metric == MET_FSC) {
+    m = s[0];  // resolution of the single-image FSC
     halt = it >= 1 && done >= min_iter && m - hist[it - 1] < threshold;
   } else {
     const double n = (double)nvox;
@@ -1013,7 +1016,8 @@ __global__ void __launch_bounds__(256) k_accel_alpha(const double* __restrict__ 
 // ---------------------------------------------------------------------------
 // a[z][y][x] = u[2z][2y][2x], b[z][y][x] = u[2z+1][2y+1][2x+1] (half-size volumes).
 __global__ void k_split_diag(const float* __restrict__ u, int nz, int ny, int nx,
-                             float* __restrict__ a, float* __restrict__ b) {
+                             float* __restrict__ a, float* __restrict__ b, const int* stop) {
+  if (stop && *stop) return;
   const int hz = nz / 2, hy = ny / 2, hx = nx / 2;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
   if (x >= hx) return;
@@ -1038,7 +1042,8 @@ __device__ __forceinline__ long long abs_index(int j, int n) {
 __global__ void __launch_bounds__(256) k_shell(const float2* __restrict__ F,
                                                const float2* __restrict__ G, int nz, int ny,
                                                int nx, int xt, int nbins, long long lcm,
-                                               double* __restrict__ part) {
+                                               double* __restrict__ part, const int* stop) {
+  if (stop && *stop) return;  // stopped: the whole work-group leaves together
   extern __shared__ double hist[];  // (nbins + 1) * 3
   const int tid = threadIdx.x;
   const int nb1 = nbins + 1;
@@ -1080,7 +1085,8 @@ __global__ void __launch_bounds__(256) k_shell(const float2* __restrict__ F,
 // interpolated between the centres of shells s-1 and s; 0.5 if none.
 __global__ void __launch_bounds__(256) k_fsc_final(const double* __restrict__ part, int groups,
                                                    int nbins, double threshold,
-                                                   double* __restrict__ out) {
+                                                   double* __restrict__ out, const int* stop) {
+  if (stop && *stop) return;
   const int nb1 = nbins + 1;
   for (int sh = threadIdx.x; sh < nb1; sh += blockDim.x) {
     double n = 0.0, d1 = 0.0, d2 = 0.0;
@@ -1568,21 +1574,22 @@ hipError_t launch_ssim(const float* u, const float* g, int nz, int ny, int nx, d
 }
 
 hipError_t launch_split_diag(const float* u, int nz, int ny, int nx, float* a, float* b,
-                             hipStream_t s) {
+                             hipStream_t s, const int* stop) {
   dim3 g((unsigned)((nx / 2 + 255) / 256), (unsigned)(ny / 2), (unsigned)(nz / 2));
-  hipLaunchKernelGGL(k_split_diag, g, dim3(256), 0, s, u, nz, ny, nx, a, b);
+  hipLaunchKernelGGL(k_split_diag, g, dim3(256), 0, s, u, nz, ny, nx, a, b, stop);
   return hipGetLastError();
 }
 
 hipError_t launch_fsc(const float2* F, const float2* G, int nz, int ny, int nx, int xt, int nbins,
                       long long lcm, double threshold, double* part, double* out,
-                      hipStream_t s) {
+                      hipStream_t s, const int* stop) {
   const size_t lds = (size_t)(nbins + 1) * 3 * sizeof(double);
   hipLaunchKernelGGL(k_shell, dim3((unsigned)xt, (unsigned)nz), dim3(256), lds, s, F, G, nz, ny,
-                     nx, xt, nbins, lcm, part);
+                     nx, xt, nbins, lcm, part, stop);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fsc_final, dim3(1), dim3(256), 0, s, part, nz * xt, nbins, threshold, out);
+  hipLaunchKernelGGL(k_fsc_final, dim3(1), dim3(256), 0, s, part, nz * xt, nbins, threshold, out,
+                     stop);
   return hipGetLastError();
 }
 

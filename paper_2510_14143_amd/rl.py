@@ -27,9 +27,9 @@ RL_PRECISION_FP32, RL_PRECISION_SPLIT_BF16, RL_PRECISION_SPLIT_FP16 = 0, 1, 2
 _PRECISIONS = {"fp32": RL_PRECISION_FP32, "split_bf16": RL_PRECISION_SPLIT_BF16,
                "split_fp16": RL_PRECISION_SPLIT_FP16}
 RL_ACCEL_NONE, RL_ACCEL_BIGGS_ANDREWS = 0, 1
-RL_STOP_LOGLIK, RL_STOP_CHANGE, RL_STOP_PSNR, RL_STOP_SSIM = 1, 2, 3, 4
+RL_STOP_LOGLIK, RL_STOP_CHANGE, RL_STOP_PSNR, RL_STOP_SSIM, RL_STOP_FSC = 1, 2, 3, 4, 5
 _STOP_METRICS = {"loglik": RL_STOP_LOGLIK, "change": RL_STOP_CHANGE, "psnr": RL_STOP_PSNR,
-                 "ssim": RL_STOP_SSIM}
+                 "ssim": RL_STOP_SSIM, "fsc": RL_STOP_FSC}
 _ACCELS = {"none": RL_ACCEL_NONE, "biggs_andrews": RL_ACCEL_BIGGS_ANDREWS}
 KERNEL_KINDS = ("x_r2c", "x_c2r", "x_ratio", "x_update", "y", "z_otf", "z", "other")
 
@@ -48,7 +48,8 @@ _STATUS_NAMES = {0: "RL_OK", 1: "RL_E_INVALID", 2: "RL_E_UNSUPPORTED", 3: "RL_E_
 
 class _StopRule(ctypes.Structure):
     _fields_ = [("metric", ctypes.c_int), ("threshold", ctypes.c_double), ("min_iter", ctypes.c_int),
-                ("reference", ctypes.c_void_p)]
+                ("reference", ctypes.c_void_p), ("fsc_bins", ctypes.c_int),
+                ("fsc_threshold", ctypes.c_double)]
 
 
 class _Options(ctypes.Structure):
@@ -96,6 +97,8 @@ def lib() -> ctypes.CDLL:
                                ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "rl_plan_get_timing": ([vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)],
                                ctypes.c_int),
+        "rl_plan_get_pass_kernel": ([vp, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t, i64p],
+                                    ctypes.c_int),
         "rl_probe_copy": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
         "rl_plan_create_batch": ([ctypes.c_int, i64p, ctypes.POINTER(vp), ctypes.c_int,
                                   ctypes.POINTER(_Options), ctypes.POINTER(vp)], ctypes.c_int),
@@ -215,9 +218,10 @@ def rl_plan_get_alpha(plan: int) -> np.ndarray:
 
 
 def rl_iterate_stop(plan: int, observed_ptr: int, estimate_ptr: int, max_iter: int, metric: int,
-                    threshold: float, min_iter: int = 0, reference_ptr: int = 0) -> None:
+                    threshold: float, min_iter: int = 0, reference_ptr: int = 0,
+                    fsc_bins: int = 0, fsc_threshold: float = 0.0) -> None:
     rule = _StopRule(int(metric), float(threshold), int(min_iter),
-                     ctypes.c_void_p(reference_ptr or None))
+                     ctypes.c_void_p(reference_ptr or None), int(fsc_bins), float(fsc_threshold))
     _check(lib().rl_iterate_stop(ctypes.c_void_p(plan), ctypes.c_void_p(observed_ptr),
                                  ctypes.c_void_p(estimate_ptr), int(max_iter), ctypes.byref(rule)))
 
@@ -308,6 +312,15 @@ def rl_plan_time_pass(plan: int, kind: str, observed_ptr: int, estimate_ptr: int
     return ms.value
 
 
+def rl_plan_get_pass_kernel(plan: int, kind: str):
+    """(kernel names, threads per launch) of a pass kind as a profiler names them."""
+    buf = ctypes.create_string_buffer(512)
+    threads = ctypes.c_int64(0)
+    _check(lib().rl_plan_get_pass_kernel(ctypes.c_void_p(plan), KERNEL_KINDS.index(kind), buf,
+                                         ctypes.c_size_t(len(buf)), ctypes.byref(threads)))
+    return buf.value.decode().split("|"), threads.value
+
+
 def rl_probe_copy(src_ptr: int, dst_ptr: int, nbytes: int, stream: int = 0) -> None:
     _check(lib().rl_probe_copy(ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr),
                                ctypes.c_size_t(nbytes), ctypes.c_void_p(stream or None)))
@@ -390,9 +403,12 @@ class Plan:
         rl_iterate(self.handle, observed.data_ptr(), estimate.data_ptr(), n_iter)
 
     def iterate_until(self, observed, estimate, max_iter: int, metric: str, threshold: float,
-                      min_iter: int = 0, reference=None) -> None:
+                      min_iter: int = 0, reference=None, fsc_bins: int = 0,
+                      fsc_threshold: float = 0.0) -> None:
         """At most max_iter iterations, stopped on the device by `metric` ("loglik",
-        "change", or "psnr" / "ssim" against `reference`); results via stop() and flux()."""
+        "change", "fsc" (single-image FSC resolution; fsc_bins shells, crossing
+        level fsc_threshold, 0 = defaults 64 and 1/7), or "psnr" / "ssim" against
+        `reference`); results via stop() and flux()."""
         self._live()
         _check_volume(observed, self.shape, self.device, "observed")
         _check_volume(estimate, self.shape, self.device, "estimate")
@@ -406,35 +422,18 @@ class Plan:
             ref_ptr = reference.data_ptr()
         self._bind_stream()
         rl_iterate_stop(self.handle, observed.data_ptr(), estimate.data_ptr(), max_iter,
-                        _STOP_METRICS[metric], threshold, min_iter, ref_ptr)
+                        _STOP_METRICS[metric], threshold, min_iter, ref_ptr, fsc_bins,
+                        fsc_threshold)
 
     def iterate_until_fsc(self, observed, estimate, max_iter: int, threshold: float,
                           nbins: int = 64, fsc_threshold: float = 1.0 / 7.0, min_iter: int = 0):
-        """At most max_iter iterations, stopped once the single-image FSC resolution
-        of the estimate (FSC of its two diagonal half-size sub-volumes, frequency where
-        it first drops below fsc_threshold) improves by less than `threshold` cycles
-        per voxel between consecutive iterations.  Every step runs on the device
-        (iterations, split, transforms, shell sums); the host only compares the
-        resolutions.  Returns (iterations done, resolution after each)."""
-        import torch
-        self._live()
-        if any(n % 2 for n in self.shape):
-            raise ValueError("the single-image split needs even dimensions")
-        half = tuple(n // 2 for n in self.shape)
-        delta = torch.zeros(half, dtype=torch.float32, device=self.device)
-        delta[tuple(n // 2 for n in half)] = 1.0
-        hist = []
-        n_done = 0
-        with Plan(delta) as q:
-            while n_done < max_iter:
-                self.iterate(observed, estimate, 1)
-                n_done += 1
-                a, b = split_diagonal(estimate)
-                _, res = q.fsc(a, b, nbins, fsc_threshold)
-                hist.append(res)
-                if len(hist) >= 2 and n_done >= min_iter and hist[-1] - hist[-2] < threshold:
-                    break
-        return n_done, np.array(hist)
+        """iterate_until with the "fsc" rule: at most max_iter iterations, stopped on
+        the device once the single-image FSC resolution of the estimate improves by
+        less than `threshold` cycles per voxel between consecutive iterations.
+        Returns (iterations done, resolution after each) (synchronises)."""
+        self.iterate_until(observed, estimate, max_iter, "fsc", threshold, min_iter=min_iter,
+                           fsc_bins=nbins, fsc_threshold=fsc_threshold)
+        return self.stop()
 
     def stop(self):
         """(iterations done, metric history) of the last iterate_until call (synchronises)."""
@@ -514,6 +513,12 @@ class Plan:
         """Elements per thread and work-group widths in use (and whether tuned)."""
         self._live()
         return rl_plan_get_launch(self.handle)
+
+    def pass_kernel(self, kind: str):
+        """(kernel names, threads per launch) of a pass kind ('x_ratio', 'x_update',
+        'y', 'z_otf') as a profiler's kernel trace names them."""
+        self._live()
+        return rl_plan_get_pass_kernel(self.handle, kind)
 
     def _live(self):
         if getattr(self, "handle", None) is None:

@@ -2,6 +2,7 @@
 graph launch per iteration, against the FP64 oracle and against single-volume
 plans (same kernels, so equal bit for bit)."""
 
+import os
 import sys
 
 import numpy as np
@@ -162,3 +163,53 @@ def test_batch_errors(torch):
             rl.rl_iterate(bp.handle, d[0].data_ptr(), u[0].data_ptr(), 1)
         with pytest.raises(rl.RLError):
             rl.conv3d_fft(bp.handle, d[0].data_ptr(), u[0].data_ptr())
+
+
+BATCH_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                            "rl_batch96_samples.txt")
+
+
+def batch_golden():
+    """{volume: (points, values)} and {volume: flux} of the FP64 oracle after 50
+    iterations, written by tests/golden/make_rl_batch96_samples.py (oracle only)."""
+    flux, pts = {}, {}
+    with open(BATCH_GOLDEN) as f:
+        for line in f:
+            if line.startswith("# flux "):
+                _, _, v, val = line.split()
+                flux[int(v)] = float(val)
+    a = np.loadtxt(BATCH_GOLDEN, comments="#")
+    for v in np.unique(a[:, 0]).astype(int):
+        rows = a[a[:, 0] == v]
+        pts[v] = (rows[:, 1:4].astype(np.int64), rows[:, 4])
+    return pts, flux
+
+
+def test_full_size_batch_workload_50_iterations(torch, batch96):
+    # the benchmark's batch as it is timed (autotuned, 50 iterations, graph replays):
+    # the first and last volume of every shape class against the oracle's stored
+    # estimate at sampled voxels, every volume's flux against its data, and the
+    # stored volumes' flux against the oracle's
+    vols = batch96
+    n_iter = 50
+    pts, ref_flux = batch_golden()
+    shapes = {tuple(vols[v]["shape"]) for v in pts}
+    assert len(shapes) == 5 and len(pts) == 10  # two volumes of every class
+    say("full-size batch, 50 iterations, volumes", sorted(pts))
+    with rl.BatchPlan([dev(torch, v["psf"]) for v in vols], autotune=True) as bp:
+        d = [dev(torch, v["d"]) for v in vols]
+        u = [dev(torch, v["u0"]) for v in vols]
+        bp.iterate(d, u, n_iter)
+        flux = bp.flux()
+        got = {v: u[v].cpu().numpy().astype(np.float64) for v in pts}
+    for i, v in enumerate(vols):
+        total = float(v["d"].sum(dtype=np.float64))
+        assert np.all(np.abs(flux[i] - total) / total <= 1e-6), (i, flux[i][-1], total)
+    for v, (p, ref) in sorted(pts.items()):
+        g = got[v][tuple(p.T)]
+        err = float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
+        worst = float(np.max(np.abs(g - ref)) / np.max(np.abs(ref)))
+        say("  volume", v, vols[v]["shape"], "relL2 over", len(ref), "samples", err,
+            "max abs / peak", worst)
+        assert err <= 1e-4
+        assert abs(flux[v][-1] - ref_flux[v]) / ref_flux[v] <= 1e-6

@@ -9,6 +9,7 @@ import sys
 import numpy as np
 import pytest
 
+import oracle
 from oracle import fsc_oracle as fo
 from oracle import stop_oracle as so
 from paper_2510_14143_amd import rl, synth
@@ -135,3 +136,50 @@ def test_full_size_single_image_fsc_as_benchmarked(torch):
     say("  max |d curve|", err, "resolution", res, fo.resolution(ref, 64))
     assert err <= 1e-5
     assert abs(res - fo.resolution(ref, 64)) <= 1e-4
+
+
+def test_fsc_stop_rule_errors(torch):
+    # FSC-guided stopping through the C ABI: bad shell counts and thresholds are
+    # rejected before any device work, odd dimensions and the zero boundary are not
+    # supported
+    shape = (8, 16, 32)
+    d = dev(torch, synth.uniform_volume(shape, 95) + 1.0)
+    psf = dev(torch, synth.gaussian_psf(shape, (1.0, 1.0, 1.0)))
+    with rl.Plan(psf) as p:
+        u = d.clone()
+        for nb in (1, 1025, -3):
+            with pytest.raises(rl.RLError) as ei:
+                p.iterate_until(d, u, 3, "fsc", 0.0, fsc_bins=nb)
+            assert ei.value.status == rl.RL_E_INVALID
+        with pytest.raises(rl.RLError) as ei:
+            p.iterate_until(d, u, 3, "fsc", 0.0, fsc_threshold=float("nan"))
+        assert ei.value.status == rl.RL_E_INVALID
+        assert torch.equal(u, d)  # nothing ran
+    odd = (8, 16, 18)  # the half-size volume would have 9 columns (odd nx is not supported)
+    with rl.Plan(dev(torch, synth.gaussian_psf(odd, (1.0, 1.0, 1.0)))) as p:
+        dd = dev(torch, synth.uniform_volume(odd, 96) + 1.0)
+        with pytest.raises(rl.RLError) as ei:
+            p.iterate_until(dd, dd.clone(), 3, "fsc", 0.0)
+        assert ei.value.status == rl.RL_E_UNSUPPORTED
+    with rl.Plan(dev(torch, synth.gaussian_psf((3, 3, 3), (1.0, 1.0, 1.0))), shape=shape,
+                 boundary="zero") as p:
+        with pytest.raises(rl.RLError) as ei:
+            p.iterate_until(d, d.clone(), 3, "fsc", 0.0)
+        assert ei.value.status == rl.RL_E_UNSUPPORTED
+
+
+def test_fsc_stop_history_full_size(torch):
+    # the benchmark's 128x256x256 volume: the device rule's resolution history over 3
+    # iterations (it never fires) against the stop oracle's
+    c = synth.make_config(1)
+    say("full-size fsc-guided stop history", c["shape"])
+    n = 3
+    ref_u, ref_n, ref_hist = so.rl_stop(c["d"], c["psf"], c["u0"], n, "fsc", -1e300, nbins=64)
+    with rl.Plan(dev(torch, c["psf"]), autotune=True) as p:
+        u = dev(torch, c["u0"])
+        n_done, hist = p.iterate_until_fsc(dev(torch, c["d"]), u, n, -1e300, nbins=64)
+        got = u.cpu().numpy()
+    say("  gpu", hist, "oracle", ref_hist)
+    assert n_done == ref_n == n
+    assert np.max(np.abs(hist - ref_hist)) <= 1e-4
+    assert oracle.rel_l2(got, ref_u) <= 1e-5

@@ -5,6 +5,7 @@ Tolerances (relative L2, FP64, oracle as reference): one FP32 convolution
 oracle's flux <= 1e-6 relative.
 """
 
+import os
 import sys
 
 import numpy as np
@@ -424,3 +425,37 @@ def test_full_size_config1_rl_matches_oracle_autotuned(torch):
     say("  rel L2", err, "max abs error / peak", worst)
     assert err <= 1e-5
     assert worst <= 1e-5
+
+
+GOLDEN_CFG1 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "rl_256x256x128_samples.txt")
+
+
+def test_full_size_config1_rl_100_iterations_vs_oracle_samples(torch):
+    # the 128x256x256 workload as the benchmark runs it (autotuned plan, 100
+    # iterations in one call) against the FP64 oracle's stored estimate after 50 and
+    # 100 iterations at 4096 sampled voxels (tests/golden/make_rl_256x256x128_samples.py)
+    c = synth.make_config(1)
+    a = np.loadtxt(GOLDEN_CFG1, comments="#")
+    with open(GOLDEN_CFG1) as f:
+        ref_flux = [float(t) for t in next(ln for ln in f if ln.startswith("# flux:")).split()[2:]]
+    pts = a[:, :3].astype(np.int64)
+    say("full-size rl, 100 iterations, vs oracle samples", c["shape"])
+    with rl.Plan(dev(torch, c["psf"]), autotune=True) as p:
+        d = dev(torch, c["d"])
+        u = dev(torch, c["u0"])
+        p.iterate(d, u, 50)
+        u50 = u.cpu().numpy().astype(np.float64)
+        f50 = p.flux()
+        u.copy_(dev(torch, c["u0"]))
+        p.iterate(d, u, 100)
+        u100 = u.cpu().numpy().astype(np.float64)
+        f100 = p.flux()
+    for k, got, ref, fl, rf in ((50, u50, a[:, 3], f50, ref_flux[0]),
+                                (100, u100, a[:, 4], f100, ref_flux[1])):
+        g = got[tuple(pts.T)]
+        err = float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
+        worst = float(np.max(np.abs(g - ref)) / np.max(np.abs(ref)))
+        say(f"  {k} iterations: relL2 over {len(ref)} samples {err:.3e}, max abs / peak {worst:.3e}")
+        assert err <= RL_TOL
+        assert abs(fl[-1] - rf) / rf <= 1e-6
