@@ -577,6 +577,38 @@ def run_zero_boundary(torch, rl, synth, steps: int, cfg: int = 1):
             "flux_drift": float(np.max(np.abs(flux - total)) / total)}
 
 
+def run_paper_shape(torch, rl, synth, steps: int, n_iter: int = 20):
+    """The paper's own stack shape, 30x2160x2560 (periodic, PSF of the volume's
+    shape): throughput of n_iter iterations per step (the paper states no iteration
+    count) and the plan's launch configuration."""
+    c = synth.make_paper_shape()
+    dev = torch.device("cuda:0")
+    psf = torch.from_numpy(c["psf"]).to(dev)
+    d = torch.from_numpy(c["d"]).to(dev)
+    u0 = torch.from_numpy(c["u0"]).to(dev)
+    nvox = int(np.prod(c["shape"]))
+    plan = rl.Plan(psf, autotune=True)
+    u = u0.clone()
+    plan.iterate(d, u, n_iter)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        u.copy_(u0)
+        plan.iterate(d, u, n_iter)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    flux = plan.flux()
+    total = float(c["d"].sum(dtype=np.float64))
+    launch = plan.launch()
+    plan.close()
+    return {"workload": f"rl_fp32_2560x2160x30_{n_iter}it", "shape_zyx": list(c["shape"]),
+            "unit": "Gvoxel-iter/s", "ms_per_step": round(ms, 3),
+            "value": round(nvox * n_iter / (ms * 1e-3) / 1e9, 3), "launch": launch,
+            "flux_drift": float(np.max(np.abs(flux - total)) / total)}
+
+
 def run_stop(torch, rl, synth, steps: int, cfg: int = 1):
     """Metric-guided stopping on the 128x256x256 volume: iterations chosen by each
     rule (at most the configuration's 100) and the wall-clock time of the call,
@@ -802,6 +834,8 @@ def main():
     ap.add_argument("--no-accel", action="store_true", help="skip the extrapolated form")
     ap.add_argument("--no-zero", action="store_true", help="skip the zero-boundary form")
     ap.add_argument("--no-stop", action="store_true", help="skip metric-guided stopping")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the paper's 30x2160x2560 stack shape")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the batched and single-volume paths "
@@ -855,6 +889,11 @@ def main():
         log("workload: split-precision forms, 256x512x512, 50 it")
         split = run_split(torch, rl, synth, max(1, args.steps // 5))
         log(json.dumps({"split": split}))
+    paper = None
+    if not args.no_paper:
+        log("workload: the paper's stack shape 30x2160x2560, 20 it")
+        paper = run_paper_shape(torch, rl, synth, max(1, args.steps // 5))
+        log(json.dumps({"paper_shape": paper}))
     cpu = cpu_ctx = None
     if rank == 0 and not args.no_cpu:
         log("cpu baseline (oracle, first iteration of the headline volume)")
@@ -902,6 +941,7 @@ def main():
         "accel": accel,
         "zero_boundary": zero,
         "stop": stop,
+        "paper_shape": paper,
         "copy_probe_gbs": round(copy_gbs, 1),
     }
     if rank == 0:

@@ -80,10 +80,14 @@ typedef enum {
 
 typedef enum {
   RL_PRECISION_FP32 = 0,       /* FP32 transforms, FP64 twiddle generation and sums */
-  RL_PRECISION_SPLIT_BF16 = 1, /* radix-16 butterflies as 32x32 real DFT matrices on MFMA,
-                                  operands split into BF16 hi + lo, three products
-                                  accumulated in FP32; other stages, twiddles, the
-                                  elementwise steps and all sums as in FP32 mode */
+  RL_PRECISION_SPLIT_BF16 = 1, /* radix-16 butterflies of the Y and Z transforms as 32x32
+                                  real DFT matrices on MFMA, operands split into BF16
+                                  hi + lo, three products accumulated in FP32; other
+                                  stages, twiddles, the elementwise steps and all sums as
+                                  in FP32 mode.  The X transforms (fused with the ratio
+                                  and the update) keep FP32 radix-8/4 butterflies unless
+                                  rl_options.x_elems = 16 asks for radix-16 stages there,
+                                  which then run on MFMA too */
   RL_PRECISION_SPLIT_FP16 = 2  /* the same with FP16 hi + lo and a power-of-two scale
                                   per 16-point DFT */
 } rl_precision;
@@ -165,6 +169,24 @@ rl_status rl_plan_create_ex(const int64_t shape[3], const float* psf, int bounda
  * unsplit one.
  */
 rl_status rl_iterate(rl_plan p, const float* observed, float* estimate, int n_iter);
+
+/*
+ * rl_iterate for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * plain iteration, kernels and results as rl_iterate, with its per-iteration flux
+ * partials in a fixed device array of the library (8 MiB, 2^20 FP64 values, one
+ * per GPU, held until the process ends) instead of plan memory that rl_iterate
+ * grows for long calls.  The call makes no device allocation.  Limits (else
+ * RL_E_INVALID, nothing enqueued): n_iter times the plan's X-pass work-group
+ * count <= 2^20, and n_iter <= the plan's flux capacity (128, or the longest
+ * earlier rl_iterate call).  Plain single-volume plans without per-launch
+ * timing only (else RL_E_UNSUPPORTED).  Every call on a GPU shares that GPU's
+ * array: calls that overlap in time on one GPU (other streams, other plans,
+ * other host threads) race and give wrong flux values; order them.  The array
+ * keeps the last call's contents, which no call reads before writing.
+ * rl_plan_get_flux returns the flux as after rl_iterate.
+ */
+rl_status rl_iterate_noalloc(rl_plan p, const float* observed, float* estimate, int n_iter);
 
 /*
  * out = H x: circular convolution of x (device) with the plan's normalised PSF,

@@ -32,7 +32,7 @@ namespace {
 constexpr uint64_t kMagic = 0x31504c4d494c52ull;  // live plan
 constexpr uint64_t kDead = 0xdeadbeefdeadbeefull;
 constexpr int64_t kMaxNx = 4096;
-constexpr int64_t kMaxNyz = 1024;
+constexpr int64_t kMaxNyz = 4096;
 constexpr size_t kMaxLds = 65536;        // X pass work-group LDS budget
 constexpr size_t kMaxPencilLds = 163840;  // gfx950: 160 KB per work-group
 constexpr int kStatBlocks = 256;
@@ -149,11 +149,44 @@ int e_with_cap(int64_t L, int cap) {
   return best;
 }
 
+// Y and Z pencils (a work-group per group of pencils, any thread count): where no
+// E carries the whole odd part of L (odd parts 27, 45, 135, ...; e.g. 2160 =
+// 16 * 135), E only needs every odd prime of L, so that each radix-3/5/7 stage
+// still takes its R inputs from one thread's registers; the thread count P = L/E
+// then carries the remaining odd factor.
+bool strict_e_exists(int64_t L, int64_t max_p) {
+  for (int E : kE)
+    if (e_ok(L, E, max_p)) return true;
+  return false;
+}
+
+bool e_ok_relaxed(int64_t L, int E, int64_t max_p) {
+  bool known = false;
+  for (int k : kE) known = known || (k == E);
+  if (!known || L < 1 || L % E != 0 || L / E > max_p) return false;
+  int64_t o = odd_part(L);
+  for (int r : {3, 5, 7}) {
+    if (o % r == 0 && E % r != 0) return false;
+    while (o % r == 0) o /= r;
+  }
+  if (o != 1) return false;  // a prime the radix stages do not have
+  if (pow2_part(L) != 1 && pow2_part(E) < 2) return false;
+  return radices(L, E).size() <= (size_t)rlmi::kMaxStages;
+}
+
+bool e_ok_yz(int64_t L, int E, int64_t max_p) {
+  return strict_e_exists(L, max_p) ? e_ok(L, E, max_p) : e_ok_relaxed(L, E, max_p);
+}
+
 int pick_e(int64_t L) {
   if (L == 1) return 1;
   if (is_pow2(L)) return (int)(L < 16 ? L : 16);
-  const int e = e_with_cap(L, 24);
-  return e > 0 ? e : e_with_cap(L, 30);
+  int e = e_with_cap(L, 24);
+  if (e == 0) e = e_with_cap(L, 30);
+  if (e == 0)  // relaxed pencil rule: the largest E that applies
+    for (int E : kE)
+      if (e_ok_relaxed(L, E, 1 << 20) && E > e) e = E;
+  return e;
 }
 
 // X pass: few elements per thread so that one row fills (up to) a wavefront;
@@ -335,10 +368,16 @@ rl_status check_shape(const int64_t* shape) {
   if (!length_ok(nx / 2) || nx > kMaxNx || !has_e(nx / 2, 64))
     return fail(RL_E_UNSUPPORTED, std::string("nx/2 must be ") + kLens +
                                       ", nx <= 4096, split over at most 64 threads");
-  if (!length_ok(ny) || ny > kMaxNyz || !has_e(ny, 1024))
-    return fail(RL_E_UNSUPPORTED, std::string("ny must be ") + kLens + " and <= 1024");
-  if (!length_ok(nz) || nz > kMaxNyz || !has_e(nz, 1024))
-    return fail(RL_E_UNSUPPORTED, std::string("nz must be ") + kLens + " and <= 1024");
+  auto has_e_yz = [](int64_t L) {
+    for (int E : kE)
+      if (e_ok_yz(L, E, 1024)) return true;
+    return false;
+  };
+  static const char* kLensYz =
+      " must be 2^a 3^b 5^c 7^d <= 4096 with an elements-per-thread count that every odd "
+      "prime divides (at most 8 radix stages)";
+  if (ny > kMaxNyz || !has_e_yz(ny)) return fail(RL_E_UNSUPPORTED, std::string("ny") + kLensYz);
+  if (nz > kMaxNyz || !has_e_yz(nz)) return fail(RL_E_UNSUPPORTED, std::string("nz") + kLensYz);
   return RL_OK;
 }
 
@@ -631,10 +670,13 @@ bool configure_x(rl_plan p, int x_e) {
   if (ax.P > 64 || 64 % ax.P != 0) return false;
   const int rows_per_wave = 64 / ax.P;
   const int rs = (int)(p->M + 1 + ((p->M + 1) >> rlmi::kXPad) + 1);  // padded row
-  // split precision stages 16-byte granules in each wave's rows: keep them aligned
-  if (p->precision != RL_PRECISION_FP32 && (rows_per_wave * rs) % 2 != 0) return false;
+  // split-precision stages (E = 16) stage 16-byte granules in each wave's rows:
+  // keep them aligned; they add the static MFMA operand table to the LDS
+  const bool mfma = p->precision != RL_PRECISION_FP32 && ax.E == 16;
+  if (mfma && (rows_per_wave * rs) % 2 != 0) return false;
+  const size_t fixed = mfma ? rlmi::kSplitTabBytes : 0;
   auto lds_for = [&](int w) {
-    return (size_t)(2 * p->M + (int64_t)w * rows_per_wave * rs) * sizeof(float2);
+    return (size_t)(2 * p->M + (int64_t)w * rows_per_wave * rs) * sizeof(float2) + fixed;
   };
   int waves = rlmi::kXMaxThreads / 64;
   while (waves > 1 && lds_for(waves) > kMaxLds) waves >>= 1;
@@ -642,7 +684,7 @@ bool configure_x(rl_plan p, int x_e) {
   p->axx = ax;
   p->x_rs = rs;
   p->x_rpw = waves * rows_per_wave;
-  p->x_lds = lds_for(waves);
+  p->x_lds = lds_for(waves) - fixed;  // dynamic part
   p->x_block = dim3((unsigned)(64 * waves));
   p->x_grid = dim3((unsigned)((x_rows(p) + p->x_rpw - 1) / p->x_rpw));
   p->ch_x_e = ax.E;
@@ -663,10 +705,18 @@ bool prepare_pencil(rl_plan p, const Pencil& pc) {
   return true;
 }
 
+// The pencil's LDS with the split-precision operand table where it applies.
+bool pencil_fits_plan(rl_plan p, const Pencil& pc) {
+  const size_t extra =
+      (p->precision != RL_PRECISION_FP32 && pc.ax.E == 16) ? rlmi::kSplitTabBytes : 0;
+  return pencil_fits(pc) && pc.lds + extra <= kMaxPencilLds;
+}
+
 bool configure_y(rl_plan p, int y_e, int y_txb) {
   Pencil pc = make_pencil_y(p->ny, p->nz, p->xt, p->ncols, y_txb,
                             y_e > 0 ? y_e : pick_e_y(p->ny), pencil_thread_cap(p));
-  if (!pencil_fits(pc) || (int)pc.block.x > pencil_thread_cap(p) || !prepare_pencil(p, pc))
+  if (!pencil_fits_plan(p, pc) || (int)pc.block.x > pencil_thread_cap(p) ||
+      !prepare_pencil(p, pc))
     return false;
   p->py = pc;
   p->ch_y_e = pc.ax.E;
@@ -676,7 +726,8 @@ bool configure_y(rl_plan p, int y_e, int y_txb) {
 
 bool configure_z(rl_plan p, int z_e, int z_txb, int z_swap) {
   Pencil pc = make_pencil_z(p->nz, p->ny, p->xt, p->ncols, z_txb, z_e, pencil_thread_cap(p));
-  if (!pencil_fits(pc) || (int)pc.block.x > pencil_thread_cap(p) || !prepare_pencil(p, pc))
+  if (!pencil_fits_plan(p, pc) || (int)pc.block.x > pencil_thread_cap(p) ||
+      !prepare_pencil(p, pc))
     return false;
   if (z_swap) {  // outer (y group) index fastest: resident work-groups share tile columns
     if (pc.grid.x > 65535) return false;
@@ -695,8 +746,8 @@ bool configure(rl_plan p, const Choice& c) {
       !configure_z(p, c.z_e, c.z_txb, c.z_swap))
     return false;
   // every transform needs an element count the kernels and the schedule support
-  return e_ok(p->M, p->axx.E, 64) && e_ok(p->ny, p->py.ax.E, 1 << 20) &&
-         e_ok(p->nz, p->pz.ax.E, 1 << 20);
+  return e_ok(p->M, p->axx.E, 64) && e_ok_yz(p->ny, p->py.ax.E, 1 << 20) &&
+         e_ok_yz(p->nz, p->pz.ax.E, 1 << 20);
 }
 
 // --- autotuner ---------------------------------------------------------------
@@ -777,11 +828,12 @@ rl_status time_ms(rl_plan p, F fn, float* ms) {
   return st;
 }
 
-std::vector<int> e_candidates(int64_t L, int64_t max_p, int precision) {
+// pencil: the Y / Z rule (e_ok_yz), else the X rule (e_ok)
+std::vector<int> e_candidates(int64_t L, int64_t max_p, int precision, bool pencil) {
   std::vector<int> out;
   if (precision != RL_PRECISION_FP32 && split_e(L, max_p) == 16) return {16};
   for (int e : {4, 8, 16, 2, 6, 12, 24, 3, 20, 10, 5, 14, 7, 18, 9, 30, 15})
-    if (e_ok(L, e, max_p)) out.push_back(e);
+    if (pencil ? e_ok_yz(L, e, max_p) : e_ok(L, e, max_p)) out.push_back(e);
   return out;
 }
 
@@ -806,7 +858,7 @@ rl_status autotune(rl_plan p, Choice* best) {
   Choice c = *best;
   // X: fused ratio + update
   float bt = 1e30f;
-  for (int xe : e_candidates(p->M, 64, p->precision)) {
+  for (int xe : e_candidates(p->M, 64, RL_PRECISION_FP32, false)) {  // X stays FP32
     if (st != RL_OK) break;
     if (!configure_x(p, xe)) continue;
     float ms = 0.f;
@@ -830,7 +882,7 @@ rl_status autotune(rl_plan p, Choice* best) {
   // Y: forward + inverse
   bt = 1e30f;
   if (p->ny > 1) {
-    for (int ye : e_candidates(p->ny, 1024, p->precision))
+    for (int ye : e_candidates(p->ny, 1024, p->precision, true))
       for (int w : {16, 8}) {
         if (st != RL_OK || !configure_y(p, ye, w) || p->py.args.TXB != w) continue;
         float ms = 0.f;
@@ -848,7 +900,7 @@ rl_status autotune(rl_plan p, Choice* best) {
   }
   // Z: forward * K * inverse
   bt = 1e30f;
-  for (int ze : e_candidates(p->nz, 1024, p->precision))
+  for (int ze : e_candidates(p->nz, 1024, p->precision, true))
     for (int w : {32, 16, 64})
     for (int sw : {0, 1}) {
       if (st != RL_OK || !configure_z(p, ze, w, sw) || p->pz.args.TXB != w) continue;
@@ -880,7 +932,7 @@ rl_status check_options(const int64_t shape[3], const rl_options* opt) {
   if (opt->x_elems != 0 && !e_ok(shape[2] / 2, opt->x_elems, 64))
     return fail(RL_E_INVALID, "x_elems does not fit nx/2");
   if (opt->yz_elems != 0 &&
-      (!e_ok(shape[1], opt->yz_elems, 1024) || !e_ok(shape[0], opt->yz_elems, 1024)))
+      (!e_ok_yz(shape[1], opt->yz_elems, 1024) || !e_ok_yz(shape[0], opt->yz_elems, 1024)))
     return fail(RL_E_INVALID, "yz_elems does not fit ny and nz");
   if (opt->autotune != 0 && opt->autotune != 1) return fail(RL_E_INVALID, "autotune must be 0 or 1");
   if (opt->accel != RL_ACCEL_NONE && opt->accel != RL_ACCEL_BIGGS_ANDREWS)
@@ -956,7 +1008,7 @@ rl_status make_geometry(const int64_t shape[3], const rl_options* opt, int bound
   };
   for (int i = 0; i < 2; ++i)
     g->grid[i] = next_len(g->vol[i] + g->psf[i] / 2,
-                          [&](int64_t L) { return L <= kMaxNyz && has_e(L, 1024); });
+                          [&](int64_t L) { return L <= kMaxNyz && has_e(L, 1024); });  // strict lengths
   const int64_t need_x = g->vol[2] + g->psf[2] / 2;
   const int64_t half = next_len((need_x + 1) / 2 < 2 ? 2 : (need_x + 1) / 2,
                                 [&](int64_t m) { return 2 * m <= kMaxNx && has_e(m, 64); });
@@ -1022,9 +1074,12 @@ rl_status build_class(const Geometry& geo, int count, const float* const* psfs, 
   p->accel = opt ? opt->accel : RL_ACCEL_NONE;
   Choice choice;
   if (p->precision != RL_PRECISION_FP32) {
-    // split precision runs radix-16 stages on MFMA: 16 elements per thread
-    // wherever the length has radix-16 stages (other lengths stay FP32)
-    choice.x_e = split_e(p->M, 64);
+    // split precision runs the radix-16 stages of the Y and Z transforms on MFMA:
+    // 16 elements per thread wherever the length has radix-16 stages (other
+    // lengths stay FP32).  The fused X passes keep their FP32 radix-8/4 schedule
+    // unless x_elems = 16 is requested: with 16 elements per thread they hold the
+    // row, the real operand and the MFMA operands at once, over 200 registers and
+    // one wavefront per SIMD.
     choice.y_e = split_e(ny, 1024);
     choice.z_e = split_e(nz, 1024);
   }
@@ -1261,8 +1316,9 @@ rl_status enqueue_prologue(rl_plan p, const float* u) {
 
 // One RL iteration for every volume of the plan (d/u == nullptr: device tables).
 // The iteration index for the flux partials is `it`, or *iter_ptr if non-null.
+// partials: the flux partial table (nullptr = the plan's own).
 rl_status enqueue_iteration(rl_plan p, const float* d, float* u, int it, const int* iter_ptr,
-                            bool do_fwd) {
+                            bool do_fwd, double* partials = nullptr) {
   rl_status st;
   XArgs r = base_xargs(p, p->spec);
   r.d = d;
@@ -1272,7 +1328,7 @@ rl_status enqueue_iteration(rl_plan p, const float* d, float* u, int it, const i
   XArgs w = base_xargs(p, p->spec);
   w.u = u;
   w.u_tab = u ? nullptr : p->u_tab;
-  w.partials = p->partials;
+  w.partials = partials ? partials : p->partials;
   w.iter = it;
   w.iter_ptr = iter_ptr;
   w.do_fwd = do_fwd ? 1 : 0;
@@ -1282,15 +1338,16 @@ rl_status enqueue_iteration(rl_plan p, const float* d, float* u, int it, const i
 }
 
 // flux[it * count + v] for it < n_iter, on `stream`.
-rl_status enqueue_flux_reduce(rl_plan p, int n_iter, hipStream_t stream) {
+rl_status enqueue_flux_reduce(rl_plan p, int n_iter, hipStream_t stream,
+                              const double* partials = nullptr) {
   hipStream_t keep = p->stream;
   p->stream = stream;
   size_t slot = 0;
   hipEvent_t ev0, ev1;
   rl_status st = timed_begin(p, RL_KERNEL_OTHER, &slot, &ev0, &ev1);
   if (st == RL_OK) {
-    hipError_t e = rlmi::launch_flux_reduce(p->partials, (int)p->x_grid.x, n_iter * p->count,
-                                            p->flux, stream, ev0, ev1);
+    hipError_t e = rlmi::launch_flux_reduce(partials ? partials : p->partials, (int)p->x_grid.x,
+                                            n_iter * p->count, p->flux, stream, ev0, ev1);
     st = (e == hipSuccess) ? RL_OK : hip_fail(e, "flux reduction launch");
   }
   p->stream = keep;
@@ -1361,6 +1418,70 @@ rl_status iterate_impl(rl_plan p, const float* observed, float* estimate, int n_
     if ((st = enqueue_iteration(p, observed, estimate, it, nullptr, it + 1 < n_iter)) != RL_OK)
       return st;
   return enqueue_flux_reduce(p, n_iter, p->stream);
+}
+
+// --- the iteration without allocation ------------------------------------------
+// Device scratch of rl_iterate_noalloc: the FP64 flux partials [iteration][X
+// work-group] live in this fixed array instead of plan memory that may have to
+// grow.  Host code must not pass the array's name to a kernel (it is a host-side
+// stand-in there); it uses the device address looked up once per device.
+constexpr size_t kScratchDoubles = (size_t)1 << 20;  // 8 MiB per device
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (current), looked up on the first call.
+rl_status scratch_on(int device, double** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(RL_E_UNSUPPORTED, "device index too large");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[device] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return RL_OK;
+}
+
+rl_status iterate_noalloc_impl(rl_plan p, const float* observed, float* estimate, int n_iter) {
+  rl_status st = check_plan(p);
+  if (st != RL_OK) return st;
+  if (p->is_batch) return fail(RL_E_INVALID, "batch plans iterate with rl_iterate_batch");
+  if (p->accel != RL_ACCEL_NONE)
+    return fail(RL_E_UNSUPPORTED, "rl_iterate_noalloc runs the plain iteration (no extrapolation)");
+  if (p->timing)
+    return fail(RL_E_UNSUPPORTED, "rl_iterate_noalloc does not run with per-launch timing");
+  if (n_iter < 0) return fail(RL_E_INVALID, "n_iter must be >= 0");
+  const size_t need = (size_t)n_iter * p->x_grid.x;
+  if (need > kScratchDoubles)
+    return fail(RL_E_INVALID, "rl_iterate_noalloc: n_iter * X work-groups = " +
+                                  std::to_string(need) + " exceeds the scratch of " +
+                                  std::to_string(kScratchDoubles) + " values");
+  if (n_iter > p->flux_cap)
+    return fail(RL_E_INVALID, "rl_iterate_noalloc: n_iter exceeds the plan's flux capacity (" +
+                                  std::to_string(p->flux_cap) + ")");
+  const size_t bytes = (size_t)p->vnvox * sizeof(float);
+  int dev = p->device;
+  if ((st = check_dev_ptr(observed, bytes, &dev, "observed")) != RL_OK) return st;
+  if ((st = check_dev_ptr(estimate, bytes, &dev, "estimate")) != RL_OK) return st;
+  if (n_iter == 0) return RL_OK;
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  double* part = nullptr;
+  if ((st = scratch_on(p->device, &part)) != RL_OK) return st;
+  p->flux_count = n_iter;
+  p->stop_call = false;
+  // every [iteration][work-group] slot read by the reduction is written by that
+  // iteration's update pass first, so the scratch needs no clearing
+  if ((st = enqueue_prologue(p, estimate)) != RL_OK) return st;
+  for (int it = 0; it < n_iter; ++it)
+    if ((st = enqueue_iteration(p, observed, estimate, it, nullptr, it + 1 < n_iter, part)) !=
+        RL_OK)
+      return st;
+  return enqueue_flux_reduce(p, n_iter, p->stream, part);
 }
 
 constexpr int kSsimRangeBlocks = 512;
@@ -2013,6 +2134,15 @@ rl_status rl_iterate(rl_plan p, const float* observed, float* estimate, int n_it
   }
 }
 
+rl_status rl_iterate_noalloc(rl_plan p, const float* observed, float* estimate, int n_iter) {
+  ApiRange range("rl_iterate_noalloc");
+  try {
+    return iterate_noalloc_impl(p, observed, estimate, n_iter);
+  } catch (...) {
+    return fail(RL_E_INTERNAL, "unexpected exception in rl_iterate_noalloc");
+  }
+}
+
 rl_status conv3d_fft(rl_plan p, const float* x, float* out) {
   ApiRange range("conv3d_fft");
   try {
@@ -2360,7 +2490,11 @@ rl_status rl_probe_copy(const void* src, void* dst, size_t bytes, void* hip_stre
 }
 
 const char* rl_status_string(rl_status s) {
-  switch (s) {
+  // a caller may pass any int: read the bits, not the enum (whose C++ range is 0..7)
+  static_assert(sizeof(rl_status) == sizeof(int), "rl_status is passed as an int");
+  int v = 0;
+  std::memcpy(&v, &s, sizeof(v));
+  switch (v) {
     case RL_OK: return "RL_OK";
     case RL_E_INVALID: return "RL_E_INVALID";
     case RL_E_UNSUPPORTED: return "RL_E_UNSUPPORTED";

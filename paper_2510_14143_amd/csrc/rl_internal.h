@@ -14,6 +14,9 @@ constexpr int kPencilMaxThreads = 512;
 constexpr int kXMaxThreads = 256;
 // X-pass LDS rows: one spare slot after every 4 elements (radix-4 stages).
 constexpr int kXPad = 2;
+// Static LDS of the split-precision kernels: the MFMA A-operand table (both
+// signs, 64 lanes, four 16-byte operands), beside their dynamic LDS.
+constexpr int kSplitTabBytes = 2 * 64 * 4 * 16;
 
 // Radix schedule of one axis transform of length L, executed in this order.
 // Stage s has radix r[s], input span p[s] (product of earlier radices) and

@@ -265,6 +265,41 @@ struct SplitT<2> {  // FP16 hi/lo with a power-of-two scale per DFT
   }
 };
 
+// A operands of the 16-point DFT per lane: lane l holds row n = l % 16 of the
+// real-output block [Fr, -S Fi] and of the imaginary-output block [S Fi, Fr] over
+// K = 8g .. 8g+7 (g = l / 16), each split into hi and lo.  They depend only on the
+// lane and the sign, so every work-group computes them once into this LDS table,
+// [sign: forward, inverse][lane][re hi, re lo, im hi, im lo] (8 KB), which the
+// host adds to the kernel's LDS budget (kSplitTabBytes).
+template <int PREC>
+__device__ __forceinline__ typename SplitT<PREC>::V8* split_atab() {
+  __shared__ typename SplitT<PREC>::V8 tab[2 * 64 * 4];
+  return tab;
+}
+
+// Every thread of the work-group calls this; a barrier must follow before use.
+template <int PREC>
+__device__ __forceinline__ void split_atab_fill() {
+  typedef SplitT<PREC> ST;
+  typedef typename ST::T T;
+  typename ST::V8* tab = split_atab<PREC>();
+  for (int e = threadIdx.x; e < 2 * 64 * 4; e += blockDim.x) {
+    const int S = (e >> 8) ? 1 : -1;
+    const int l = (e >> 2) & 63, w = e & 3;
+    const int n = l & 15, g = l >> 4;
+    typename ST::V8 v;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int kk = 8 * g + q, k = kk & 15, t = (n * k) & 15;
+      const float c = kCos16[t], sn = kCos16[(t + 12) & 15];
+      const float val = (w < 2) ? (kk < 16 ? c : -S * sn) : (kk < 16 ? S * sn : c);
+      const T hi = (T)val;
+      v[q] = (w & 1) ? (T)(val - (float)hi) : hi;
+    }
+    tab[e] = v;
+  }
+}
+
 // Staging slot (in float4 units) of 16-byte granule G (0..7) of row t: rows of 32
 // floats, granules XOR-swizzled by f(t) = (t ^ t >> 3) & 7, which takes distinct
 // values on every 8 consecutive rows and, within 16 consecutive rows, on the even
@@ -275,7 +310,10 @@ __device__ __forceinline__ int stg_q(int t, int G) { return 8 * t + (G ^ ((t ^ (
 
 // y[0..15] of every thread of the wavefront <- its 16-point DFT (sign S).
 // `stg` is a wave-private, 16-byte aligned LDS area of 64 * 32 floats; all 64
-// lanes must call.
+// lanes must call.  The 16 pencils of column group grp (rows 16 grp .. 16 grp + 15)
+// are transformed and written back before the next group is read: a group's
+// outputs overwrite only its own rows, whose inputs every lane of the wave has
+// read before the MFMAs that consume them, so at most two accumulators are live.
 template <int PREC, int S>
 __device__ __forceinline__ void dft16_mfma(float2 (&y)[16], float* stg) {
   typedef SplitT<PREC> ST;
@@ -283,20 +321,8 @@ __device__ __forceinline__ void dft16_mfma(float2 (&y)[16], float* stg) {
   typedef typename ST::V8 V8;
   const int l = threadIdx.x & 63;
   const int n = l & 15, g = l >> 4;
-  // A operands: row m = n of the re-output and im-output blocks, K = 8g .. 8g+7
-  V8 are_hi, are_lo, aim_hi, aim_lo;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int kk = 8 * g + q, k = kk & 15, t = (n * k) & 15;
-    const float c = kCos16[t], sn = kCos16[(t + 12) & 15];
-    const float ar = kk < 16 ? c : -S * sn;
-    const float ai = kk < 16 ? S * sn : c;
-    const T arh = (T)ar, aih = (T)ai;
-    are_hi[q] = arh;
-    are_lo[q] = (T)(ar - (float)arh);
-    aim_hi[q] = aih;
-    aim_lo[q] = (T)(ai - (float)aih);
-  }
+  const V8* at = split_atab<PREC>() + ((S < 0 ? 0 : 1) * 64 + l) * 4;
+  const V8 are_hi = at[0], are_lo = at[1], aim_hi = at[2], aim_lo = at[3];
   float4* s4 = reinterpret_cast<float4*>(stg);
   // stage the inputs: thread t's (re_0..15, im_0..15) in row t
 #pragma unroll
@@ -305,16 +331,13 @@ __device__ __forceinline__ void dft16_mfma(float2 (&y)[16], float* stg) {
     s4[stg_q(l, 4 + G)] = make_float4(y[4 * G].y, y[4 * G + 1].y, y[4 * G + 2].y, y[4 * G + 3].y);
   }
   wave_sync();
-  f32x4 dr[4], di[4];
-  float inv[4];
 #pragma unroll
   for (int grp = 0; grp < 4; ++grp) {
     const int row = 16 * grp + n;
     // K = 8g .. 8g+7 of pencil `row`: granules 2g and 2g+1
     const float4 lo4 = s4[stg_q(row, 2 * g)], hi4 = s4[stg_q(row, 2 * g + 1)];
     const float x[8] = {lo4.x, lo4.y, lo4.z, lo4.w, hi4.x, hi4.y, hi4.z, hi4.w};
-    float sc = 1.f;
-    inv[grp] = 1.f;
+    float sc = 1.f, inv = 1.f;
     if constexpr (ST::kScale) {
       float mx = 0.f;
 #pragma unroll
@@ -328,7 +351,7 @@ __device__ __forceinline__ void dft16_mfma(float2 (&y)[16], float* stg) {
         // finite for tiny inputs (e.g. the far tail of a PSF), which then round to 0
         const int sh = min(14 - e, 64);
         sc = ldexpf(1.f, sh);
-        inv[grp] = ldexpf(1.f, -sh);
+        inv = ldexpf(1.f, -sh);
       }
     }
     V8 bh, bl;
@@ -339,23 +362,16 @@ __device__ __forceinline__ void dft16_mfma(float2 (&y)[16], float* stg) {
       bh[q] = h;
       bl[q] = (T)(xs - (float)h);
     }
-    f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    const f32x4 z = {0.f, 0.f, 0.f, 0.f};
     f32x4 r = ST::mma(are_hi, bh, z);
     r = ST::mma(are_hi, bl, r);
-    dr[grp] = ST::mma(are_lo, bh, r);
+    r = ST::mma(are_lo, bh, r);
     f32x4 im = ST::mma(aim_hi, bh, z);
     im = ST::mma(aim_hi, bl, im);
-    di[grp] = ST::mma(aim_lo, bh, im);
-  }
-  wave_sync();  // every lane has read its operands
-  // outputs 4g .. 4g+3 of pencil `row`: real parts in granule g, imaginary in 4 + g
-#pragma unroll
-  for (int grp = 0; grp < 4; ++grp) {
-    const int row = 16 * grp + n;
-    const float s = inv[grp];
-    s4[stg_q(row, g)] = make_float4(dr[grp][0] * s, dr[grp][1] * s, dr[grp][2] * s, dr[grp][3] * s);
-    s4[stg_q(row, 4 + g)] =
-        make_float4(di[grp][0] * s, di[grp][1] * s, di[grp][2] * s, di[grp][3] * s);
+    im = ST::mma(aim_lo, bh, im);
+    // outputs 4g .. 4g+3 of pencil `row`: real parts in granule g, imaginary in 4 + g
+    s4[stg_q(row, g)] = make_float4(r[0] * inv, r[1] * inv, r[2] * inv, r[3] * inv);
+    s4[stg_q(row, 4 + g)] = make_float4(im[0] * inv, im[1] * inv, im[2] * inv, im[3] * inv);
   }
   wave_sync();
 #pragma unroll
@@ -479,10 +495,12 @@ __device__ __forceinline__ void fft(float2 (&v)[E], const Sched& sc, int i, int 
 // elements of the tiled layout, so a wavefront access covers TXB consecutive
 // elements of 64/TXB pencil positions (for the Y pass the whole work-group
 // reads one contiguous tile column).
-// 1024-thread work-groups of E = 8 are held to 64 VGPRs (8 waves per SIMD), so
-// that two of them share a CU.
+// 1024-thread work-groups of the forward and inverse passes with E = 8 are held to
+// 64 VGPRs (8 waves per SIMD), so that two of them share a CU; the filtered
+// passes (which hold the transfer function too) are not, since at 64 VGPRs they
+// would spill.
 template <int E, int MODE, int MAXT, int PREC = 0>
-__global__ void __launch_bounds__(MAXT, (MAXT == 1024 && E == 8) ? 8 : 1)
+__global__ void __launch_bounds__(MAXT, (MAXT == 1024 && E == 8 && MODE <= PM_INV) ? 8 : 1)
     k_pencil(float2* __restrict__ data, const float2* __restrict__ otf,
              const float2* __restrict__ twg, PencilArgs a, Sched sc) {
   if (a.stop && *a.stop) return;  // stopped: the whole work-group leaves together
@@ -491,6 +509,7 @@ __global__ void __launch_bounds__(MAXT, (MAXT == 1024 && E == 8) ? 8 : 1)
   // twiddle table (L entries) after the exchange buffer
   float2* tw = lds + (size_t)a.L * a.TXP;
   for (int t = tid; t < a.L; t += blockDim.x) tw[t] = twg[t];
+  if constexpr (PREC > 0) split_atab_fill<PREC>();
   const int lane = tid & (a.TXB - 1);
   const int i = tid / a.TXB;
   const int bx = a.swap ? blockIdx.y : blockIdx.x;  // tile (and split) index
@@ -656,6 +675,7 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
   const int tid = threadIdx.x;
   float2* tw = lds;  // 2M entries: exp(-2 pi i k / (2M))
   for (int t = tid; t < 2 * M; t += blockDim.x) tw[t] = twg[t];
+  if constexpr (PREC > 0) split_atab_fill<PREC>();  // ordered by the barrier below
   const int rpw = 64 / P;                       // rows per wavefront
   const int wave = tid >> 6, lane = tid & 63;
   const int rw = lane / P, i = lane - rw * P;
@@ -1412,12 +1432,13 @@ static hipError_t pencil_one(dim3 g, dim3 b, size_t lds, hipStream_t s, float2* 
                              const float2* otf, const float2* tw, const PencilArgs& a,
                              const Sched& sc, bool launch = true, hipEvent_t ev0 = nullptr,
                              hipEvent_t ev1 = nullptr) {
-  if (lds > 65536) {
+  if (lds > 65536 - (PREC > 0 ? kSplitTabBytes : 0)) {
     static bool attr_done = false;  // once per instantiation
     if (!attr_done) {
       hipError_t e =
           hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pencil<EV, MODE, MAXT, PREC>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              163840 - (PREC > 0 ? kSplitTabBytes : 0));
       if (e != hipSuccess) return e;
       attr_done = true;
     }
@@ -1434,14 +1455,12 @@ static hipError_t pencil_e(int E, int prec, dim3 g, dim3 b, size_t lds, hipStrea
                            hipEvent_t ev1 = nullptr) {
   if (b.x > 1024) return hipErrorInvalidValue;
   if (b.x % 64 != 0) prec = 0;  // MFMA stages need whole wavefronts
-  if (E == 16 && prec == 1) {
-    return b.x > 512 ? pencil_one<MODE, 1024, 16, 1>(g, b, lds, s, data, otf, tw, a, sc, launch, ev0, ev1)
-                     : pencil_one<MODE, 512, 16, 1>(g, b, lds, s, data, otf, tw, a, sc, launch, ev0, ev1);
-  }
-  if (E == 16 && prec == 2) {
-    return b.x > 512 ? pencil_one<MODE, 1024, 16, 2>(g, b, lds, s, data, otf, tw, a, sc, launch, ev0, ev1)
-                     : pencil_one<MODE, 512, 16, 2>(g, b, lds, s, data, otf, tw, a, sc, launch, ev0, ev1);
-  }
+  // split-precision work-groups have at most 512 threads (their register budget)
+  if (E == 16 && prec > 0 && b.x > 512) return hipErrorInvalidValue;
+  if (E == 16 && prec == 1)
+    return pencil_one<MODE, 512, 16, 1>(g, b, lds, s, data, otf, tw, a, sc, launch, ev0, ev1);
+  if (E == 16 && prec == 2)
+    return pencil_one<MODE, 512, 16, 2>(g, b, lds, s, data, otf, tw, a, sc, launch, ev0, ev1);
   if (b.x > 512) {
     switch (E) {
       case 8: return pencil_one<MODE, 1024, 8>(g, b, lds, s, data, otf, tw, a, sc, launch, ev0, ev1);

@@ -75,6 +75,7 @@ def lib() -> ctypes.CDLL:
         "rl_plan_create_ex": ([i64p, vp, ctypes.c_int, ctypes.POINTER(_Options), ctypes.POINTER(vp)],
                               ctypes.c_int),
         "rl_iterate": ([vp, vp, vp, ctypes.c_int], ctypes.c_int),
+        "rl_iterate_noalloc": ([vp, vp, vp, ctypes.c_int], ctypes.c_int),
         "conv3d_fft": ([vp, vp, vp], ctypes.c_int),
         "rl_plan_destroy": ([vp], None),
         "rl_plan_set_stream": ([vp, vp], ctypes.c_int),
@@ -161,6 +162,11 @@ def rl_plan_create_ex(shape, psf_ptr: int, boundary: int = RL_BOUNDARY_PERIODIC,
 def rl_iterate(plan: int, observed_ptr: int, estimate_ptr: int, n_iter: int) -> None:
     _check(lib().rl_iterate(ctypes.c_void_p(plan), ctypes.c_void_p(observed_ptr),
                             ctypes.c_void_p(estimate_ptr), int(n_iter)))
+
+
+def rl_iterate_noalloc(plan: int, observed_ptr: int, estimate_ptr: int, n_iter: int) -> None:
+    _check(lib().rl_iterate_noalloc(ctypes.c_void_p(plan), ctypes.c_void_p(observed_ptr),
+                                    ctypes.c_void_p(estimate_ptr), int(n_iter)))
 
 
 def conv3d_fft(plan: int, x_ptr: int, out_ptr: int) -> None:

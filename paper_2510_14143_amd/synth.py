@@ -17,6 +17,9 @@ Sizes and distributions (Z, Y, X):
   config 1  (128, 256, 256) 400 textured solid nuclei, PSF (2,2,5), peak ~2000
   config 2  (256, 512, 512) 3000 nuclei on a spherical shell, PSF (2.5,2.5,6), + read noise
   batch     96 volumes (s/2, s, s), s in {48, 64, 96, 128, 192}, per-volume PSF
+  paper     (30, 2160, 2560) the shape of the paper's own stack: 8000 textured
+            nuclei (semi-axes x, y in [6, 14], z in [2, 5]), PSF (2, 2, 2.5),
+            peak ~2000 photons on background 50, Poisson noise
 """
 
 from __future__ import annotations
@@ -126,6 +129,53 @@ def _solid_nuclei_volume(rng, shape, sigma_xyz, n_nuclei, background, peak,
     if read_noise > 0:
         d = np.maximum(0.0, d + rng.normal(0.0, read_noise, size=shape))
     return d.astype(np.float32), psf, truth * scale + background
+
+
+PAPER_SHAPE = (30, 2160, 2560)
+PAPER_SIGMA = (2.0, 2.0, 2.5)
+PAPER_SEED = 2160
+
+
+def make_paper_shape(seed: int = PAPER_SEED) -> dict:
+    """A volume of the paper's stack shape (Z, Y, X) = (30, 2160, 2560): a flat,
+    wide field of textured nuclei, PSF of the volume's shape, Poisson noise.  Built
+    in float32 with scipy's multithreaded FFT for the image-formation blur, since
+    the volume has 1.7e8 voxels."""
+    import os
+
+    import scipy.fft as sfft
+
+    rng = np.random.default_rng(seed)
+    shape = PAPER_SHAPE
+    truth = np.zeros(shape, dtype=np.float32)
+    for _ in range(8000):
+        ax, ay = rng.uniform(6.0, 14.0, size=2)
+        az = rng.uniform(2.0, 5.0)
+        a = (az, ay, ax)
+        c = _place(rng, shape, a)
+        _add_solid_nucleus(truth, rng, c, a, rng.uniform(200.0, 1000.0))
+    # the Gaussian PSF is a product of per-axis factors: normalise each in FP64
+    sx, sy, sz = PAPER_SIGMA
+    g = []
+    for n, sg in zip(shape, (sz, sy, sx)):
+        t = (np.arange(n) - n // 2) / sg
+        e = np.exp(-0.5 * t * t)
+        g.append(e / e.sum())
+    gzy = g[0][:, None] * g[1][None, :]
+    psf = np.empty(shape, dtype=np.float32)
+    for z in range(shape[0]):
+        psf[z] = (gzy[z][:, None] * g[2][None, :]).astype(np.float32)
+    w = os.cpu_count() or 1
+    k = np.fft.ifftshift(psf)
+    blur = sfft.irfftn(sfft.rfftn(truth, workers=w) * sfft.rfftn(k, workers=w), s=shape,
+                       workers=w)
+    del k
+    np.maximum(blur, 0.0, out=blur)
+    scale = (2000.0 - 50.0) / max(float(blur.max()), 1e-30)
+    blur *= np.float32(scale)
+    blur += np.float32(50.0)
+    d = rng.poisson(blur).astype(np.float32)
+    return dict(shape=shape, sigma=PAPER_SIGMA, d=d, psf=psf, u0=initial_estimate(d))
 
 
 def initial_estimate(d: np.ndarray) -> np.ndarray:

@@ -39,12 +39,14 @@ def _create(shape, psf_ptr=4096, boundary=0):
     ((8, 8, 2), rl.RL_E_UNSUPPORTED),      # nx < 4
     ((8, 8, 22), rl.RL_E_UNSUPPORTED),     # radix 11
     ((8, 26, 8), rl.RL_E_UNSUPPORTED),     # radix 13
-    ((27, 8, 8), rl.RL_E_UNSUPPORTED),     # three factors of 3
-    ((8, 25, 8), rl.RL_E_UNSUPPORTED),     # two factors of 5
+    ((8, 8, 54), rl.RL_E_UNSUPPORTED),     # nx/2 = 27: the X rule needs the odd part in one thread
+    ((8, 22, 8), rl.RL_E_UNSUPPORTED),     # radix 11 in Y
     ((8, 8, 70), rl.RL_E_UNSUPPORTED),     # nx/2 = 35 = 5 * 7
+    ((8, 105, 8), rl.RL_E_UNSUPPORTED),    # 3 * 5 * 7: no element count holds all three primes
     ((8, 8, 8192), rl.RL_E_UNSUPPORTED),   # above the nx limit
     ((8, 8, 4096), rl.RL_E_UNSUPPORTED),   # nx/2 = 2048 needs 32 elements per thread
-    ((2048, 8, 8), rl.RL_E_UNSUPPORTED),   # above the nz limit
+    ((8192, 8, 8), rl.RL_E_UNSUPPORTED),   # above the nz limit
+    ((8, 8192, 8), rl.RL_E_UNSUPPORTED),   # above the ny limit
 ])
 def test_bad_shapes_rejected(shape, code):
     st, out = _create(shape)

@@ -141,3 +141,41 @@ def test_batch_with_odd_radix_shapes(torch):
     for c, g in zip(cases, got):
         ref, _, _ = oracle.rl(c["d"], c["psf"], c["u0"], 12)
         assert oracle.rel_l2(g, ref) <= 1e-4
+
+
+# Y and Z lengths whose odd part has a repeated prime (27, 25, 45, 135) or which
+# are longer than 1024: their elements-per-thread count carries every odd prime
+# once and the thread count per pencil the rest (2160 = 16 * 135: 30 elements on
+# 72 threads)
+LONG_SHAPES = [(27, 8, 8), (4, 25, 16), (45, 18, 8), (2, 270, 16), (4, 2160, 8), (1080, 2, 8),
+               (2048, 4, 8), (3, 4096, 4)]
+
+
+@pytest.mark.parametrize("shape", LONG_SHAPES)
+def test_conv_repeated_odd_primes_and_long_pencils(torch, shape):
+    say("conv long/odd", shape)
+    x = synth.uniform_volume(shape, 410)
+    psf = rand_psf(shape, 411)
+    with rl.Plan(dev(torch, psf)) as p:
+        cfg = p.launch()
+        got = p.conv(dev(torch, x)).cpu().numpy()
+    err = oracle.rel_l2(got, oracle.conv3d(x, psf))
+    say("  relL2", err, cfg)
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("shape", [(6, 270, 32), (4, 2160, 16)])
+def test_rl_long_pencils(torch, shape):
+    say("rl long", shape)
+    c = synth.small_case(shape, sigma_xyz=(1.5, 2.5, 2.0), seed=72)
+    with rl.Plan(dev(torch, c["psf"]), autotune=True) as p:
+        u = dev(torch, c["u0"])
+        p.iterate(dev(torch, c["d"]), u, 10)
+        got = u.cpu().numpy()
+        flux = p.flux()
+    ref, _, _ = oracle.rl(c["d"], c["psf"], c["u0"], 10)
+    err = oracle.rel_l2(got, ref)
+    say("  relL2", err)
+    assert err <= 1e-4
+    total = float(c["d"].sum(dtype=np.float64))
+    assert np.all(np.abs(flux - total) / total <= 1e-5)

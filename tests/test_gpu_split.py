@@ -58,6 +58,39 @@ def test_split_conv(torch, precision, shape):
 
 
 @pytest.mark.parametrize("precision", SPLITS)
+@pytest.mark.parametrize("shape", [(16, 32, 64), (32, 64, 64), (16, 16, 256)])
+def test_split_conv_mfma_x_passes(torch, precision, shape):
+    # x_elems = 16: the fused X passes run their radix-16 stages on MFMA too
+    say("split conv, MFMA X passes", precision, shape)
+    x = synth.uniform_volume(shape, 202)
+    rng = np.random.default_rng(4)
+    psf = (rng.uniform(0, 1, size=shape) ** 4).astype(np.float32)
+    psf[tuple(s // 3 for s in shape)] += 5.0
+    ref = oracle.conv3d(x, psf)
+    with rl.Plan(dev(torch, psf), precision=precision, x_elems=16) as p:
+        cfg = p.launch()
+        got = p.conv(dev(torch, x)).cpu().numpy()
+    assert cfg["x_elems"] == 16
+    err = oracle.rel_l2(got, ref)
+    say("  relL2", err, cfg)
+    assert err <= CONV_TOL[precision]
+
+
+@pytest.mark.parametrize("precision", SPLITS)
+def test_split_rl_mfma_x_passes(torch, precision):
+    c = synth.make_config(0)
+    say("split rl, MFMA X passes", precision)
+    with rl.Plan(dev(torch, c["psf"]), precision=precision, x_elems=16) as p:
+        u = dev(torch, c["u0"])
+        p.iterate(dev(torch, c["d"]), u, 10)
+        got = u.cpu().numpy()
+    ref = oracle.rl(c["d"], c["psf"], c["u0"], 10)[0]
+    err = oracle.rel_l2(got, ref)
+    say("  relL2", err)
+    assert err <= RL_TOL
+
+
+@pytest.mark.parametrize("precision", SPLITS)
 def test_split_conv_gaussian_psf_tail(torch, precision):
     # a Gaussian PSF over the whole grid has FP32 values far below 2^-100 in its
     # tail: the FP16 per-DFT scale must stay finite there
