@@ -439,7 +439,7 @@ def run_split(torch, rl, synth, steps: int, cfg: int = 2):
     res, ref = {}, {}
     samples = oracle_samples()
     for prec in ("fp32", "split_bf16", "split_fp16"):
-        plan = rl.Plan(psf, precision=prec)
+        plan = rl.Plan(psf, precision=prec, autotune=True)  # each form tuned alike
         u = u0.clone()
         plan.iterate(d, u, 10)
         u10 = u.clone()
@@ -701,7 +701,7 @@ def copy_probe(torch, rl, nbytes: int = 1 << 30, reps: int = 20) -> float:
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(c: dict, n_iter_sample: int = 1):
+def cpu_baseline(c: dict, n_iter_sample: int = 2):
     """The FP64 oracle on the host cores, on a bounded sample of the headline
     workload (its first iteration(s)).  Returns the record and the oracle's estimate
     after the sample's iterations."""
@@ -896,9 +896,9 @@ def main():
         log(json.dumps({"paper_shape": paper}))
     cpu = cpu_ctx = None
     if rank == 0 and not args.no_cpu:
-        log("cpu baseline (oracle, first iteration of the headline volume)")
+        log("cpu baseline (oracle, first iterations of the headline volume)")
         c2 = synth.make_config(2)
-        n_s = 1
+        n_s = 2
         cpu, u_ref = cpu_baseline(c2, n_s)
         u_gpu = gpu_estimate_after(torch, rl, c2, n_s)
         import oracle

@@ -121,7 +121,8 @@ typedef struct {
                      fastest (adds tens of ms; needs 8 bytes per voxel of
                      temporary device memory).  With RLMI_TUNE_CACHE naming a
                      text file, results are read from / appended to it, keyed
-                     by GPU architecture, HIP runtime version and shape; the
+                     by GPU architecture, HIP runtime version, shape and
+                     precision; the
                      last line of a key wins, and a line whose configuration
                      does not fit the shape is ignored (the plan tunes afresh
                      and appends a new line). */

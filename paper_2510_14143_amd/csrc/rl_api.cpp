@@ -765,6 +765,7 @@ std::string tune_key(rl_plan p) {
   (void)hipRuntimeGetVersion(&rt);
   std::ostringstream k;
   k << prop.gcnArchName << "/hip" << rt << "/" << p->nz << "x" << p->ny << "x" << p->nx;
+  if (p->precision != RL_PRECISION_FP32) k << "/split" << p->precision;  // its own choice
   std::string s = k.str();
   for (char& ch : s)
     if (ch == ' ') ch = '_';
@@ -2426,9 +2427,13 @@ rl_status rl_plan_get_pass_kernel(rl_plan p, int kind, char* name, size_t cap, i
   switch (kind) {
     case RL_KERNEL_X_RATIO:
     case RL_KERNEL_X_UPDATE:
-      s = "k_xrow<" + std::to_string(p->axx.E) + ", " +
-          std::to_string(kind == RL_KERNEL_X_RATIO ? (int)rlmi::XM_RATIO : (int)rlmi::XM_UPDATE) +
-          ", " + std::to_string(p->axx.E == 16 ? p->precision : 0) + ">";
+    {
+      const int mode = kind == RL_KERNEL_X_RATIO ? (int)rlmi::XM_RATIO : (int)rlmi::XM_UPDATE;
+      const int prec = p->axx.E == 16 ? p->precision : 0;
+      s = "k_xrow<" + std::to_string(p->axx.E) + ", " + std::to_string(mode) + ", " +
+          std::to_string(prec) + ", " +
+          std::to_string(rlmi::xrow_compiled_len(mode, p->axx.E, (int)p->M, prec)) + ">";
+    }
       n = (int64_t)p->x_grid.x * p->x_block.x;
       break;
     case RL_KERNEL_Y: pencil(p->py, rlmi::PM_FWD, rlmi::PM_INV); break;

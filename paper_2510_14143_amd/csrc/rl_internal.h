@@ -78,6 +78,17 @@ enum XMode {
   XM_UPDATE_PSNR = 8  // XM_UPDATE that also accumulates the MET_PSNR sums
 };
 
+// Row length M the X-pass kernel of (mode, E, M, prec) is compiled for (0 = the
+// runtime schedule): the per-iteration ratio and update passes of power-of-two
+// rows M in {64, 128, 256, 512} with E in {4, 8} elements per thread and at most
+// 64 threads per row.
+constexpr int xrow_compiled_len(int mode, int E, int M, int prec) {
+  return ((mode == XM_RATIO || mode == XM_UPDATE) && (E == 4 || E == 8) && prec == 0 &&
+          (M == 64 || M == 128 || M == 256 || M == 512) && M / E <= 64)
+             ? M
+             : 0;
+}
+
 // Arguments of an X-row pass (contiguous axis, real <-> half spectrum).
 struct XArgs {
   float2* spec;          // half spectrum, x-tile-major layout (see kTile)

@@ -489,6 +489,98 @@ __device__ __forceinline__ void fft(float2 (&v)[E], const Sched& sc, int i, int 
 }
 
 // ---------------------------------------------------------------------------
+// Compile-time schedules (power-of-two lengths of the X rows)
+// ---------------------------------------------------------------------------
+// The stages of fft() with the length, the elements per thread, and every
+// stage's radix, span and twiddle stride known at compile time, for rows that
+// one wavefront holds (LDS stride 1).  The index arithmetic of the runtime
+// schedule (spans, butterfly positions, LDS slots, twiddle indices) then folds
+// into constants and LDS immediate offsets: the fused X passes, whose vector
+// instruction issue bounds them, run about half the instructions.
+struct CtSched {
+  int ns;
+  int r[kMaxStages];
+  int p[kMaxStages];
+};
+
+// The host's radix order for a power-of-two length L: the largest power-of-two
+// radix dividing E, repeated, the remainder by the next smaller ones.
+constexpr CtSched ct_sched(int L, int E) {
+  CtSched s{0, {0, 0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0, 0, 0}};
+  const int big = E % 16 == 0 ? 16 : E % 8 == 0 ? 8 : E % 4 == 0 ? 4 : E % 2 == 0 ? 2 : 1;
+  int n = L, p = 1;
+  while (n > 1 && big > 1 && s.ns < kMaxStages) {
+    int r = big;
+    while (r > 1 && n % r) r /= 2;
+    s.r[s.ns] = r;
+    s.p[s.ns] = p;
+    p *= r;
+    n /= r;
+    ++s.ns;
+  }
+  return s;
+}
+
+template <int E, int R, int S, int PAD, int P, int p, int TM, bool LAST>
+__device__ __forceinline__ void stage_ct(float2 (&v)[E], int i, const float2* __restrict__ tw,
+                                         float2* lds) {
+  constexpr int V = E / R;
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const int b = i + q * P;
+    const int k = LAST ? b : (b & (p - 1));
+    float2 y[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) y[j] = v[q + j * V];
+    if constexpr (p > 1) {
+#pragma unroll
+      for (int j = 1; j < R; ++j) {
+        const float2 w = tw[j * k * TM];
+        y[j] = (S < 0) ? cmul(y[j], w) : cmulc(y[j], w);
+      }
+    }
+    Dft<R, S>::run(y);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) v[q + j * V] = y[j];
+    } else {
+      const int base = (b - k) * R + k;
+#pragma unroll
+      for (int j = 0; j < R; ++j) lds[lslot<PAD>(base + j * p)] = y[j];
+    }
+  }
+}
+
+// Full transform of a wave-held row of length L (twiddle table stride TS);
+// natural order in and out, like fft<E, S, true, PAD>.
+template <int E, int S, int PAD, int L, int TS, int ST = 0>
+__device__ __forceinline__ void fft_ct(float2 (&v)[E], int i, const float2* __restrict__ tw,
+                                       float2* lds) {
+  constexpr CtSched cs = ct_sched(L, E);
+  if constexpr (ST < cs.ns) {
+    constexpr int P = L / E, R = cs.r[ST], p = cs.p[ST];
+    constexpr bool last = ST == cs.ns - 1;
+    stage_ct<E, R, S, PAD, P, p, TS * (L / (p * R)), last>(v, i, tw, lds);
+    if constexpr (!last) {
+      wave_sync();
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = lds[lslot<PAD>(i + P * m)];
+      wave_sync();
+      fft_ct<E, S, PAD, L, TS, ST + 1>(v, i, tw, lds);
+    }
+  }
+}
+
+// X-row transform: the compile-time schedule when CM (the row length) is
+// non-zero, else the runtime one.
+template <int E, int S, int PREC, int CM>
+__device__ __forceinline__ void fft_row(float2 (&v)[E], const Sched& sc, int i, int P,
+                                        const float2* __restrict__ tw, float2* row, float* stg) {
+  if constexpr (CM > 0) fft_ct<E, S, kXPad, CM, 2>(v, i, tw, row);
+  else fft<E, S, true, kXPad, PREC>(v, sc, i, P, tw, row, 1, 0, stg);
+}
+
+// ---------------------------------------------------------------------------
 // Y / Z pencil pass
 // ---------------------------------------------------------------------------
 // Work-group = TXB lanes x P threads; lanes run along contiguous complex
@@ -561,11 +653,11 @@ __device__ __forceinline__ long long col_off(int kx, long long tstride) {
   return (long long)(kx >> 4) * tstride + (kx & (kTile - 1));
 }
 
-template <int E, int PREC>
+template <int E, int PREC, int CM = 0>
 __device__ __forceinline__ void r2c_store(float2 (&v)[E], int M, int P, const Sched& sc, int i,
                                           const float2* tw, float2* row, bool ok,
                                           float2* __restrict__ out, long long ts, float* stg) {
-  fft<E, -1, true, kXPad, PREC>(v, sc, i, P, tw, row, 1, 0, stg);
+  fft_row<E, -1, PREC, CM>(v, sc, i, P, tw, row, stg);
 #pragma unroll
   for (int m = 0; m < E; ++m) row[lslot<kXPad>(i + P * m)] = v[m];
   wave_sync();
@@ -667,11 +759,12 @@ __device__ __forceinline__ void wg_reduce_rows(double (&v)[K], const int (&op)[K
   }
 }
 
-template <int E, int MODE, int PREC = 0>
+// CM > 0: the row length M = CM is known at compile time (compile-time schedule).
+template <int E, int MODE, int PREC = 0, int CM = 0>
 __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const float2* __restrict__ twg) {
   if (a.stop && *a.stop) return;  // stopped: the whole work-group leaves together
   extern __shared__ __attribute__((aligned(16))) float2 lds[];
-  const int M = a.M, P = a.P;
+  const int M = CM > 0 ? CM : a.M, P = CM > 0 ? CM / E : a.P;
   const int tid = threadIdx.x;
   float2* tw = lds;  // 2M entries: exp(-2 pi i k / (2M))
   for (int t = tid; t < 2 * M; t += blockDim.x) tw[t] = twg[t];
@@ -704,7 +797,7 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = load_pair(rin, i + P * m, vx, rv);
     __syncthreads();  // twiddles in LDS
-    r2c_store<E, PREC>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
+    r2c_store<E, PREC, CM>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
   } else if constexpr (MODE == XM_PREDICT) {
     const long long ro = rr * vx;
     const bool hist = a.iter > 0;
@@ -722,7 +815,7 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = predict2(v[m], hv[m], al);
     __syncthreads();  // twiddles in LDS
-    r2c_store<E, PREC>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
+    r2c_store<E, PREC, CM>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
   } else {
     constexpr bool kAcc = MODE == XM_UPDATE_ACC;
     // issue every global load of the row first
@@ -760,7 +853,7 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
     }
     __syncthreads();  // twiddles in LDS
     c2r_prepare<E>(v, nyq, M, P, i, tw, row);
-    fft<E, +1, true, kXPad, PREC>(v, sc, i, P, tw, row, 1, 0, stg);
+    fft_row<E, +1, PREC, CM>(v, sc, i, P, tw, row, stg);
     // v[m] holds (x[2n], x[2n+1]) for n = i + P*m (unnormalised; the 1/N is in the OTF)
     if constexpr (MODE == XM_C2R) {
       float* rout = (a.rout_tab ? a.rout_tab[vol] : a.rout) + rr * a.rout_stride;
@@ -782,7 +875,7 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
         v[m] = make_float2(q.x > 1e-12f ? w[m].x / q.x : 0.f, q.y > 1e-12f ? w[m].y / q.y : 0.f);
       }
       wave_sync();  // row buffer reuse
-      r2c_store<E, PREC>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
+      r2c_store<E, PREC, CM>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
       if constexpr (want_ll) {
         double r[1] = {(double)ll};
         constexpr int ops[1] = {0};
@@ -875,7 +968,7 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
       }
       if (a.do_fwd) {
         wave_sync();
-        r2c_store<E, PREC>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
+        r2c_store<E, PREC, CM>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
       }
       // work-group partial of the flux: wavefront butterfly, then the waves in order
 #pragma unroll
@@ -1510,10 +1603,37 @@ hipError_t launch_pencil(int mode, int E, int prec, dim3 grid, dim3 block, size_
   }
 }
 
+// The per-iteration passes of power-of-two rows with 4 or 8 elements per thread
+// (P = M / E <= 64) run on compile-time schedules.
+template <int MODE, int E>
+static bool xrow_ct(int M, dim3 g, dim3 b, size_t lds, hipStream_t s, const XArgs& a,
+                    const Sched& sc, const float2* tw, hipEvent_t ev0, hipEvent_t ev1) {
+  switch (M) {
+#define RL_CM(MV)                                                                \
+  case MV:                                                                       \
+    if constexpr (MV / E <= 64) {                                                \
+      RL_LAUNCH((k_xrow<E, MODE, 0, MV>), g, b, lds, s, ev0, ev1, a, sc, tw);    \
+      return true;                                                               \
+    }                                                                            \
+    return false;
+    RL_CM(64) RL_CM(128) RL_CM(256) RL_CM(512)
+#undef RL_CM
+    default:
+      return false;
+  }
+}
+
 template <int MODE>
 static hipError_t xrow_e(int E, int prec, dim3 g, dim3 b, size_t lds, hipStream_t s,
                          const XArgs& a, const Sched& sc, const float2* tw, hipEvent_t ev0,
                          hipEvent_t ev1) {
+  if constexpr (MODE == XM_RATIO || MODE == XM_UPDATE) {
+    if (xrow_compiled_len(MODE, E, a.M, E == 16 ? prec : 0) > 0) {  // PREC of the instance
+      const bool ok = E == 4 ? xrow_ct<MODE, 4>(a.M, g, b, lds, s, a, sc, tw, ev0, ev1)
+                             : xrow_ct<MODE, 8>(a.M, g, b, lds, s, a, sc, tw, ev0, ev1);
+      return ok ? hipGetLastError() : hipErrorInvalidValue;
+    }
+  }
   if (E == 16 && prec == 1) {
     RL_LAUNCH((k_xrow<16, MODE, 1>), g, b, lds, s, ev0, ev1, a, sc, tw);
     return hipGetLastError();
