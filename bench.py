@@ -158,7 +158,7 @@ def counter_table(pmc_dir: str, counter: str) -> dict:
 
 
 def rocprof_summary(trace_dir: str, fetch_dir=None, write_dir=None, title: str = "",
-                    commands=()) -> str:
+                    commands=(), src_hash=None) -> str:
     """Markdown summary of one profiled benchmark command: per kernel and thread
     count, launches and durations from the kernel trace, and HBM read / write bytes
     per launch from FETCH_SIZE / WRITE_SIZE (KiB per dispatch), each scaled so that
@@ -176,7 +176,7 @@ def rocprof_summary(trace_dir: str, fetch_dir=None, write_dir=None, title: str =
              "Commands (run from the repository root on one MI355X, ROCm 7.2, after "
              "`cd /tmp && export TMPDIR=/tmp`):", ""]
     lines += [f"    {c}" for c in commands]
-    lines += ["", f"Kernel source sha256[:16]: `{source_hash()}`.", "",
+    lines += ["", f"Kernel source sha256[:16]: `{src_hash or source_hash()}`.", "",
               "Durations from the kernel trace.  Back-to-back launches started less than "
               f"{B2B_GAP_NS / 1000:g} µs after the previous kernel on their queue ended (the "
               "iteration sequence of the timed steps); the others follow an idle gap (launches "
@@ -342,7 +342,8 @@ def run_workload(torch, rl, synth, cfg: int, steps: int, warmup: int, workload: 
 def run_batched(torch, rl, synth, steps: int, warmup: int, count: int = 96, n_iter: int = 50,
                 autotune: bool = True):
     """Batched form: `count` uneven volumes with their own PSFs, one graph launch per
-    iteration, against the same volumes run one plain plan at a time.  With
+    iteration (the per-pass kernels of every shape class), against the same volumes
+    run one plain plan at a time.  With
     `autotune`, the batch plan tunes each shape class once and the plain plans reuse
     those choices through a temporary tuning cache (both sides tuned alike; plan
     creation is outside the timed region)."""
@@ -370,6 +371,7 @@ def run_batched(torch, rl, synth, steps: int, warmup: int, count: int = 96, n_it
             os.remove(os.path.join(cache, "tune.txt"))
         os.rmdir(cache)
     launch = bp.launch()
+    mode = bp.mode()
 
     def step_batched():
         for a, b in zip(u, u0):
@@ -406,7 +408,7 @@ def run_batched(torch, rl, synth, steps: int, warmup: int, count: int = 96, n_it
     return {"workload": f"rl_fp32_batch{count}_uneven_{n_iter}it", "volumes": count,
             "voxels": nvox, "shape_classes": classes,
             "value": round(nvox * n_iter / (out["batched"] * 1e-3) / 1e9, 3),
-            "unit": "Gvoxel-iter/s", "ms_per_step": round(out["batched"], 3),
+            "unit": "Gvoxel-iter/s", "ms_per_step": round(out["batched"], 3), "mode": mode,
             "plain_one_plan_per_volume_ms": round(out["plain"], 3),
             "speedup_vs_plain": round(out["plain"] / out["batched"], 3), "flux_drift": drift,
             "autotuned": autotune, "launch": launch}
@@ -773,9 +775,15 @@ def summarize_main(argv):
     ap.add_argument("--title", default="")
     ap.add_argument("--cmd", action="append", default=[],
                     help="the profiled command(s), recorded in the summary")
+    ap.add_argument("--bench-log", required=True,
+                    help="stderr of the profiled benchmark run: the kernel source hash it "
+                         "ran on is taken from there")
     a = ap.parse_args(argv)
+    m = re.search(r"kernel source sha256\[:16\]: ([0-9a-f]{16})", open(a.bench_log).read())
+    if not m:
+        sys.exit(f"{a.bench_log}: no kernel source hash")
     dirs = a.rocprof_summary + [None] * (3 - len(a.rocprof_summary))
-    text = rocprof_summary(dirs[0], dirs[1], dirs[2], a.title, a.cmd)
+    text = rocprof_summary(dirs[0], dirs[1], dirs[2], a.title, a.cmd, src_hash=m.group(1))
     with open(a.out, "w") as f:
         f.write(text)
     print(f"wrote {a.out}")
@@ -847,6 +855,7 @@ def main():
     from paper_2510_14143_amd import rl, synth as synth_mod
     synth = _CachedInputs(synth_mod)
 
+    log(f"kernel source sha256[:16]: {source_hash()}")
     copy_gbs = copy_probe(torch, rl)
     log(f"copy probe: {copy_gbs:.1f} GB/s (read + write)")
     log("workload: 256x512x512 volume, 50 iterations (headline)")

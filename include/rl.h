@@ -136,7 +136,22 @@ typedef struct {
                      volume's dimension] (else RL_E_INVALID); the PSF is centred
                      at voxel floor(p/2) and zero beyond its extent.  Single-
                      volume plans only. */
+  int batch_mode; /* rl_batch_mode, batch plans only (single-volume plans ignore it) */
 } rl_options;
+
+/* How rl_iterate_batch runs one iteration of all volumes (rl_options.batch_mode). */
+typedef enum {
+  RL_BATCH_AUTO = 0,       /* RL_BATCH_GRAPH (RL_BATCH_PERSISTENT is switched off) */
+  RL_BATCH_PERSISTENT = 1, /* one persistent kernel launch per iteration: work-groups
+                              of 128 threads take the tiles of every pass of every
+                              volume from per-XCD work queues in pass-major order and
+                              wait on per-(volume, pass) completion counters; each
+                              volume's tiles run on one XCD.  Switched off in this
+                              library: its completion waits did not finish on MI355X,
+                              and plan creation returns RL_E_UNSUPPORTED */
+  RL_BATCH_GRAPH = 2       /* per-pass kernels of each shape class, one hipGraph branch
+                              per class */
+} rl_batch_mode;
 
 /*
  * Create a plan for volumes of shape {nz, ny, nx} blurred by `psf`
@@ -365,8 +380,10 @@ rl_status rl_plan_get_grid(rl_plan p, int64_t grid[3]);
 /* Launch configuration in use: out = {X elements per thread, Y elements per
  * thread, Y work-group lanes, Z elements per thread, Z work-group lanes,
  * 1 if chosen by the autotuner else 0, 1 if the Z grid runs row groups
- * fastest else 0}. */
-rl_status rl_plan_get_launch(rl_plan p, int out[7]);
+ * fastest else 0, 1 if a batch plan runs the persistent kernel else 0 (always 0
+ * while that kernel is switched off)}
+ * (batch plans: the first volume's shape class). */
+rl_status rl_plan_get_launch(rl_plan p, int out[8]);
 
 /*
  * Per-kernel timing with HIP events (measurement support).  When enabled,

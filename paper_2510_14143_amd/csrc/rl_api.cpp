@@ -334,6 +334,20 @@ struct rl_plan_s {
   hipStream_t cap_stream = nullptr;  // private stream the iteration graphs are captured on
   hipGraphExec_t graph_full = nullptr, graph_last = nullptr;
   int batch_n = 0;                // iterations of the last rl_iterate_batch call
+  // persistent batched iteration (batch container): one k_persist launch per
+  // iteration; [0] = every pass, [1] = the last iteration (no forward chain)
+  bool persist = false;
+  bool persist_shapes = false;    // class plan: launch shapes of the persistent kernel's work-groups
+  rlmi::PersistClass* p_cls = nullptr;
+  std::vector<rlmi::PersistClass> p_host;  // host copy of p_cls
+  std::vector<int> p_qtotal[2];            // tickets per queue and launch
+  rlmi::PersistSeg* p_segs[2] = {nullptr, nullptr};
+  int* p_qseg[2] = {nullptr, nullptr};
+  int p_nq = 0, p_grid = 0, p_nvrow = 0, p_cap = 0;
+  size_t p_lds = 0;
+  int* p_tickets = nullptr;       // [iteration][queue]
+  int* p_done = nullptr;          // [iteration][volume][pass]
+  int* p_error = nullptr;
   // applied launch choice (elements per thread and work-group widths)
   int ch_x_e = 0, ch_y_e = 0, ch_y_txb = 0, ch_z_e = 0, ch_z_txb = 0, ch_z_swap = 0;
   bool tuned = false;
@@ -452,6 +466,14 @@ void release(rl_plan p) {
   (void)hipFree(p->fsc_a);
   (void)hipFree(p->fsc_b);
   if (p->fsc_sub) release(p->fsc_sub);
+  (void)hipFree(p->p_cls);
+  for (int k = 0; k < 2; ++k) {
+    (void)hipFree(p->p_segs[k]);
+    (void)hipFree(p->p_qseg[k]);
+  }
+  (void)hipFree(p->p_tickets);
+  (void)hipFree(p->p_done);
+  (void)hipFree(p->p_error);
   for (rl_plan c : p->classes) release(c);
   if (p->graph_full) (void)hipGraphExecDestroy(p->graph_full);
   if (p->graph_last) (void)hipGraphExecDestroy(p->graph_last);
@@ -678,7 +700,8 @@ bool configure_x(rl_plan p, int x_e) {
   auto lds_for = [&](int w) {
     return (size_t)(2 * p->M + (int64_t)w * rows_per_wave * rs) * sizeof(float2) + fixed;
   };
-  int waves = rlmi::kXMaxThreads / 64;
+  // persistent batch classes: work-groups of the persistent kernel's size
+  int waves = p->persist_shapes ? rlmi::kPersistThreads / 64 : rlmi::kXMaxThreads / 64;
   while (waves > 1 && lds_for(waves) > kMaxLds) waves >>= 1;
   if (lds_for(waves) > kMaxLds) return false;
   p->axx = ax;
@@ -750,6 +773,79 @@ bool configure(rl_plan p, const Choice& c) {
          e_ok_yz(p->nz, p->pz.ax.E, 1 << 20);
 }
 
+// --- launch shapes of the persistent batched kernel ----------------------------
+// Every pass of a class must split into work-groups of exactly kPersistThreads
+// threads with element counts the kernel is built for: X rows of 2 waves, Y and Z
+// pencils of lanes x threads-per-pencil = kPersistThreads.  persist_choice finds such a
+// choice for a shape (default-first candidate order); false if there is none.
+constexpr int kPersistXWaves = rlmi::kPersistThreads / 64;
+
+bool persist_x_ok(int64_t M, int E) {
+  if (!rlmi::persist_x_e(E) || !e_ok(M, E, 64)) return false;
+  const int64_t P = M / E;
+  const int64_t rs = M + 1 + ((M + 1) >> rlmi::kXPad) + 1;
+  return (size_t)(2 * M + kPersistXWaves * (64 / P) * rs) * sizeof(float2) <= kMaxLds;
+}
+
+bool persist_y_ok(int64_t ny, int E, int txb) {
+  const int64_t P = rlmi::kPersistThreads / txb;
+  return txb <= rlmi::kTile && ny % P == 0 && ny / P == E && rlmi::persist_yz_e(E) &&
+         e_ok_yz(ny, E, 1024) && (size_t)ny * (txb + 1) * sizeof(float2) <= kMaxPencilLds;
+}
+
+bool persist_z_ok(int64_t nz, int64_t ny, int E, int txb) {
+  const int64_t P = rlmi::kPersistThreads / txb;
+  if (txb >= rlmi::kTile && ny % (txb / rlmi::kTile) != 0) return false;
+  return nz % P == 0 && nz / P == E && rlmi::persist_yz_e(E) && e_ok_yz(nz, E, 1024) &&
+         (size_t)nz * (txb + 1) * sizeof(float2) <= kMaxPencilLds;
+}
+
+constexpr int kPersistYLanes[] = {16, 8, 4};
+constexpr int kPersistZLanes[] = {32, 16, 64, 8};
+
+bool persist_choice(int64_t nz, int64_t ny, int64_t nx, Choice* c) {
+  const int64_t M = nx / 2;
+  int xe = 0;
+  for (int e : {pick_e_x(M), 4, 8, 2, 6})
+    if (persist_x_ok(M, e)) {
+      xe = e;
+      break;
+    }
+  int ye = 0, yt = 0, ze = 0, zt = 0;
+  for (int t : kPersistYLanes) {
+    const int64_t P = rlmi::kPersistThreads / t;
+    if (ny % P == 0 && persist_y_ok(ny, (int)(ny / P), t)) {
+      ye = (int)(ny / P);
+      yt = t;
+      break;
+    }
+  }
+  for (int t : kPersistZLanes) {
+    const int64_t P = rlmi::kPersistThreads / t;
+    if (nz % P == 0 && persist_z_ok(nz, ny, (int)(nz / P), t)) {
+      ze = (int)(nz / P);
+      zt = t;
+      break;
+    }
+  }
+  if (!xe || !ye || !ze) return false;
+  c->x_e = xe;
+  c->y_e = ye;
+  c->y_txb = yt;
+  c->z_e = ze;
+  c->z_txb = zt;
+  c->z_swap = 0;
+  return true;
+}
+
+// The configured shapes of a class plan run in the persistent kernel.
+bool persist_fits(rl_plan c) {
+  return c->precision == RL_PRECISION_FP32 && c->x_block.x == (unsigned)rlmi::kPersistThreads &&
+         rlmi::persist_x_e(c->axx.E) && c->py.block.x == (unsigned)rlmi::kPersistThreads &&
+         rlmi::persist_yz_e(c->py.ax.E) && c->pz.block.x == (unsigned)rlmi::kPersistThreads &&
+         rlmi::persist_yz_e(c->pz.ax.E);
+}
+
 // --- autotuner ---------------------------------------------------------------
 // Times candidate elements-per-thread and lane widths for each pass on the
 // plan's own buffers (HIP events, median of a few launches) and keeps the
@@ -766,6 +862,7 @@ std::string tune_key(rl_plan p) {
   std::ostringstream k;
   k << prop.gcnArchName << "/hip" << rt << "/" << p->nz << "x" << p->ny << "x" << p->nx;
   if (p->precision != RL_PRECISION_FP32) k << "/split" << p->precision;  // its own choice
+  if (p->persist_shapes) k << "/persist";
   std::string s = k.str();
   for (char& ch : s)
     if (ch == ' ') ch = '_';
@@ -861,6 +958,7 @@ rl_status autotune(rl_plan p, Choice* best) {
   float bt = 1e30f;
   for (int xe : e_candidates(p->M, 64, RL_PRECISION_FP32, false)) {  // X stays FP32
     if (st != RL_OK) break;
+    if (p->persist_shapes && !persist_x_ok(p->M, xe)) continue;
     if (!configure_x(p, xe)) continue;
     float ms = 0.f;
     st = time_ms(p, [&]() {
@@ -884,7 +982,8 @@ rl_status autotune(rl_plan p, Choice* best) {
   bt = 1e30f;
   if (p->ny > 1) {
     for (int ye : e_candidates(p->ny, 1024, p->precision, true))
-      for (int w : {16, 8}) {
+      for (int w : {16, 8, 4}) {
+        if (p->persist_shapes ? !persist_y_ok(p->ny, ye, w) : w == 4) continue;
         if (st != RL_OK || !configure_y(p, ye, w) || p->py.args.TXB != w) continue;
         float ms = 0.f;
         st = time_ms(p, [&]() {
@@ -902,8 +1001,9 @@ rl_status autotune(rl_plan p, Choice* best) {
   // Z: forward * K * inverse
   bt = 1e30f;
   for (int ze : e_candidates(p->nz, 1024, p->precision, true))
-    for (int w : {32, 16, 64})
+    for (int w : {32, 16, 64, 8})
     for (int sw : {0, 1}) {
+      if (p->persist_shapes ? (sw || !persist_z_ok(p->nz, p->ny, ze, w)) : w == 8) continue;
       if (st != RL_OK || !configure_z(p, ze, w, sw) || p->pz.args.TXB != w) continue;
       float ms = 0.f;
       st = time_ms(p, [&]() {
@@ -1042,7 +1142,8 @@ rl_status check_device_present() {
 // a transform-only plan (no transfer function; used for the half-size transforms
 // of the single-image FSC).  Synchronous.
 rl_status build_class(const Geometry& geo, int count, const float* const* psfs, int device,
-                      const rl_options* opt, hipStream_t stream, rl_plan* out) {
+                      const rl_options* opt, hipStream_t stream, rl_plan* out,
+                      bool persist_shapes = false) {
   rl_status st;
   hipError_t e;
   const int64_t nz = geo.grid[0], ny = geo.grid[1], nx = geo.grid[2];
@@ -1090,6 +1191,13 @@ rl_status build_class(const Geometry& geo, int count, const float* const* psfs, 
     if (opt->yz_elems) choice.y_e = choice.z_e = opt->yz_elems;
     choice.y_txb = tx > rlmi::kTile ? rlmi::kTile : tx;
     choice.z_txb = tx;
+  }
+  if (persist_shapes) {  // launch shapes the persistent batched kernel runs
+    p->persist_shapes = true;
+    if (!persist_choice(nz, ny, nx, &choice)) {
+      delete p;
+      return fail(RL_E_UNSUPPORTED, "shape has no launch shapes for the persistent kernel");
+    }
   }
   const bool want_tune = opt && opt->autotune;
   if (!configure(p, choice)) {
@@ -1204,7 +1312,8 @@ rl_status build_class(const Geometry& geo, int count, const float* const* psfs, 
     const std::string key = tune_key(p);
     Choice tuned = choice;
     bool cached = cache_lookup(key, &tuned);
-    if (cached && !configure(p, tuned)) {  // a stale or edited line: tune afresh
+    if (cached && (!configure(p, tuned) || (p->persist_shapes && !persist_fits(p)))) {
+      // a stale or edited line: tune afresh
       cached = false;
       tuned = choice;
     }
@@ -1214,7 +1323,7 @@ rl_status build_class(const Geometry& geo, int count, const float* const* psfs, 
         return st;
       }
       cache_store(key, tuned);
-      if (!configure(p, tuned)) {
+      if (!configure(p, tuned) || (p->persist_shapes && !persist_fits(p))) {
         release(p);
         return fail(RL_E_INTERNAL, "tuned configuration does not apply");
       }
@@ -1833,6 +1942,159 @@ rl_status fsc_impl(rl_plan p, const float* a, const float* b, int nbins, double 
 
 // --- batched volumes -----------------------------------------------------------
 
+// Tables of the persistent batched kernel: one PersistClass per shape class, and
+// per XCD queue the pass-major run of tiles of its volumes (volumes assigned to
+// queues by decreasing voxel count, each to the least loaded queue).
+// The persistent batched kernel is switched off: with it, a batch of small volumes
+// did not finish within two minutes.  Its completion polls had been compiled into
+// plain device-scope loads (the compiler folds an atomic add of zero into a load);
+// they now poll with a compare-and-swap that never changes the counter, which has
+// not yet run on the GPU.  Plans refuse RL_BATCH_PERSISTENT until it has.
+constexpr bool kPersistentBatchEnabled = false;
+
+rl_status setup_persist(rl_plan b) {
+  for (rl_plan c : b->classes)
+    if (!persist_fits(c))
+      return fail(RL_E_INTERNAL, "a shape class is not configured for the persistent kernel");
+  hipDeviceProp_t prop;
+  std::memset(&prop, 0, sizeof(prop));
+  hipError_t e = hipGetDeviceProperties(&prop, b->device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  // gfx950: 32 compute units per XCD
+  const int nq = std::max(1, std::min(rlmi::kPersistMaxQueues, prop.multiProcessorCount / 32));
+  std::vector<rlmi::PersistClass> pcs(b->classes.size());
+  size_t lds = 0;
+  for (size_t ci = 0; ci < b->classes.size(); ++ci) {
+    rl_plan c = b->classes[ci];
+    rlmi::PersistClass& pc = pcs[ci];
+    std::memset(&pc, 0, sizeof(pc));
+    pc.xr = base_xargs(c, c->spec);
+    pc.xr.d_tab = c->d_tab;
+    pc.xu = base_xargs(c, c->spec);
+    pc.xu.u_tab = c->u_tab;
+    pc.xu.partials = c->partials;
+    pc.xu.iter_ptr = b->iter_dev;
+    pc.xu.do_fwd = 1;
+    pc.py = c->py.args;
+    pc.pz = c->pz.args;
+    pc.py.vstride = pc.pz.vstride = (long long)c->spec_elems;
+    pc.py.stop = pc.pz.stop = nullptr;
+    pc.sx = c->axx.sc;
+    pc.sy = c->py.ax.sc;
+    pc.sz = c->pz.ax.sc;
+    pc.twx = c->tw_x;
+    pc.twy = c->tw_y;
+    pc.twz = c->tw_z;
+    pc.spec = c->spec;
+    pc.otf = c->otf;
+    pc.ex = c->axx.E;
+    pc.ey = c->py.ax.E;
+    pc.ez = c->pz.ax.E;
+    pc.xtiles = (int)c->x_grid.x;
+    pc.ygx = (int)c->py.grid.x;
+    pc.ytiles = (int)(c->py.grid.x * c->py.grid.y);
+    pc.zgx = (int)c->pz.grid.x;
+    pc.ztiles = (int)(c->pz.grid.x * c->pz.grid.y);
+    lds = std::max({lds, c->x_lds, c->py.lds, c->pz.lds});
+  }
+  // volumes to queues: decreasing voxel count, least loaded queue first
+  std::vector<int> order(b->count);
+  for (int v = 0; v < b->count; ++v) order[v] = v;
+  auto vox = [&](int v) { return b->classes[b->vol_class[v]]->nvox; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return vox(a) > vox(c); });
+  std::vector<std::vector<int>> qv(nq);
+  std::vector<int64_t> load(nq, 0);
+  for (int v : order) {
+    const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    qv[q].push_back(v);
+    load[q] += vox(v);
+  }
+  hipError_t e2;
+  for (int k = 0; k < 2; ++k) {
+    const int npass = k == 0 ? rlmi::kPersistPasses : 5;
+    std::vector<rlmi::PersistSeg> segs;
+    std::vector<int> qseg(nq + 1, 0);
+    for (int q = 0; q < nq; ++q) {
+      qseg[q] = (int)segs.size();
+      int first = 0;
+      for (int pass = 0; pass < npass; ++pass)
+        for (int v : qv[q]) {
+          const int ci = b->vol_class[v];
+          const rlmi::PersistClass& pc = pcs[ci];
+          const int kind = pass & 3;
+          const int tiles = kind == 0 ? pc.xtiles : kind == 2 ? pc.ztiles : pc.ytiles;
+          segs.push_back(rlmi::PersistSeg{pass, ci, b->vol_index[v], v, tiles, first});
+          first += tiles;
+        }
+    }
+    qseg[nq] = (int)segs.size();
+    b->p_qtotal[k].assign(nq, 0);
+    for (int q = 0; q < nq; ++q)
+      if (qseg[q + 1] > qseg[q])
+        b->p_qtotal[k][q] = segs[qseg[q + 1] - 1].first + segs[qseg[q + 1] - 1].tiles;
+    if ((e2 = hipMalloc(&b->p_segs[k], segs.size() * sizeof(rlmi::PersistSeg))) != hipSuccess ||
+        (e2 = hipMalloc(&b->p_qseg[k], qseg.size() * sizeof(int))) != hipSuccess ||
+        (e2 = hipMemcpy(b->p_segs[k], segs.data(), segs.size() * sizeof(rlmi::PersistSeg),
+                        hipMemcpyHostToDevice)) != hipSuccess ||
+        (e2 = hipMemcpy(b->p_qseg[k], qseg.data(), qseg.size() * sizeof(int),
+                        hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e2, "persistent kernel tables");
+  }
+  if ((e2 = hipMalloc(&b->p_cls, pcs.size() * sizeof(rlmi::PersistClass))) != hipSuccess ||
+      (e2 = hipMemcpy(b->p_cls, pcs.data(), pcs.size() * sizeof(rlmi::PersistClass),
+                      hipMemcpyHostToDevice)) != hipSuccess ||
+      (e2 = hipMalloc(&b->p_error, rlmi::kPersistMaxQueues * sizeof(int))) != hipSuccess)
+    return hip_fail(e2, "persistent kernel tables");
+  int per_cu = 0;
+  if ((e2 = rlmi::persist_occupancy(lds, &per_cu)) != hipSuccess || per_cu < 1)
+    return hip_fail(e2 != hipSuccess ? e2 : hipErrorInvalidConfiguration,
+                    "persistent kernel occupancy");
+  b->p_host = pcs;
+  b->p_nq = nq;
+  b->p_lds = lds;
+  b->p_grid = per_cu * prop.multiProcessorCount;
+  b->p_nvrow = b->count;
+  b->persist = true;
+  return RL_OK;
+}
+
+// Per-iteration tickets and completion counters for n_iter iterations.
+rl_status ensure_persist_capacity(rl_plan b, int n_iter, bool* grew) {
+  *grew = false;
+  if (n_iter <= b->p_cap) return RL_OK;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  else (void)hipDeviceSynchronize();
+  (void)hipFree(b->p_tickets);
+  (void)hipFree(b->p_done);
+  b->p_tickets = b->p_done = nullptr;
+  b->p_cap = 0;
+  hipError_t e;
+  if ((e = hipMalloc(&b->p_tickets, (size_t)n_iter * b->p_nq * sizeof(int))) != hipSuccess ||
+      (e = hipMalloc(&b->p_done, (size_t)n_iter * b->p_nvrow * rlmi::kPersistPasses *
+                                     sizeof(int))) != hipSuccess)
+    return hip_fail(e, "hipMalloc(persistent counters)");
+  b->p_cap = n_iter;
+  *grew = true;
+  return RL_OK;
+}
+
+rlmi::PersistArgs persist_args(rl_plan b, int k) {
+  rlmi::PersistArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.cls = b->p_cls;
+  a.segs = b->p_segs[k];
+  a.qseg = b->p_qseg[k];
+  a.nq = b->p_nq;
+  a.npass = k == 0 ? rlmi::kPersistPasses : 5;
+  a.nvrow = b->p_nvrow;
+  a.iter_ptr = b->iter_dev;
+  a.tickets = b->p_tickets;
+  a.done = b->p_done;
+  a.error = b->p_error;
+  a.spin_limit = 1 << 16;  // a small fraction of a second of polling
+  return a;
+}
+
 rl_status create_batch_impl(int count, const int64_t* shapes, const float* const* psfs,
                             int boundary, const rl_options* opt, rl_plan* out) {
   if (!out) return fail(RL_E_INVALID, "out is NULL");
@@ -1858,6 +2120,23 @@ rl_status create_batch_impl(int count, const int64_t* shapes, const float* const
     return fail(RL_E_UNSUPPORTED, "batch plans take PSFs of their volumes' shapes");
   if (opt && opt->tile_x != 0)
     return fail(RL_E_INVALID, "batch plans choose work-group widths per shape (tile_x must be 0)");
+  const int mode = opt ? opt->batch_mode : RL_BATCH_AUTO;
+  if (mode != RL_BATCH_AUTO && mode != RL_BATCH_PERSISTENT && mode != RL_BATCH_GRAPH)
+    return fail(RL_E_INVALID, "unknown batch_mode");
+  if (mode == RL_BATCH_PERSISTENT && !kPersistentBatchEnabled)
+    return fail(RL_E_UNSUPPORTED, "the persistent batched kernel is switched off: its completion "
+                                  "waits did not finish on the GPU (batch_mode AUTO or GRAPH "
+                                  "runs the per-pass graph)");
+  // the persistent kernel needs 128-thread launch shapes for every shape class
+  bool all_fit = kPersistentBatchEnabled && (!opt || opt->precision == RL_PRECISION_FP32);
+  for (int v = 0; v < count && all_fit; ++v) {
+    Choice c;
+    all_fit = persist_choice(shapes[3 * v], shapes[3 * v + 1], shapes[3 * v + 2], &c);
+  }
+  if (mode == RL_BATCH_PERSISTENT && !all_fit)
+    return fail(RL_E_UNSUPPORTED, "a volume shape has no launch shapes for the persistent kernel "
+                                  "(every pass must split into 128-thread work-groups, FP32)");
+  const bool use_persist = all_fit && mode != RL_BATCH_GRAPH;
   if ((st = check_device_present()) != RL_OK) return st;
   int device = -1;
   for (int v = 0; v < count; ++v) {
@@ -1917,7 +2196,8 @@ rl_status create_batch_impl(int count, const int64_t* shapes, const float* const
     Geometry geo;
     geo.boundary = RL_BOUNDARY_PERIODIC;
     for (int i = 0; i < 3; ++i) geo.grid[i] = geo.vol[i] = geo.psf[i] = sh[i];
-    if ((st = build_class(geo, (int)members.size(), cpsf.data(), device, opt, cs, &c)) != RL_OK) {
+    if ((st = build_class(geo, (int)members.size(), cpsf.data(), device, opt, cs, &c,
+                          use_persist)) != RL_OK) {
       const std::string msg = g_err;
       release(b);
       return fail(st, msg);
@@ -1928,6 +2208,11 @@ rl_status create_batch_impl(int count, const int64_t* shapes, const float* const
       b->vol_class[members[k]] = ci;
       b->vol_index[members[k]] = (int)k;
     }
+  }
+  if (use_persist && (st = setup_persist(b)) != RL_OK) {
+    const std::string msg = g_err;
+    release(b);
+    return fail(st, msg);
   }
   plan_register(b);
   *out = b;
@@ -1974,6 +2259,25 @@ rl_status capture_graph(rl_plan b, bool do_fwd, hipGraphExec_t* exec) {
   return e == hipSuccess ? RL_OK : hip_fail(e, "hipGraphInstantiate");
 }
 
+// One persistent launch (k = 0: every pass, 1: the last iteration) and the
+// iteration counter's advance, captured on the plan's private stream.
+rl_status capture_persist_graph(rl_plan b, int k, hipGraphExec_t* exec) {
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  hipError_t le = rlmi::launch_persist(persist_args(b, k), b->p_grid, b->p_lds, b->cap_stream);
+  if (le == hipSuccess) le = rlmi::launch_advance(b->iter_dev, b->cap_stream);
+  e = hipStreamEndCapture(b->cap_stream, &g);
+  if (le != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(le, "persistent kernel launch");
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return e == hipSuccess ? RL_OK : hip_fail(e, "hipGraphInstantiate");
+}
+
 rl_status iterate_batch_impl(rl_plan b, const float* const* observed, float* const* estimate,
                              int n_iter) {
   rl_status st = check_plan(b);
@@ -1999,13 +2303,31 @@ rl_status iterate_batch_impl(rl_plan b, const float* const* observed, float* con
     rebuild = rebuild || grew;
     c->flux_count = n_iter;
   }
+  if (b->persist) {
+    bool grew = false;
+    if ((st = ensure_persist_capacity(b, n_iter, &grew)) != RL_OK) return st;
+    rebuild = rebuild || grew;
+  }
+  if (rebuild && b->persist) {  // the classes' flux partial tables may have moved
+    for (size_t ci = 0; ci < b->classes.size(); ++ci)
+      b->p_host[ci].xu.partials = b->classes[ci]->partials;
+    if ((e = hipMemcpy(b->p_cls, b->p_host.data(),
+                       b->p_host.size() * sizeof(rlmi::PersistClass), hipMemcpyHostToDevice)) !=
+        hipSuccess)
+      return hip_fail(e, "persistent kernel tables");
+  }
   if (rebuild) {  // partial tables moved: captured kernel arguments are stale
     if (b->graph_full) (void)hipGraphExecDestroy(b->graph_full);
     if (b->graph_last) (void)hipGraphExecDestroy(b->graph_last);
     b->graph_full = b->graph_last = nullptr;
   }
-  if (!b->graph_full && (st = capture_graph(b, true, &b->graph_full)) != RL_OK) return st;
-  if (!b->graph_last && (st = capture_graph(b, false, &b->graph_last)) != RL_OK) return st;
+  if (b->persist) {
+    if (!b->graph_full && (st = capture_persist_graph(b, 0, &b->graph_full)) != RL_OK) return st;
+    if (!b->graph_last && (st = capture_persist_graph(b, 1, &b->graph_last)) != RL_OK) return st;
+  } else {
+    if (!b->graph_full && (st = capture_graph(b, true, &b->graph_full)) != RL_OK) return st;
+    if (!b->graph_last && (st = capture_graph(b, false, &b->graph_last)) != RL_OK) return st;
+  }
   // per-volume pointer tables (ordered after earlier work on b->stream)
   for (size_t ci = 0; ci < b->classes.size(); ++ci) {
     rl_plan c = b->classes[ci];
@@ -2024,6 +2346,15 @@ rl_status iterate_batch_impl(rl_plan b, const float* const* observed, float* con
   }
   if ((e = rlmi::launch_set_counter(b->iter_dev, 0, b->stream)) != hipSuccess)
     return hip_fail(e, "iteration counter launch");
+  if (b->persist &&
+      ((e = rlmi::launch_zero_ints(b->p_tickets, (long long)n_iter * b->p_nq, b->stream)) !=
+           hipSuccess ||
+       (e = rlmi::launch_zero_ints(b->p_done,
+                                   (long long)n_iter * b->p_nvrow * rlmi::kPersistPasses,
+                                   b->stream)) != hipSuccess ||
+       (e = rlmi::launch_zero_ints(b->p_error, rlmi::kPersistMaxQueues, b->stream)) !=
+           hipSuccess))
+    return hip_fail(e, "persistent counters");
   // prologue per class, forked from and joined back into b->stream
   if ((e = hipEventRecord(b->fork_event, b->stream)) != hipSuccess)
     return hip_fail(e, "hipEventRecord");
@@ -2189,6 +2520,28 @@ rl_status rl_plan_get_flux(rl_plan p, double* flux, int cap, int* n_written) {
                                 hipMemcpyDeviceToHost)) != hipSuccess)
       return hip_fail(e, "hipMemcpy(flux)");
   } else {
+    if (p->persist) {
+      int errs[rlmi::kPersistMaxQueues] = {};
+      if ((e = hipMemcpy(errs, p->p_error, sizeof(errs), hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy(persistent kernel state)");
+      int err = 0;
+      for (int q = 0; q < rlmi::kPersistMaxQueues; ++q) err |= errs[q];
+      if (err)
+        return fail(RL_E_INTERNAL, "persistent kernel: a wait for a completion counter ran "
+                                   "past its bound; the estimates of that call are not valid");
+      // every queue handed out all of its tiles in every launch (a queue whose XCD
+      // ran no work-group would leave its volumes untouched)
+      const int n = p->batch_n;
+      std::vector<int> tk((size_t)n * p->p_nq);
+      if (n > 0 && (e = hipMemcpy(tk.data(), p->p_tickets, tk.size() * sizeof(int),
+                                  hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy(persistent kernel state)");
+      for (int it = 0; it < n; ++it)
+        for (int q = 0; q < p->p_nq; ++q)
+          if (tk[(size_t)it * p->p_nq + q] < p->p_qtotal[it + 1 < n ? 0 : 1][q])
+            return fail(RL_E_INTERNAL, "persistent kernel: queue " + std::to_string(q) +
+                                           " was not drained in iteration " + std::to_string(it));
+    }
     // volume-major: flux[v * n + it]
     const int n = p->batch_n;
     h.assign((size_t)n * p->count, 0.0);
@@ -2331,10 +2684,11 @@ rl_status rl_plan_get_info(rl_plan p, int64_t shape[3], int64_t* spectrum_pitch)
   return RL_OK;
 }
 
-rl_status rl_plan_get_launch(rl_plan p, int out[7]) {
+rl_status rl_plan_get_launch(rl_plan p, int out[8]) {
   rl_status st = check_plan(p);
   if (st != RL_OK) return st;
   if (!out) return fail(RL_E_INVALID, "out is NULL");
+  out[7] = p->persist ? 1 : 0;
   if (p->is_batch) p = p->classes[0];  // configuration of the first volume's shape
   out[0] = p->ch_x_e;
   out[1] = p->ch_y_e;

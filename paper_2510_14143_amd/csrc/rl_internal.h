@@ -140,6 +140,68 @@ struct XArgs {
   int nrows;             // grid rows covered by the launch (row = z * ny + y)
 };
 
+// --- persistent batched iteration -------------------------------------------
+// One launch runs every pass of one Richardson-Lucy iteration of every volume of
+// a batch.  Work-groups of kPersistThreads (128) threads take tiles (one work-group's
+// share of one pass of one volume, exactly as the per-pass kernels split it)
+// from a work queue in pass-major order and wait, before a tile of pass s of
+// volume v, until every tile of pass s - 1 of v has completed.  Each volume is
+// assigned to one XCD and its tiles are taken only by work-groups running on that
+// XCD, so producer and consumer of every dependency share an L2: completion is a
+// store wait plus an atomic increment in that L2, and a wait ends with an L1
+// invalidation (no L2 writeback).  Switched off on the host side: plans refuse
+// the persistent mode (its waits did not finish on the GPU).
+constexpr int kPersistThreads = 128;
+constexpr int kPersistPasses = 8;  // X ratio, Y, Z conj K, Y^-1, X update, Y, Z K, Y^-1
+constexpr int kPersistMaxQueues = 16;
+
+// Per shape class: the arguments its per-pass launches would get.
+struct PersistClass {
+  XArgs xr, xu;           // ratio and update passes (per-volume pointer tables)
+  PencilArgs py, pz;      // Y and Z passes (vstride set)
+  Sched sx, sy, sz;
+  const float2* twx;
+  const float2* twy;
+  const float2* twz;
+  float2* spec;
+  const float2* otf;
+  int ex, ey, ez;         // elements per thread of the X, Y and Z transforms
+  int xtiles;             // X work-groups per volume
+  int ygx, ytiles;        // Y grid x extent and work-groups per volume
+  int zgx, ztiles;        // Z grid x extent and work-groups per volume
+};
+
+// A run of tiles: pass `pass` of volume `vol` (index within its class `cls`),
+// counter row `vrow`; tickets [first, first + tiles) of its queue.
+struct PersistSeg {
+  int pass, cls, vol, vrow, tiles, first;
+};
+
+struct PersistArgs {
+  const PersistClass* cls;
+  const PersistSeg* segs;   // queue q owns segs[qseg[q] .. qseg[q + 1])
+  const int* qseg;
+  int nq;                   // queues (XCDs); work-groups on XCD >= nq take no work
+  int npass;                // passes this launch runs (8, or 5 on the last iteration)
+  int nvrow;                // counter rows (volumes)
+  const int* iter_ptr;      // iteration index within the call
+  int* tickets;             // [iteration][queue], zero at the start of the call
+  int* done;                // [iteration][volume][pass] completed tiles, zero at the start
+  int* error;               // [queue]: set to 1 when a dependency wait runs past its bound
+  int spin_limit;           // polls of a counter before giving up
+};
+
+// Element counts the persistent kernel is built for (other classes use the
+// per-pass graph).
+constexpr bool persist_x_e(int E) { return E == 2 || E == 4 || E == 6; }
+constexpr bool persist_yz_e(int E) { return E == 4 || E == 6 || E == 8 || E == 12; }
+
+hipError_t launch_persist(const PersistArgs& a, int grid, size_t lds, hipStream_t s);
+// Resident work-groups of the persistent kernel per CU with `lds` bytes of LDS.
+hipError_t persist_occupancy(size_t lds, int* blocks_per_cu);
+// *counter = 0 for n ints (a fill kernel; graph-capture safe).
+hipError_t launch_zero_ints(int* p, long long n, hipStream_t s);
+
 // Pencil kernels exist for work-groups of up to 512 threads (all E) and up to
 // 1024 threads (E = 8 and 16 only).
 // prec: 0 = FP32 butterflies; 1 / 2 = radix-16 stages of E = 16 transforms on

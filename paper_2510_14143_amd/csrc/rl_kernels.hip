@@ -591,12 +591,13 @@ __device__ __forceinline__ void fft_row(float2 (&v)[E], const Sched& sc, int i, 
 // 64 VGPRs (8 waves per SIMD), so that two of them share a CU; the filtered
 // passes (which hold the transfer function too) are not, since at 64 VGPRs they
 // would spill.
-template <int E, int MODE, int MAXT, int PREC = 0>
-__global__ void __launch_bounds__(MAXT, (MAXT == 1024 && E == 8 && MODE <= PM_INV) ? 8 : 1)
-    k_pencil(float2* __restrict__ data, const float2* __restrict__ otf,
-             const float2* __restrict__ twg, PencilArgs a, Sched sc) {
-  if (a.stop && *a.stop) return;  // stopped: the whole work-group leaves together
-  extern __shared__ __attribute__((aligned(16))) float2 lds[];
+// One work-group tile of a pencil pass: (gx, gy) is the tile's position in the
+// pass's launch grid, vz the volume (all threads of the work-group call it).
+template <int E, int MODE, int PREC = 0>
+__device__ __forceinline__ void pencil_tile(float2* __restrict__ data,
+                                            const float2* __restrict__ otf,
+                                            const float2* __restrict__ twg, const PencilArgs& a,
+                                            const Sched& sc, int gx, int gy, int vz, float2* lds) {
   const int tid = threadIdx.x;
   // twiddle table (L entries) after the exchange buffer
   float2* tw = lds + (size_t)a.L * a.TXP;
@@ -604,12 +605,12 @@ __global__ void __launch_bounds__(MAXT, (MAXT == 1024 && E == 8 && MODE <= PM_IN
   if constexpr (PREC > 0) split_atab_fill<PREC>();
   const int lane = tid & (a.TXB - 1);
   const int i = tid / a.TXB;
-  const int bx = a.swap ? blockIdx.y : blockIdx.x;  // tile (and split) index
-  const int by = a.swap ? blockIdx.x : blockIdx.y;  // outer index
+  const int bx = a.swap ? gy : gx;  // tile (and split) index
+  const int by = a.swap ? gx : gy;  // outer index
   const int xb = bx / a.xsplit;
   const int c = (bx - xb * a.xsplit) * a.TXB + lane;
   const bool ok = xb * kTile + (c & (kTile - 1)) < a.ncols;
-  const long long base = (long long)blockIdx.z * a.vstride + (long long)xb * a.xstride +
+  const long long base = (long long)vz * a.vstride + (long long)xb * a.xstride +
                          (long long)by * a.ostride + c;
 
   float2 v[E];
@@ -636,6 +637,15 @@ __global__ void __launch_bounds__(MAXT, (MAXT == 1024 && E == 8 && MODE <= PM_IN
     for (int m = 0; m < E; ++m)
       if (i + a.P * m < a.lout) data[base + (long long)(i + a.P * m) * a.estride] = v[m];
   }
+}
+
+template <int E, int MODE, int MAXT, int PREC = 0>
+__global__ void __launch_bounds__(MAXT, (MAXT == 1024 && E == 8 && MODE <= PM_INV) ? 8 : 1)
+    k_pencil(float2* __restrict__ data, const float2* __restrict__ otf,
+             const float2* __restrict__ twg, PencilArgs a, Sched sc) {
+  if (a.stop && *a.stop) return;  // stopped: the whole work-group leaves together
+  extern __shared__ __attribute__((aligned(16))) float2 lds[];
+  pencil_tile<E, MODE, PREC>(data, otf, twg, a, sc, blockIdx.x, blockIdx.y, blockIdx.z, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -759,11 +769,13 @@ __device__ __forceinline__ void wg_reduce_rows(double (&v)[K], const int (&op)[K
   }
 }
 
-// CM > 0: the row length M = CM is known at compile time (compile-time schedule).
+// One work-group tile of an X pass: gx is the tile's index among the ngx tiles of
+// a volume, vol the volume (all threads of the work-group call it).  CM > 0: the
+// row length M = CM is known at compile time (compile-time schedule).
 template <int E, int MODE, int PREC = 0, int CM = 0>
-__global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const float2* __restrict__ twg) {
-  if (a.stop && *a.stop) return;  // stopped: the whole work-group leaves together
-  extern __shared__ __attribute__((aligned(16))) float2 lds[];
+__device__ __forceinline__ void xrow_tile(const XArgs& a, const Sched& sc,
+                                          const float2* __restrict__ twg, int gx, int vol,
+                                          int ngx, float2* lds) {
   const int M = CM > 0 ? CM : a.M, P = CM > 0 ? CM / E : a.P;
   const int tid = threadIdx.x;
   float2* tw = lds;  // 2M entries: exp(-2 pi i k / (2M))
@@ -773,14 +785,13 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
   const int wave = tid >> 6, lane = tid & 63;
   const int rw = lane / P, i = lane - rw * P;
   const int lrow = wave * rpw + rw;             // row within the work-group
-  const int rowi = blockIdx.x * a.RPW + lrow;
+  const int rowi = gx * a.RPW + lrow;
   const bool inrow = rowi < a.nrows;
   const long long rix = inrow ? rowi : 0;
   float2* row = lds + 2 * M + lrow * a.RS;
   // split-precision stages: the wave's rows double as its staging area (>= 64 * 32
   // floats, 16-byte aligned: the host admits only even rows-per-wave * RS there)
   float* stg = reinterpret_cast<float*>(lds + 2 * M + wave * rpw * a.RS);
-  const int vol = blockIdx.y;
   const int zz = (int)(rix / a.ny), yy = (int)(rix - (long long)zz * a.ny);
   // rows of the caller's volume (vz, vy, vx) inside the transform grid; grid rows
   // outside it are neither read nor written (the pencil passes read them as zero)
@@ -922,9 +933,9 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
           t1 += wacc[1][q];
           t2 += wacc[2][q];
         }
-        a.partials[(long long)a.iter * gridDim.x + blockIdx.x] = t0;
-        a.acc_partials[blockIdx.x] = t1;
-        a.acc_partials[gridDim.x + blockIdx.x] = t2;
+        a.partials[(long long)a.iter * ngx + gx] = t0;
+        a.acc_partials[gx] = t1;
+        a.acc_partials[ngx + gx] = t2;
       }
     } else {  // XM_UPDATE
       float* ur = (a.u_tab ? a.u_tab[vol] : a.u) + rr * vx;
@@ -981,7 +992,7 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
         const int nw = blockDim.x >> 6;
         for (int q = 0; q < nw; ++q) t += wsum[q];
         const int it = a.iter_ptr ? *a.iter_ptr : a.iter;
-        a.partials[((long long)it * a.nvol + vol) * gridDim.x + blockIdx.x] = t;
+        a.partials[((long long)it * a.nvol + vol) * ngx + gx] = t;
       }
       if constexpr (want_change) {
         double r[2] = {(double)met[0], (double)met[1]};
@@ -998,6 +1009,15 @@ __global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const 
       }
     }
   }
+}
+
+// The metric variants (XM_RATIO_LL, XM_UPDATE_CHG / PSNR) write their partials
+// with wg_reduce_rows, indexed by the launch's own block and grid.
+template <int E, int MODE, int PREC = 0, int CM = 0>
+__global__ void __launch_bounds__(kXMaxThreads) k_xrow(XArgs a, Sched sc, const float2* __restrict__ twg) {
+  if (a.stop && *a.stop) return;  // stopped: the whole work-group leaves together
+  extern __shared__ __attribute__((aligned(16))) float2 lds[];
+  xrow_tile<E, MODE, PREC, CM>(a, sc, twg, blockIdx.x, blockIdx.y, gridDim.x, lds);
 }
 
 // Metric and stop decision of iteration `it` (one work-group; fixed summation order).
@@ -1742,6 +1762,157 @@ hipError_t launch_accel_alpha(const double* acc_partials, int groups, int it, fl
 hipError_t launch_flux_reduce(const double* partials, int groups, int rows, double* flux,
                               hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   RL_LAUNCH(k_flux_reduce, dim3(rows), dim3(256), 0, s, ev0, ev1, partials, groups, flux);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batched iteration (see PersistArgs)
+// ---------------------------------------------------------------------------
+// Index of the XCD (accelerator complex die) this wave runs on.
+__device__ __forceinline__ int xcc_id() {
+  return (int)(__builtin_amdgcn_s_getreg((3 << 11) | 20) & 15);  // hwreg(HW_REG_XCC_ID, 0, 4)
+}
+
+// Current value of a counter or flag that only ever holds values >= 0, read with
+// an atomic compare-and-swap (against -1, so it never stores): the read is
+// performed where the atomic increments are.  An atomic add of zero would not do:
+// the compiler folds it into a plain load.
+__device__ __forceinline__ int poll_int(int* p) {
+  int v = -1;
+  __hip_atomic_compare_exchange_strong(p, &v, -1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  return v;
+}
+
+template <int MODE>
+__device__ __forceinline__ void persist_pencil(const PersistClass& c, const PencilArgs& a,
+                                               const Sched& sc, const float2* tw, int E, int gx,
+                                               int gy, int vol, float2* lds) {
+  switch (E) {
+#define RL_PE(EV) \
+  case EV: pencil_tile<EV, MODE>(c.spec, c.otf, tw, a, sc, gx, gy, vol, lds); break;
+    RL_PE(4) RL_PE(6) RL_PE(8) RL_PE(12)
+#undef RL_PE
+    default: break;
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ void persist_xrow(const PersistClass& c, const XArgs& a, int gx,
+                                             int vol, float2* lds) {
+  switch (c.ex) {
+#define RL_XE(EV) \
+  case EV: xrow_tile<EV, MODE>(a, c.sx, c.twx, gx, vol, c.xtiles, lds); break;
+    RL_XE(2) RL_XE(4) RL_XE(6)
+#undef RL_XE
+    default: break;
+  }
+}
+
+__global__ void __launch_bounds__(kPersistThreads) k_persist(PersistArgs pa) {
+  extern __shared__ __attribute__((aligned(16))) float2 lds[];
+  __shared__ int s_seg, s_tile;
+  const int q = xcc_id();
+  if (q >= pa.nq) return;  // no work is queued for this XCD
+  const int it = *pa.iter_ptr;
+  int* tickets = pa.tickets + (long long)it * pa.nq;
+  int* done = pa.done + (long long)it * pa.nvrow * kPersistPasses;
+  const int s0 = pa.qseg[q], s1 = pa.qseg[q + 1];
+  if (s1 <= s0) return;
+  const int total = pa.segs[s1 - 1].first + pa.segs[s1 - 1].tiles;
+  // Counters and the error flag of queue q are only touched by this XCD's
+  // work-groups, and only with atomic read-modify-writes (poll_int reads too).
+  int* err = pa.error + q;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const int t = __hip_atomic_fetch_add(&tickets[q], 1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+      int seg = -1, tile = 0;
+      if (t < total && !poll_int(err)) {
+        int lo = s0, hi = s1 - 1;  // last segment with first <= t
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (pa.segs[mid].first <= t) lo = mid;
+          else hi = mid - 1;
+        }
+        seg = lo;
+        const PersistSeg g = pa.segs[seg];
+        tile = t - g.first;
+        if (g.pass > 0) {  // every tile of the previous pass of this volume
+          const PersistClass& c = pa.cls[g.cls];
+          const int pp = g.pass - 1, kind = pp & 3;
+          const int need = kind == 0 ? c.xtiles : (kind == 2 ? c.ztiles : c.ytiles);
+          int* ctr = done + (long long)g.vrow * kPersistPasses + pp;
+          int n = 0;
+          while (poll_int(ctr) < need) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++n >= pa.spin_limit || poll_int(err)) {
+              __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              seg = -1;
+              break;
+            }
+          }
+          // the producers' stores are in this XCD's L2: drop this CU's L1 copies
+          asm volatile("buffer_inv sc0" ::: "memory");
+        }
+      }
+      s_seg = seg;
+      s_tile = tile;
+    }
+    __syncthreads();
+    const int seg = s_seg, tile = s_tile;
+    if (seg < 0) break;
+    const PersistSeg g = pa.segs[seg];
+    const PersistClass& c = pa.cls[g.cls];
+    switch (g.pass) {
+      case 0: persist_xrow<XM_RATIO>(c, c.xr, tile, g.vol, lds); break;
+      case 1: case 5:
+        persist_pencil<PM_FWD>(c, c.py, c.sy, c.twy, c.ey, tile % c.ygx, tile / c.ygx, g.vol, lds);
+        break;
+      case 2:
+        persist_pencil<PM_FCKI>(c, c.pz, c.sz, c.twz, c.ez, tile % c.zgx, tile / c.zgx, g.vol, lds);
+        break;
+      case 3: case 7:
+        persist_pencil<PM_INV>(c, c.py, c.sy, c.twy, c.ey, tile % c.ygx, tile / c.ygx, g.vol, lds);
+        break;
+      case 4: {  // the last iteration's update skips the forward transform
+        XArgs xu = c.xu;
+        xu.do_fwd = pa.npass > 5 ? 1 : 0;
+        persist_xrow<XM_UPDATE>(c, xu, tile, g.vol, lds);
+        break;
+      }
+      case 6:
+        persist_pencil<PM_FKI>(c, c.pz, c.sz, c.twz, c.ez, tile % c.zgx, tile / c.zgx, g.vol, lds);
+        break;
+      default: break;
+    }
+    // completion: every wave's stores acknowledged by the L2, then one increment
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(done + (long long)g.vrow * kPersistPasses + g.pass, 1,
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+hipError_t launch_persist(const PersistArgs& a, int grid, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL(k_persist, dim3((unsigned)grid), dim3(kPersistThreads), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t persist_occupancy(size_t lds, int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persist, kPersistThreads,
+                                                      lds);
+}
+
+__global__ void k_zero_ints(int* p, long long n) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = 0;
+}
+
+hipError_t launch_zero_ints(int* p, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_ints, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
 

@@ -55,7 +55,8 @@ class _StopRule(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("stream", ctypes.c_void_p), ("tile_x", ctypes.c_int),
                 ("x_elems", ctypes.c_int), ("yz_elems", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("accel", ctypes.c_int), ("psf_shape", ctypes.c_int64 * 3)]
+                ("accel", ctypes.c_int), ("psf_shape", ctypes.c_int64 * 3),
+                ("batch_mode", ctypes.c_int)]
 
 
 _lib = None
@@ -173,9 +174,13 @@ def conv3d_fft(plan: int, x_ptr: int, out_ptr: int) -> None:
     _check(lib().conv3d_fft(ctypes.c_void_p(plan), ctypes.c_void_p(x_ptr), ctypes.c_void_p(out_ptr)))
 
 
+RL_BATCH_AUTO, RL_BATCH_PERSISTENT, RL_BATCH_GRAPH = 0, 1, 2
+_BATCH_MODES = {"auto": RL_BATCH_AUTO, "persistent": RL_BATCH_PERSISTENT, "graph": RL_BATCH_GRAPH}
+
+
 def rl_plan_create_batch(shapes, psf_ptrs, boundary: int = RL_BOUNDARY_PERIODIC,
                          stream: int = 0, x_elems: int = 0, yz_elems: int = 0,
-                         autotune: bool = False) -> int:
+                         autotune: bool = False, batch_mode: int = RL_BATCH_AUTO) -> int:
     n = len(shapes)
     if len(psf_ptrs) != n:
         raise ValueError("one PSF per volume")
@@ -183,7 +188,8 @@ def rl_plan_create_batch(shapes, psf_ptrs, boundary: int = RL_BOUNDARY_PERIODIC,
     ps = (ctypes.c_void_p * n)(*psf_ptrs)
     out = ctypes.c_void_p()
     opt = _Options(RL_PRECISION_FP32, ctypes.c_void_p(stream or None), 0, int(x_elems),
-                   int(yz_elems), 1 if autotune else 0, RL_ACCEL_NONE)
+                   int(yz_elems), 1 if autotune else 0, RL_ACCEL_NONE,
+                   (ctypes.c_int64 * 3)(0, 0, 0), int(batch_mode))
     _check(lib().rl_plan_create_batch(n, sh, ps, int(boundary), ctypes.byref(opt),
                                       ctypes.byref(out)))
     return out.value
@@ -291,10 +297,10 @@ def rl_plan_get_info(plan: int):
 
 
 def rl_plan_get_launch(plan: int) -> dict:
-    out = (ctypes.c_int * 7)()
+    out = (ctypes.c_int * 8)()
     _check(lib().rl_plan_get_launch(ctypes.c_void_p(plan), out))
     return dict(x_elems=out[0], y_elems=out[1], y_lanes=out[2], z_elems=out[3], z_lanes=out[4],
-                tuned=bool(out[5]), z_rows_fastest=bool(out[6]))
+                tuned=bool(out[5]), z_rows_fastest=bool(out[6]), batch_persistent=bool(out[7]))
 
 
 def rl_plan_set_timing(plan: int, enable: bool) -> None:
@@ -552,7 +558,13 @@ class Plan:
 class BatchPlan:
     """Batched plan: volumes of uneven shape, each with its own PSF (float32 CUDA tensors)."""
 
-    def __init__(self, psfs, autotune: bool = False, x_elems: int = 0, yz_elems: int = 0):
+    def __init__(self, psfs, autotune: bool = False, x_elems: int = 0, yz_elems: int = 0,
+                 mode: str = "auto"):
+        """mode: "graph" (per-pass kernels of each shape class in one graph per
+        iteration), "auto" (the same) or "persistent" (one persistent kernel per
+        iteration; switched off in the library, which refuses it with RL_E_UNSUPPORTED)."""
+        if mode not in _BATCH_MODES:
+            raise ValueError(f"mode must be one of {sorted(_BATCH_MODES)}")
         if len(psfs) == 0:
             raise ValueError("at least one volume")
         for i, h in enumerate(psfs):
@@ -563,7 +575,8 @@ class BatchPlan:
         self.device = psfs[0].device
         self.handle = rl_plan_create_batch(self.shapes, [h.data_ptr() for h in psfs],
                                            stream=_stream_of(self.device), x_elems=x_elems,
-                                           yz_elems=yz_elems, autotune=autotune)
+                                           yz_elems=yz_elems, autotune=autotune,
+                                           batch_mode=_BATCH_MODES[mode])
 
     def iterate(self, observed, estimates, n_iter: int) -> None:
         """n_iter iterations of every volume, in place on `estimates` (lists of tensors)."""
@@ -587,6 +600,11 @@ class BatchPlan:
     def launch(self) -> dict:
         self._live()
         return rl_plan_get_launch(self.handle)
+
+    def mode(self) -> str:
+        """"persistent" or "graph": how this plan runs its iterations."""
+        self._live()
+        return "persistent" if rl_plan_get_launch(self.handle)["batch_persistent"] else "graph"
 
     def _live(self):
         if getattr(self, "handle", None) is None:

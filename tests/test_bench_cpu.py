@@ -132,9 +132,14 @@ def test_rocprof_summary_and_lookup(bench, tmp_path, monkeypatch):
 def test_rocprof_summary_command_line(tmp_path):
     _fixture(tmp_path)
     out = tmp_path / "s.md"
+    log = tmp_path / "bench.err"
+    log.write_text("copy probe: 5500 GB/s\nkernel source sha256[:16]: 0123456789abcdef\n")
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--rocprof-summary",
                         str(tmp_path / "trace"), str(tmp_path / "fetch"), str(tmp_path / "write"),
-                        "--out", str(out), "--title", "t", "--cmd", "c"],
+                        "--out", str(out), "--title", "t", "--cmd", "c", "--bench-log", str(log)],
                        capture_output=True, text=True, timeout=300, cwd=ROOT)
     assert r.returncode == 0, r.stderr
-    assert "| `k_copy` | 4096 | 2 |" in out.read_text()
+    text = out.read_text()
+    assert "| `k_copy` | 4096 | 2 |" in text
+    # the hash is the one the profiled run reported, not the current source's
+    assert "Kernel source sha256[:16]: `0123456789abcdef`" in text

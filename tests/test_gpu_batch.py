@@ -213,3 +213,111 @@ def test_full_size_batch_workload_50_iterations(torch, batch96):
             "max abs / peak", worst)
         assert err <= 1e-4
         assert abs(flux[v][-1] - ref_flux[v]) / ref_flux[v] <= 1e-6
+
+
+# shapes whose every pass splits into the persistent kernel's 128-thread work-groups;
+# their launch shapes hold the same elements per thread on Y and Z (ny = 2 nz)
+PERSIST_SHAPES = [(24, 48, 48), (32, 64, 64), (24, 48, 48), (48, 96, 96), (32, 64, 64)]
+PERSIST_ELEMS = {(24, 48, 48): (6, 6), (32, 64, 64): (4, 8), (48, 96, 96): (6, 12)}
+
+
+# The library refuses the persistent mode: a run of the first test below did not
+# finish within its two-minute limit, and neither did the one that tested a change
+# of its completion polls (which, as it turned out, the compiler had folded back
+# into the same plain loads).  Its tests stay, skipped, until the mode is switched
+# on again.
+PERSIST_OFF = pytest.mark.skip(reason="persistent batched kernel switched off: its completion "
+                                      "waits did not finish on the GPU")
+
+
+def persist_cases():
+    out = []
+    for i, shp in enumerate(PERSIST_SHAPES):
+        sig = (1.0 + 0.3 * i, 1.2 + 0.2 * i, 2.0 + 0.25 * i)
+        out.append(synth.small_case(shp, sigma_xyz=sig, seed=40 + i, density=2.0))
+    return out
+
+
+@PERSIST_OFF
+def test_persistent_batch_matches_oracle_and_single_plans(torch):
+    # one persistent launch per iteration: every volume against the oracle, and bit
+    # for bit against single-volume plans with the same elements per thread (the
+    # same kernels' arithmetic, run as persistent tiles)
+    say("persistent batch vs oracle and single plans")
+    cs = persist_cases()
+    n_iter = 10
+    with rl.BatchPlan([dev(torch, c["psf"]) for c in cs], mode="persistent") as bp:
+        assert bp.mode() == "persistent"
+        d = [dev(torch, c["d"]) for c in cs]
+        u = [dev(torch, c["u0"]) for c in cs]
+        bp.iterate(d, u, n_iter)
+        flux = bp.flux()
+    for i, c in enumerate(cs):
+        ref, ref_flux, _ = oracle.rl(c["d"], c["psf"], c["u0"], n_iter)
+        got = u[i].cpu().numpy()
+        err = oracle.rel_l2(got, ref)
+        say("  volume", i, c["shape"], "relL2", err)
+        assert err <= 1e-4
+        assert np.max(np.abs(flux[i] - ref_flux) / ref_flux) <= 1e-6
+        xe, yze = PERSIST_ELEMS[tuple(c["shape"])]
+        with rl.Plan(dev(torch, c["psf"]), x_elems=xe, yz_elems=yze) as p:
+            us = dev(torch, c["u0"])
+            p.iterate(d[i], us, n_iter)
+            fs = p.flux()
+        assert torch.equal(us, u[i]), i
+        assert np.array_equal(fs, flux[i]), i
+
+
+@PERSIST_OFF
+def test_persistent_batch_replays_resume_and_growth(torch):
+    # separate calls replay the same two graphs (one persistent launch each); a call
+    # longer than the counters' and partials' capacity grows them and re-captures
+    say("persistent batch replays")
+    cs = persist_cases()
+    with rl.BatchPlan([dev(torch, c["psf"]) for c in cs], mode="persistent") as bp:
+        d = [dev(torch, c["d"]) for c in cs]
+        a = [dev(torch, c["u0"]) for c in cs]
+        bp.iterate(d, a, 7)
+        b = [dev(torch, c["u0"]) for c in cs]
+        for k in (3, 1, 3):
+            bp.iterate(d, b, k)
+            junk = torch.randn(1 << 20, device="cuda:0")  # eager work between replays
+            junk.mul_(2.0).sum().item()
+        torch.cuda.synchronize()
+        for i in range(len(cs)):
+            assert torch.equal(a[i], b[i]), i
+        g = [dev(torch, c["u0"]) for c in cs]
+        bp.iterate(d, g, 130)
+        f = bp.flux()
+    assert f.shape == (len(cs), 130)
+    with rl.BatchPlan([dev(torch, c["psf"]) for c in cs], mode="graph") as gp:
+        assert gp.mode() == "graph"
+        h = [dev(torch, c["u0"]) for c in cs]
+        gp.iterate(d, h, 130)
+    for i, c in enumerate(cs):
+        total = float(c["d"].sum(dtype=np.float64))
+        assert np.all(np.abs(f[i] - total) / total <= 1e-6), i
+        # the graph form (its own launch shapes) agrees to rounding
+        err = float(torch.linalg.vector_norm((g[i] - h[i]).double()) /
+                    torch.linalg.vector_norm(h[i].double()))
+        assert err <= 1e-5, (i, err)
+
+
+def test_persistent_mode_refused(torch):
+    # the switched-off persistent mode is refused with RL_E_UNSUPPORTED, also for
+    # shapes its launch shapes would fit; "auto" runs the per-pass graph
+    for cs in (cases(), persist_cases()):
+        psfs = [dev(torch, c["psf"]) for c in cs]
+        with pytest.raises(rl.RLError) as ei:
+            rl.BatchPlan(psfs, mode="persistent")
+        assert ei.value.status == rl.RL_E_UNSUPPORTED
+        with rl.BatchPlan(psfs) as bp:
+            assert bp.mode() == "graph"
+            assert not bp.launch()["batch_persistent"]
+
+
+@PERSIST_OFF
+def test_benchmark_batch_runs_persistent(torch, batch96):
+    # every shape class of the benchmark's batch fits the persistent kernel
+    with rl.BatchPlan([dev(torch, v["psf"]) for v in batch96[:12]]) as bp:
+        assert bp.mode() == "persistent"
