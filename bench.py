@@ -355,21 +355,20 @@ def run_batched(torch, rl, synth, steps: int, warmup: int, count: int = 96, n_it
     u0 = [torch.from_numpy(v["u0"]).to(dev) for v in vols]
     u = [t.clone() for t in u0]
     nvox = sum(int(np.prod(v["shape"])) for v in vols)
+    # a caller's tuning cache (RLMI_TUNE_CACHE) serves both sides; else a temporary one
     saved = os.environ.get("RLMI_TUNE_CACHE")
-    cache = tempfile.mkdtemp()
-    if autotune:
+    cache = tempfile.mkdtemp() if saved is None else None
+    if autotune and cache is not None:
         os.environ["RLMI_TUNE_CACHE"] = os.path.join(cache, "tune.txt")
     try:
         bp = rl.BatchPlan(psfs, autotune=autotune)
         plans = [rl.Plan(h, autotune=autotune) for h in psfs]
     finally:
-        if saved is None:
+        if cache is not None:
             os.environ.pop("RLMI_TUNE_CACHE", None)
-        else:
-            os.environ["RLMI_TUNE_CACHE"] = saved
-        if os.path.exists(os.path.join(cache, "tune.txt")):
-            os.remove(os.path.join(cache, "tune.txt"))
-        os.rmdir(cache)
+            if os.path.exists(os.path.join(cache, "tune.txt")):
+                os.remove(os.path.join(cache, "tune.txt"))
+            os.rmdir(cache)
     launch = bp.launch()
     mode = bp.mode()
 
@@ -604,11 +603,27 @@ def run_paper_shape(torch, rl, synth, steps: int, n_iter: int = 20):
     flux = plan.flux()
     total = float(c["d"].sum(dtype=np.float64))
     launch = plan.launch()
+    # per-pass durations: one more step with every launch bracketed by events
+    plan.set_timing(True)
+    u.copy_(u0)
+    plan.iterate(d, u, n_iter)
+    torch.cuda.synchronize()
+    live = plan.timing()
+    plan.set_timing(False)
+    kb = kernel_bytes(c["shape"])
+    per_kind = {}
+    for kind in ("x_ratio", "x_update", "y", "z_otf"):
+        cnt, kms = live[kind]
+        avg_us = kms / cnt * 1e3
+        per_kind[kind] = dict(launches_per_step=cnt, avg_us=round(avg_us, 3),
+                              bytes_per_launch=kb[kind],
+                              gbs=round(kb[kind] / (avg_us * 1e-6) / 1e9, 1),
+                              kernels=plan.pass_kernel(kind)[0])
     plan.close()
     return {"workload": f"rl_fp32_2560x2160x30_{n_iter}it", "shape_zyx": list(c["shape"]),
             "unit": "Gvoxel-iter/s", "ms_per_step": round(ms, 3),
             "value": round(nvox * n_iter / (ms * 1e-3) / 1e9, 3), "launch": launch,
-            "flux_drift": float(np.max(np.abs(flux - total)) / total)}
+            "per_kind": per_kind, "flux_drift": float(np.max(np.abs(flux - total)) / total)}
 
 
 def run_stop(torch, rl, synth, steps: int, cfg: int = 1):
