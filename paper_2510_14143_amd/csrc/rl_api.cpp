@@ -485,7 +485,13 @@ void release(rl_plan p) {
   delete p;
 }
 
-int max_threads_for(int E) { return (E == 8 || E == 16) ? 1024 : rlmi::kPencilMaxThreads; }
+// Work-group thread bound of the pencil kernels of E elements per thread (and, for
+// the compile-time pencil kernels, length L).
+int max_threads_for(int E, int64_t L = 0) {
+  if (E == 8 || E == 16) return 1024;
+  const int ct = rlmi::pencil_ct_max_threads(E, (int)L);
+  return rlmi::pencil_compiled_len(E, (int)L, ct) > 0 ? ct : rlmi::kPencilMaxThreads;
+}
 
 Axis make_axis(int64_t L, int e = 0) {
   Axis ax;
@@ -515,7 +521,7 @@ int pow2_floor(int v) {
 }
 
 bool pencil_fits(const Pencil& pc) {
-  return (int)pc.block.x <= max_threads_for(pc.ax.E) && pc.lds <= kMaxPencilLds;
+  return (int)pc.block.x <= max_threads_for(pc.ax.E, pc.ax.L) && pc.lds <= kMaxPencilLds;
 }
 
 // Y pass: one work-group per (tile column, z); lanes = `req` (a power of two
@@ -524,7 +530,7 @@ Pencil make_pencil_y(int64_t ny, int64_t nz, int64_t xt, int64_t ncols, int req,
                      int maxt_cap = 1024) {
   Pencil pc;
   pc.ax = make_axis(ny, e);
-  const int maxt = std::min(max_threads_for(pc.ax.E), maxt_cap);
+  const int maxt = std::min(max_threads_for(pc.ax.E, pc.ax.L), maxt_cap);
   int txb = req > 0 ? pow2_floor(req < rlmi::kTile ? req : rlmi::kTile) : rlmi::kTile;
   while (txb > 1 && ((int64_t)txb * pc.ax.P > maxt ||
                      (size_t)ny * (txb + 1) * sizeof(float2) > kMaxPencilLds))
@@ -547,7 +553,7 @@ Pencil make_pencil_z(int64_t nz, int64_t ny, int64_t xt, int64_t ncols, int req,
                      int maxt_cap = 1024) {
   Pencil pc;
   pc.ax = make_axis(nz, e);
-  const int maxt = std::min(max_threads_for(pc.ax.E), maxt_cap);
+  const int maxt = std::min(max_threads_for(pc.ax.E, pc.ax.L), maxt_cap);
   auto fits = [&](int txb) {
     if (txb >= rlmi::kTile && ny % (txb / rlmi::kTile) != 0) return false;
     return (int64_t)txb * pc.ax.P <= maxt &&
@@ -721,7 +727,8 @@ int pencil_thread_cap(rl_plan p) { return p->precision == RL_PRECISION_FP32 ? 10
 // (host side, outside any graph capture) for every mode the pass may launch.
 bool prepare_pencil(rl_plan p, const Pencil& pc) {
   for (int mode : {rlmi::PM_FWD, rlmi::PM_INV, rlmi::PM_FKI, rlmi::PM_FCKI})
-    if (rlmi::prepare_pencil(mode, pc.ax.E, p->precision, pc.block, pc.lds) != hipSuccess) {
+    if (rlmi::prepare_pencil(mode, pc.ax.E, pc.args.L, p->precision, pc.block, pc.lds) !=
+        hipSuccess) {
       (void)hipGetLastError();
       return false;
     }
@@ -2771,10 +2778,15 @@ rl_status rl_plan_get_pass_kernel(rl_plan p, int kind, char* name, size_t cap, i
     // the instantiation launch_pencil picks for this shape and precision
     const int maxt = (int)pc.block.x > rlmi::kPencilMaxThreads ? 1024 : rlmi::kPencilMaxThreads;
     const int prec = (pc.ax.E == 16 && pc.block.x % 64 == 0) ? p->precision : 0;
+    const int cl = rlmi::pencil_compiled_len(pc.ax.E, pc.args.L, (int)pc.block.x);
     for (int m : {m0, m1}) {
       if (!s.empty()) s += "|";
-      s += "k_pencil<" + std::to_string(pc.ax.E) + ", " + std::to_string(m) + ", " +
-           std::to_string(maxt) + ", " + std::to_string(prec) + ">";
+      if (cl > 0)
+        s += "k_pencil_ct<" + std::to_string(pc.ax.E) + ", " + std::to_string(m) + ", " +
+             std::to_string(prec) + ", " + std::to_string(cl) + ">";
+      else
+        s += "k_pencil<" + std::to_string(pc.ax.E) + ", " + std::to_string(m) + ", " +
+             std::to_string(maxt) + ", " + std::to_string(prec) + ">";
     }
     n = (int64_t)pc.grid.x * pc.grid.y * pc.block.x;
   };

@@ -81,11 +81,30 @@ enum XMode {
 // Row length M the X-pass kernel of (mode, E, M, prec) is compiled for (0 = the
 // runtime schedule): the per-iteration ratio and update passes of power-of-two
 // rows M in {64, 128, 256, 512} with E in {4, 8} elements per thread and at most
-// 64 threads per row.
+// 64 threads per row, and of the 2560-sample rows of the paper's stack (M = 1280
+// = 4^4 * 5, E = 20).
 constexpr int xrow_compiled_len(int mode, int E, int M, int prec) {
-  return ((mode == XM_RATIO || mode == XM_UPDATE) && (E == 4 || E == 8) && prec == 0 &&
-          (M == 64 || M == 128 || M == 256 || M == 512) && M / E <= 64)
+  return ((mode == XM_RATIO || mode == XM_UPDATE) && prec == 0 &&
+          (((E == 4 || E == 8) && (M == 64 || M == 128 || M == 256 || M == 512) && M / E <= 64) ||
+           (E == 20 && M == 1280)))
              ? M
+             : 0;
+}
+
+// Thread bound of the compile-time pencil kernel of (E, L): the 2160-point pencils
+// of the paper's stack (E = 30, 72 threads per pencil) run 8 lanes, 576 threads.
+constexpr int pencil_ct_max_threads(int E, int L) {
+  return (E == 30 && L == 2160) ? 576 : kPencilMaxThreads;
+}
+
+// Length L the pencil kernel of (E, L, work-group threads) is compiled for (0 =
+// the runtime schedule): power-of-two pencils L in {128, 256, 512} with 16
+// elements per thread, in every precision (the split-precision forms run their
+// 16-point MFMA stages there), and the 2160-point pencils with 30.
+constexpr int pencil_compiled_len(int E, int L, int threads) {
+  return ((E == 16 && (L == 128 || L == 256 || L == 512)) || (E == 30 && L == 2160)) &&
+                 threads <= pencil_ct_max_threads(E, L)
+             ? L
              : 0;
 }
 
@@ -212,7 +231,7 @@ hipError_t launch_pencil(int mode, int E, int prec, dim3 grid, dim3 block, size_
                          const PencilArgs& a, const Sched& sc, hipEvent_t ev0 = nullptr,
                          hipEvent_t ev1 = nullptr);
 // Sets the kernel attributes a launch with this shape needs (no launch).
-hipError_t prepare_pencil(int mode, int E, int prec, dim3 block, size_t lds);
+hipError_t prepare_pencil(int mode, int E, int L, int prec, dim3 block, size_t lds);
 hipError_t launch_xrow(int mode, int E, int prec, dim3 grid, dim3 block, size_t lds,
                        hipStream_t s, const XArgs& a, const Sched& sc, const float2* tw,
                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);

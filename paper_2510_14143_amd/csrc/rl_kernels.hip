@@ -48,6 +48,14 @@ __device__ __forceinline__ float2 mul_si(float2 a) {
 // Ordering point for LDS traffic that stays inside one wavefront: the lanes of
 // a wave execute in lock step and a wave's LDS operations complete in issue
 // order, so only the compiler must be kept from moving accesses across it.
+// A copy of v that the compiler cannot see through: index arithmetic derived from
+// it is not merged with that of an earlier transform of the same schedule (which
+// would keep every such address in a register from one transform to the other).
+__device__ __forceinline__ int opaque_int(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -301,12 +309,17 @@ __device__ __forceinline__ void split_atab_fill() {
 }
 
 // Staging slot (in float4 units) of 16-byte granule G (0..7) of row t: rows of 32
-// floats, granules XOR-swizzled by f(t) = (t ^ t >> 3) & 7, which takes distinct
-// values on every 8 consecutive rows and, within 16 consecutive rows, on the even
-// and on the odd ones.  A row's granules, and one granule across 8 or 16 rows, thus
-// fall into distinct LDS banks with 128-byte and with 256-byte bank spans.
+// floats, granules XOR-swizzled by f(t) = (n ^ n >> 3) & 7 with n = t mod 16, which
+// takes distinct values on every 8 consecutive rows of a 16-row group and on its
+// even and on its odd rows.  A row's granules, and one granule across 8 or 16 rows
+// of a group, thus fall into distinct LDS banks with 128-byte and with 256-byte
+// bank spans.  f depends on t mod 16 only, so the slots of row 16 grp + n are those
+// of row n plus 128 grp: one address register serves all four column groups.
 // Granules 0..3 hold the real parts of a 16-point pencil, 4..7 the imaginary ones.
-__device__ __forceinline__ int stg_q(int t, int G) { return 8 * t + (G ^ ((t ^ (t >> 3)) & 7)); }
+__device__ __forceinline__ int stg_q(int t, int G) {
+  const int n = t & 15;
+  return 8 * t + (G ^ ((n ^ (n >> 3)) & 7));
+}
 
 // y[0..15] of every thread of the wavefront <- its 16-point DFT (sign S).
 // `stg` is a wave-private, 16-byte aligned LDS area of 64 * 32 floats; all 64
@@ -503,19 +516,34 @@ struct CtSched {
   int p[kMaxStages];
 };
 
-// The host's radix order for a power-of-two length L: the largest power-of-two
-// radix dividing E, repeated, the remainder by the next smaller ones.
+// The host's radix order for a length L: the largest power-of-two radix
+// dividing E, repeated, the rest of the power of two by the next smaller ones,
+// then the odd factors (every 7, every 5, every 3).
 constexpr CtSched ct_sched(int L, int E) {
   CtSched s{0, {0, 0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0, 0, 0}};
+  int n = L, nodd = 0;
+  int odd[kMaxStages] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int r : {7, 5, 3})
+    while (n % r == 0 && nodd < kMaxStages) {
+      n /= r;
+      odd[nodd++] = r;
+    }
   const int big = E % 16 == 0 ? 16 : E % 8 == 0 ? 8 : E % 4 == 0 ? 4 : E % 2 == 0 ? 2 : 1;
-  int n = L, p = 1;
+  int p = 1;
   while (n > 1 && big > 1 && s.ns < kMaxStages) {
     int r = big;
     while (r > 1 && n % r) r /= 2;
+    if (r == 1) break;
     s.r[s.ns] = r;
     s.p[s.ns] = p;
     p *= r;
     n /= r;
+    ++s.ns;
+  }
+  for (int q = 0; q < nodd && s.ns < kMaxStages; ++q) {
+    s.r[s.ns] = odd[q];
+    s.p[s.ns] = p;
+    p *= odd[q];
     ++s.ns;
   }
   return s;
@@ -528,7 +556,7 @@ __device__ __forceinline__ void stage_ct(float2 (&v)[E], int i, const float2* __
 #pragma unroll
   for (int q = 0; q < V; ++q) {
     const int b = i + q * P;
-    const int k = LAST ? b : (b & (p - 1));
+    const int k = LAST ? b : (int)((unsigned)b % (unsigned)p);
     float2 y[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) y[j] = v[q + j * V];
@@ -580,6 +608,65 @@ __device__ __forceinline__ void fft_row(float2 (&v)[E], const Sched& sc, int i, 
   else fft<E, S, true, kXPad, PREC>(v, sc, i, P, tw, row, 1, 0, stg);
 }
 
+// Compile-time schedule of a work-group pencil (power-of-two length L, LDS
+// element n of this thread's pencil at lds[n * ls + lo]): the stages of fft()
+// with radix, span and twiddle stride folded into constants.  PREC > 0 runs
+// the 16-point stages on MFMA (dft16_mfma); its staging areas lie inside the
+// exchange buffer, so a work-group barrier separates them from the stage's
+// output writes.
+template <int E, int R, int S, int P, int p, int TM, bool LAST, int PREC>
+__device__ __forceinline__ void stage_ctp(float2 (&v)[E], int i, const float2* __restrict__ tw,
+                                          float2* lds, int ls, int lo, float* stg) {
+  constexpr int V = E / R;
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const int b = i + q * P;
+    const int k = LAST ? b : (int)((unsigned)b % (unsigned)p);
+    float2 y[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) y[j] = v[q + j * V];
+    if constexpr (p > 1) {
+#pragma unroll
+      for (int j = 1; j < R; ++j) {
+        const float2 w = tw[j * k * TM];
+        y[j] = (S < 0) ? cmul(y[j], w) : cmulc(y[j], w);
+      }
+    }
+    if constexpr (PREC > 0 && R == 16 && E == 16) {
+      dft16_mfma<PREC, S>(y, stg);
+      if constexpr (!LAST) __syncthreads();  // every staging area is free
+    } else {
+      Dft<R, S>::run(y);
+    }
+    if constexpr (LAST) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) v[q + j * V] = y[j];
+    } else {
+      const int base = (b - k) * R + k;
+#pragma unroll
+      for (int j = 0; j < R; ++j) lds[(base + j * p) * ls + lo] = y[j];
+    }
+  }
+}
+
+template <int E, int S, int L, int PREC, int ST = 0>
+__device__ __forceinline__ void fft_ctp(float2 (&v)[E], int i, const float2* __restrict__ tw,
+                                        float2* lds, int ls, int lo, float* stg) {
+  constexpr CtSched cs = ct_sched(L, E);
+  if constexpr (ST < cs.ns) {
+    constexpr int P = L / E, R = cs.r[ST], p = cs.p[ST];
+    constexpr bool last = ST == cs.ns - 1;
+    stage_ctp<E, R, S, P, p, L / (p * R), last, PREC>(v, i, tw, lds, ls, lo, stg);
+    if constexpr (!last) {
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = lds[(i + P * m) * ls + lo];
+      __syncthreads();
+      fft_ctp<E, S, L, PREC, ST + 1>(v, i, tw, lds, ls, lo, stg);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Y / Z pencil pass
 // ---------------------------------------------------------------------------
@@ -593,12 +680,14 @@ __device__ __forceinline__ void fft_row(float2 (&v)[E], const Sched& sc, int i, 
 // would spill.
 // One work-group tile of a pencil pass: (gx, gy) is the tile's position in the
 // pass's launch grid, vz the volume (all threads of the work-group call it).
-template <int E, int MODE, int PREC = 0>
+// CL > 0: the pencil length is CL (compile-time schedule).
+template <int E, int MODE, int PREC = 0, int CL = 0>
 __device__ __forceinline__ void pencil_tile(float2* __restrict__ data,
                                             const float2* __restrict__ otf,
                                             const float2* __restrict__ twg, const PencilArgs& a,
                                             const Sched& sc, int gx, int gy, int vz, float2* lds) {
   const int tid = threadIdx.x;
+  const int P = CL > 0 ? CL / E : a.P;
   // twiddle table (L entries) after the exchange buffer
   float2* tw = lds + (size_t)a.L * a.TXP;
   for (int t = tid; t < a.L; t += blockDim.x) tw[t] = twg[t];
@@ -616,26 +705,41 @@ __device__ __forceinline__ void pencil_tile(float2* __restrict__ data,
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m)
-    v[m] = (ok && i + a.P * m < a.lin) ? data[base + (long long)(i + a.P * m) * a.estride]
+    v[m] = (ok && i + P * m < a.lin) ? data[base + (long long)(i + P * m) * a.estride]
                                         : make_float2(0.f, 0.f);
   __syncthreads();  // twiddles in LDS
 
   // split-precision stages stage their operands in this wave's slice of the exchange buffer
   float* stg = reinterpret_cast<float*>(lds) + (tid >> 6) * (64 * 32);
-  if constexpr (MODE != PM_INV) fft<E, -1, false, 0, PREC>(v, sc, i, a.P, tw, lds, a.TXP, lane, stg);
+  if constexpr (MODE != PM_INV) {
+    if constexpr (CL > 0) fft_ctp<E, -1, CL, PREC>(v, i, tw, lds, a.TXP, lane, stg);
+    else fft<E, -1, false, 0, PREC>(v, sc, i, P, tw, lds, a.TXP, lane, stg);
+  }
   if constexpr (MODE == PM_FKI || MODE == PM_FCKI) {
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const float2 k = ok ? otf[base + (long long)(i + a.P * m) * a.estride] : make_float2(0.f, 0.f);
+      const float2 k = ok ? otf[base + (long long)(i + P * m) * a.estride] : make_float2(0.f, 0.f);
       v[m] = (MODE == PM_FKI) ? cmul(v[m], k) : cmulc(v[m], k);
     }
   }
-  if constexpr (MODE != PM_FWD) fft<E, +1, false, 0, PREC>(v, sc, i, a.P, tw, lds, a.TXP, lane, stg);
+  if constexpr (MODE != PM_FWD) {
+    if constexpr (CL > 0) {
+      // with both transforms in one kernel, fresh copies of the index operands keep
+      // the inverse's LDS addresses from being merged with the forward's (which
+      // would hold every one of them in a register through both transforms)
+      int ls = a.TXP;
+      if constexpr (MODE != PM_INV) asm volatile("" : "+s"(ls));
+      fft_ctp<E, +1, CL, PREC>(v, MODE != PM_INV ? opaque_int(i) : i, tw, lds, ls,
+                               MODE != PM_INV ? opaque_int(lane) : lane, stg);
+    } else {
+      fft<E, +1, false, 0, PREC>(v, sc, i, P, tw, lds, a.TXP, lane, stg);
+    }
+  }
 
   if (ok) {
 #pragma unroll
     for (int m = 0; m < E; ++m)
-      if (i + a.P * m < a.lout) data[base + (long long)(i + a.P * m) * a.estride] = v[m];
+      if (i + P * m < a.lout) data[base + (long long)(i + P * m) * a.estride] = v[m];
   }
 }
 
@@ -646,6 +750,17 @@ __global__ void __launch_bounds__(MAXT, (MAXT == 1024 && E == 8 && MODE <= PM_IN
   if (a.stop && *a.stop) return;  // stopped: the whole work-group leaves together
   extern __shared__ __attribute__((aligned(16))) float2 lds[];
   pencil_tile<E, MODE, PREC>(data, otf, twg, a, sc, blockIdx.x, blockIdx.y, blockIdx.z, lds);
+}
+
+// Pencils of compile-time length L (pencil_compiled_len).
+template <int E, int MODE, int PREC, int L>
+__global__ void __launch_bounds__(pencil_ct_max_threads(E, L))
+    k_pencil_ct(float2* __restrict__ data, const float2* __restrict__ otf,
+                const float2* __restrict__ twg, PencilArgs a) {
+  if (a.stop && *a.stop) return;  // stopped: the whole work-group leaves together
+  extern __shared__ __attribute__((aligned(16))) float2 lds[];
+  pencil_tile<E, MODE, PREC, L>(data, otf, twg, a, Sched{}, blockIdx.x, blockIdx.y, blockIdx.z,
+                                lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -886,7 +1001,7 @@ __device__ __forceinline__ void xrow_tile(const XArgs& a, const Sched& sc,
         v[m] = make_float2(q.x > 1e-12f ? w[m].x / q.x : 0.f, q.y > 1e-12f ? w[m].y / q.y : 0.f);
       }
       wave_sync();  // row buffer reuse
-      r2c_store<E, PREC, CM>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
+      r2c_store<E, PREC, CM>(v, M, P, sc, CM > 0 ? opaque_int(i) : i, tw, row, ok, srow, ts, stg);
       if constexpr (want_ll) {
         double r[1] = {(double)ll};
         constexpr int ops[1] = {0};
@@ -979,7 +1094,8 @@ __device__ __forceinline__ void xrow_tile(const XArgs& a, const Sched& sc,
       }
       if (a.do_fwd) {
         wave_sync();
-        r2c_store<E, PREC, CM>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
+        r2c_store<E, PREC, CM>(v, M, P, sc, CM > 0 ? opaque_int(i) : i, tw, row, ok, srow, ts,
+                               stg);
       }
       // work-group partial of the flux: wavefront butterfly, then the waves in order
 #pragma unroll
@@ -1561,6 +1677,38 @@ static hipError_t pencil_one(dim3 g, dim3 b, size_t lds, hipStream_t s, float2* 
   return hipGetLastError();
 }
 
+template <int MODE, int E, int L, int PREC>
+static hipError_t pencil_ct_one(dim3 g, dim3 b, size_t lds, hipStream_t s, float2* data,
+                                const float2* otf, const float2* tw, const PencilArgs& a,
+                                bool launch, hipEvent_t ev0, hipEvent_t ev1) {
+  if (lds > 65536 - (PREC > 0 ? kSplitTabBytes : 0)) {
+    static bool attr_done = false;  // once per instantiation
+    if (!attr_done) {
+      hipError_t e =
+          hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pencil_ct<E, MODE, PREC, L>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              163840 - (PREC > 0 ? kSplitTabBytes : 0));
+      if (e != hipSuccess) return e;
+      attr_done = true;
+    }
+  }
+  if (!launch) return hipSuccess;
+  RL_LAUNCH((k_pencil_ct<E, MODE, PREC, L>), g, b, lds, s, ev0, ev1, data, otf, tw, a);
+  return hipGetLastError();
+}
+
+template <int MODE, int L>
+static hipError_t pencil_ct_prec(int prec, dim3 g, dim3 b, size_t lds, hipStream_t s,
+                                 float2* data, const float2* otf, const float2* tw,
+                                 const PencilArgs& a, bool launch, hipEvent_t ev0, hipEvent_t ev1) {
+  switch (prec) {
+    case 0: return pencil_ct_one<MODE, 16, L, 0>(g, b, lds, s, data, otf, tw, a, launch, ev0, ev1);
+    case 1: return pencil_ct_one<MODE, 16, L, 1>(g, b, lds, s, data, otf, tw, a, launch, ev0, ev1);
+    case 2: return pencil_ct_one<MODE, 16, L, 2>(g, b, lds, s, data, otf, tw, a, launch, ev0, ev1);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int MODE>
 static hipError_t pencil_e(int E, int prec, dim3 g, dim3 b, size_t lds, hipStream_t s,
                            float2* data, const float2* otf, const float2* tw, const PencilArgs& a,
@@ -1570,6 +1718,16 @@ static hipError_t pencil_e(int E, int prec, dim3 g, dim3 b, size_t lds, hipStrea
   if (b.x % 64 != 0) prec = 0;  // MFMA stages need whole wavefronts
   // split-precision work-groups have at most 512 threads (their register budget)
   if (E == 16 && prec > 0 && b.x > 512) return hipErrorInvalidValue;
+  if (pencil_compiled_len(E, a.L, (int)b.x) > 0 && a.P * E == a.L) {
+    if (E == 30)  // the 2160-point pencils: no 16-point stages, FP32 arithmetic
+      return pencil_ct_one<MODE, 30, 2160, 0>(g, b, lds, s, data, otf, tw, a, launch, ev0, ev1);
+    switch (a.L) {
+      case 128: return pencil_ct_prec<MODE, 128>(prec, g, b, lds, s, data, otf, tw, a, launch, ev0, ev1);
+      case 256: return pencil_ct_prec<MODE, 256>(prec, g, b, lds, s, data, otf, tw, a, launch, ev0, ev1);
+      case 512: return pencil_ct_prec<MODE, 512>(prec, g, b, lds, s, data, otf, tw, a, launch, ev0, ev1);
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (E == 16 && prec == 1)
     return pencil_one<MODE, 512, 16, 1>(g, b, lds, s, data, otf, tw, a, sc, launch, ev0, ev1);
   if (E == 16 && prec == 2)
@@ -1593,8 +1751,10 @@ static hipError_t pencil_e(int E, int prec, dim3 g, dim3 b, size_t lds, hipStrea
   }
 }
 
-hipError_t prepare_pencil(int mode, int E, int prec, dim3 block, size_t lds) {
-  const PencilArgs a{};
+hipError_t prepare_pencil(int mode, int E, int L, int prec, dim3 block, size_t lds) {
+  PencilArgs a{};
+  a.L = L;
+  a.P = E > 0 ? L / E : 0;
   const Sched sc{};
   const dim3 g(1);
   switch (mode) {
@@ -1631,12 +1791,12 @@ static bool xrow_ct(int M, dim3 g, dim3 b, size_t lds, hipStream_t s, const XArg
   switch (M) {
 #define RL_CM(MV)                                                                \
   case MV:                                                                       \
-    if constexpr (MV / E <= 64) {                                                \
+    if constexpr (MV % E == 0 && MV / E <= 64) {                                 \
       RL_LAUNCH((k_xrow<E, MODE, 0, MV>), g, b, lds, s, ev0, ev1, a, sc, tw);    \
       return true;                                                               \
     }                                                                            \
     return false;
-    RL_CM(64) RL_CM(128) RL_CM(256) RL_CM(512)
+    RL_CM(64) RL_CM(128) RL_CM(256) RL_CM(512) RL_CM(1280)
 #undef RL_CM
     default:
       return false;
@@ -1649,8 +1809,9 @@ static hipError_t xrow_e(int E, int prec, dim3 g, dim3 b, size_t lds, hipStream_
                          hipEvent_t ev1) {
   if constexpr (MODE == XM_RATIO || MODE == XM_UPDATE) {
     if (xrow_compiled_len(MODE, E, a.M, E == 16 ? prec : 0) > 0) {  // PREC of the instance
-      const bool ok = E == 4 ? xrow_ct<MODE, 4>(a.M, g, b, lds, s, a, sc, tw, ev0, ev1)
-                             : xrow_ct<MODE, 8>(a.M, g, b, lds, s, a, sc, tw, ev0, ev1);
+      const bool ok = E == 4    ? xrow_ct<MODE, 4>(a.M, g, b, lds, s, a, sc, tw, ev0, ev1)
+                      : E == 8  ? xrow_ct<MODE, 8>(a.M, g, b, lds, s, a, sc, tw, ev0, ev1)
+                                : xrow_ct<MODE, 20>(a.M, g, b, lds, s, a, sc, tw, ev0, ev1);
       return ok ? hipGetLastError() : hipErrorInvalidValue;
     }
   }
