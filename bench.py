@@ -404,9 +404,20 @@ def run_batched(torch, rl, synth, steps: int, warmup: int, count: int = 96, n_it
     classes = {}
     for v in vols:
         classes[str(v["shape"])] = classes.get(str(v["shape"]), 0) + 1
+    # algorithmic bytes of one iteration of every volume (the pass model of the
+    # single-volume plans), over the whole step
+    it_bytes = 0
+    for v in vols:
+        kb = kernel_bytes(v["shape"])
+        it_bytes += kb["x_ratio"] + kb["x_update"] + 4 * kb["y"] + 2 * kb["z_otf"]
+    value = nvox * n_iter / (out["batched"] * 1e-3) / 1e9
+    bpvi = it_bytes / nvox
     return {"workload": f"rl_fp32_batch{count}_uneven_{n_iter}it", "volumes": count,
             "voxels": nvox, "shape_classes": classes,
-            "value": round(nvox * n_iter / (out["batched"] * 1e-3) / 1e9, 3),
+            "value": round(value, 3),
+            "bytes_per_vi": round(bpvi, 2),
+            "model_effective_gbs": round(bpvi * value, 1),
+            "model_frac": round(bpvi * value / PEAK_HBM_GBS, 4),
             "unit": "Gvoxel-iter/s", "ms_per_step": round(out["batched"], 3), "mode": mode,
             "plain_one_plan_per_volume_ms": round(out["plain"], 3),
             "speedup_vs_plain": round(out["plain"] / out["batched"], 3), "flux_drift": drift,
@@ -458,8 +469,13 @@ def run_split(torch, rl, synth, steps: int, cfg: int = 2):
         plan.close()
         if prec == "fp32":
             ref = {10: u10.double(), 50: u50.double()}
-        entry = {"ms_per_step": round(ms, 3),
-                 "value": round(nvox * n_iter / (ms * 1e-3) / 1e9, 3)}
+        value = nvox * n_iter / (ms * 1e-3) / 1e9
+        kb = kernel_bytes(c["shape"])
+        bpvi = (kb["x_ratio"] + kb["x_update"] + 4 * kb["y"] + 2 * kb["z_otf"]) / nvox
+        # the split forms keep every array in FP32 in HBM: the same bytes per iteration
+        entry = {"ms_per_step": round(ms, 3), "value": round(value, 3),
+                 "model_effective_gbs": round(bpvi * value, 1),
+                 "model_frac": round(bpvi * value / PEAK_HBM_GBS, 4)}
         if prec != "fp32":
             for k, uu in ((10, u10), (50, u50)):
                 entry[f"rel_l2_vs_fp32_at_{k}"] = float(

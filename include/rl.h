@@ -424,8 +424,10 @@ rl_status rl_plan_time_pass(rl_plan p, int kind, const float* observed, float* e
  * RL_KERNEL_X_UPDATE, RL_KERNEL_Y or RL_KERNEL_Z_OTF into name[0 .. cap-1]
  * (NUL-terminated; two names joined by '|' where the pass has a forward and an
  * inverse, or a plain and a conjugate, variant, e.g.
- * "k_pencil<8, 0, 1024, 0>|k_pencil<8, 1, 1024, 0>") and the number of threads
- * one launch runs (work-groups times work-group size) into *threads.
+ * "k_pencil<8, 0, 1024, 0>|k_pencil<8, 1, 1024, 0>"; pencils compiled for their
+ * length are named k_pencil_ct<E, mode, precision, length>, X rows compiled for
+ * theirs carry the row length as the last argument of k_xrow) and the number of
+ * threads one launch runs (work-groups times work-group size) into *threads.
  * RL_E_INVALID if cap is too small.  Single-volume plans only.
  */
 rl_status rl_plan_get_pass_kernel(rl_plan p, int kind, char* name, size_t cap, int64_t* threads);
