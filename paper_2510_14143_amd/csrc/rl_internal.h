@@ -81,12 +81,13 @@ enum XMode {
 // Row length M the X-pass kernel of (mode, E, M, prec) is compiled for (0 = the
 // runtime schedule): the per-iteration ratio and update passes of power-of-two
 // rows M in {64, 128, 256, 512} with E in {4, 8} elements per thread and at most
-// 64 threads per row, and of the 2560-sample rows of the paper's stack (M = 1280
-// = 4^4 * 5, E = 20).
+// 64 threads per row, of the rows 3 * 2^a of the batched volumes (M in {24, 48,
+// 96}, E = 6), and of the 2560-sample rows of the paper's stack (M = 1280 =
+// 4^4 * 5, E = 20).
 constexpr int xrow_compiled_len(int mode, int E, int M, int prec) {
   return ((mode == XM_RATIO || mode == XM_UPDATE) && prec == 0 &&
           (((E == 4 || E == 8) && (M == 64 || M == 128 || M == 256 || M == 512) && M / E <= 64) ||
-           (E == 20 && M == 1280)))
+           (E == 6 && (M == 24 || M == 48 || M == 96)) || (E == 20 && M == 1280)))
              ? M
              : 0;
 }
@@ -100,9 +101,13 @@ constexpr int pencil_ct_max_threads(int E, int L) {
 // Length L the pencil kernel of (E, L, work-group threads) is compiled for (0 =
 // the runtime schedule): power-of-two pencils L in {128, 256, 512} with 16
 // elements per thread, in every precision (the split-precision forms run their
-// 16-point MFMA stages there), and the 2160-point pencils with 30.
+// 16-point MFMA stages there); the pencils 3 * 2^a of the batched volumes (L in
+// {24, 48, 96} with 6 elements, L in {48, 96, 192} with 12); and the 2160-point
+// pencils with 30.
 constexpr int pencil_compiled_len(int E, int L, int threads) {
-  return ((E == 16 && (L == 128 || L == 256 || L == 512)) || (E == 30 && L == 2160)) &&
+  return ((E == 16 && (L == 128 || L == 256 || L == 512)) ||
+          (E == 6 && (L == 24 || L == 48 || L == 96)) ||
+          (E == 12 && (L == 48 || L == 96 || L == 192)) || (E == 30 && L == 2160)) &&
                  threads <= pencil_ct_max_threads(E, L)
              ? L
              : 0;

@@ -1719,8 +1719,13 @@ static hipError_t pencil_e(int E, int prec, dim3 g, dim3 b, size_t lds, hipStrea
   // split-precision work-groups have at most 512 threads (their register budget)
   if (E == 16 && prec > 0 && b.x > 512) return hipErrorInvalidValue;
   if (pencil_compiled_len(E, a.L, (int)b.x) > 0 && a.P * E == a.L) {
-    if (E == 30)  // the 2160-point pencils: no 16-point stages, FP32 arithmetic
-      return pencil_ct_one<MODE, 30, 2160, 0>(g, b, lds, s, data, otf, tw, a, launch, ev0, ev1);
+    // lengths without 16-point stages: FP32 arithmetic in every precision
+#define RL_PCT(EV, LV)                                                                  \
+    if (E == EV && a.L == LV)                                                           \
+      return pencil_ct_one<MODE, EV, LV, 0>(g, b, lds, s, data, otf, tw, a, launch, ev0, ev1);
+    RL_PCT(30, 2160) RL_PCT(6, 24) RL_PCT(6, 48) RL_PCT(6, 96) RL_PCT(12, 48) RL_PCT(12, 96)
+    RL_PCT(12, 192)
+#undef RL_PCT
     switch (a.L) {
       case 128: return pencil_ct_prec<MODE, 128>(prec, g, b, lds, s, data, otf, tw, a, launch, ev0, ev1);
       case 256: return pencil_ct_prec<MODE, 256>(prec, g, b, lds, s, data, otf, tw, a, launch, ev0, ev1);
@@ -1791,12 +1796,12 @@ static bool xrow_ct(int M, dim3 g, dim3 b, size_t lds, hipStream_t s, const XArg
   switch (M) {
 #define RL_CM(MV)                                                                \
   case MV:                                                                       \
-    if constexpr (MV % E == 0 && MV / E <= 64) {                                 \
+    if constexpr (xrow_compiled_len(MODE, E, MV, 0) == MV) {                     \
       RL_LAUNCH((k_xrow<E, MODE, 0, MV>), g, b, lds, s, ev0, ev1, a, sc, tw);    \
       return true;                                                               \
     }                                                                            \
     return false;
-    RL_CM(64) RL_CM(128) RL_CM(256) RL_CM(512) RL_CM(1280)
+    RL_CM(24) RL_CM(48) RL_CM(96) RL_CM(64) RL_CM(128) RL_CM(256) RL_CM(512) RL_CM(1280)
 #undef RL_CM
     default:
       return false;
@@ -1810,6 +1815,7 @@ static hipError_t xrow_e(int E, int prec, dim3 g, dim3 b, size_t lds, hipStream_
   if constexpr (MODE == XM_RATIO || MODE == XM_UPDATE) {
     if (xrow_compiled_len(MODE, E, a.M, E == 16 ? prec : 0) > 0) {  // PREC of the instance
       const bool ok = E == 4    ? xrow_ct<MODE, 4>(a.M, g, b, lds, s, a, sc, tw, ev0, ev1)
+                      : E == 6  ? xrow_ct<MODE, 6>(a.M, g, b, lds, s, a, sc, tw, ev0, ev1)
                       : E == 8  ? xrow_ct<MODE, 8>(a.M, g, b, lds, s, a, sc, tw, ev0, ev1)
                                 : xrow_ct<MODE, 20>(a.M, g, b, lds, s, a, sc, tw, ev0, ev1);
       return ok ? hipGetLastError() : hipErrorInvalidValue;

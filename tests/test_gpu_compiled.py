@@ -4,6 +4,9 @@ its pass):
 
 * pencils of 128, 256 and 512 points with 16 elements per thread (FP32 and both
   split precisions),
+* the 3 * 2^a pencils and X rows of the batched volumes (pencils of 24, 48 and
+  96 points with 6 elements, of 48, 96 and 192 with 12; rows of 24, 48 and 96
+  points with 6),
 * the 2160-point pencils of the paper's stack (30 elements per thread),
 * the fused X passes of 1280-point rows (nx = 2560, 20 elements per thread).
 
@@ -83,6 +86,44 @@ def test_compiled_pencils(torch, precision, shape, ly, lz):
     c = synth.small_case(shape, seed=502, density=4.0)
     with rl.Plan(dev(torch, c["psf"]), yz_elems=16, precision=precision) as p:
         check_rl(torch, p, c, 5, RL_TOL[precision])
+
+
+# (shape, elements per thread on Y and Z, Y length, Z length)
+BATCH_PENCIL_CASES = [((24, 48, 16), 6, 48, 24), ((48, 96, 16), 6, 96, 48),
+                      ((48, 96, 16), 12, 96, 48), ((96, 192, 16), 12, 192, 96)]
+
+
+@pytest.mark.parametrize("shape,e,ly,lz", BATCH_PENCIL_CASES)
+def test_compiled_batch_pencils(torch, shape, e, ly, lz):
+    say("compiled pencils", shape, e)
+    x = synth.uniform_volume(shape, 530)
+    psf = rand_psf(shape, 531)
+    with rl.Plan(dev(torch, psf), yz_elems=e) as p:
+        ny, _ = p.pass_kernel("y")
+        nz, _ = p.pass_kernel("z_otf")
+        say("  kernels", ny, nz)
+        assert ny == [f"k_pencil_ct<{e}, 0, 0, {ly}>", f"k_pencil_ct<{e}, 1, 0, {ly}>"]
+        assert nz == [f"k_pencil_ct<{e}, 2, 0, {lz}>", f"k_pencil_ct<{e}, 3, 0, {lz}>"]
+        got = p.conv(dev(torch, x)).cpu().numpy()
+    err = oracle.rel_l2(got, oracle.conv3d(x, psf))
+    say("  conv relL2", err)
+    assert err <= CONV_TOL["fp32"]
+    c = synth.small_case(shape, seed=532, density=4.0)
+    with rl.Plan(dev(torch, c["psf"]), yz_elems=e) as p:
+        check_rl(torch, p, c, 5, RL_TOL["fp32"])
+
+
+@pytest.mark.parametrize("nx", [48, 96, 192])
+def test_compiled_batch_rows(torch, nx):
+    shape = (6, 8, nx)
+    say("compiled rows", shape)
+    c = synth.small_case(shape, seed=540 + nx, density=16.0)
+    with rl.Plan(dev(torch, c["psf"]), x_elems=6) as p:
+        r, _ = p.pass_kernel("x_ratio")
+        u, _ = p.pass_kernel("x_update")
+        say("  kernels", r, u)
+        assert r == [f"k_xrow<6, 2, 0, {nx // 2}>"] and u == [f"k_xrow<6, 3, 0, {nx // 2}>"]
+        check_rl(torch, p, c, 5, RL_TOL["fp32"])
 
 
 def test_compiled_2160_point_pencils(torch):
