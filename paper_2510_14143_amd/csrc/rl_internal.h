@@ -95,17 +95,18 @@ constexpr int xrow_compiled_len(int mode, int E, int M, int prec) {
 // Thread bound of the compile-time pencil kernel of (E, L): the 2160-point pencils
 // of the paper's stack (E = 30, 72 threads per pencil) run 8 lanes, 576 threads.
 constexpr int pencil_ct_max_threads(int E, int L) {
-  return (E == 30 && L == 2160) ? 576 : kPencilMaxThreads;
+  return (E == 30 && L == 2160) ? 576 : E == 8 ? 1024 : kPencilMaxThreads;
 }
 
 // Length L the pencil kernel of (E, L, work-group threads) is compiled for (0 =
 // the runtime schedule): power-of-two pencils L in {128, 256, 512} with 16
 // elements per thread, in every precision (the split-precision forms run their
-// 16-point MFMA stages there); the pencils 3 * 2^a of the batched volumes (L in
-// {24, 48, 96} with 6 elements, L in {48, 96, 192} with 12); and the 2160-point
-// pencils with 30.
+// 16-point MFMA stages there), and L in {32, ..., 512} with 8 (work-groups up to
+// 1024 threads); the pencils 3 * 2^a of the batched volumes (L in {24, 48, 96}
+// with 6 elements, L in {48, 96, 192} with 12); and the 2160-point pencils with 30.
 constexpr int pencil_compiled_len(int E, int L, int threads) {
   return ((E == 16 && (L == 128 || L == 256 || L == 512)) ||
+          (E == 8 && (L == 32 || L == 64 || L == 128 || L == 256 || L == 512)) ||
           (E == 6 && (L == 24 || L == 48 || L == 96)) ||
           (E == 12 && (L == 48 || L == 96 || L == 192)) || (E == 30 && L == 2160)) &&
                  threads <= pencil_ct_max_threads(E, L)

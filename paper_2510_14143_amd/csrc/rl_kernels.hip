@@ -752,9 +752,11 @@ __global__ void __launch_bounds__(MAXT, (MAXT == 1024 && E == 8 && MODE <= PM_IN
   pencil_tile<E, MODE, PREC>(data, otf, twg, a, sc, blockIdx.x, blockIdx.y, blockIdx.z, lds);
 }
 
-// Pencils of compile-time length L (pencil_compiled_len).
+// Pencils of compile-time length L (pencil_compiled_len).  The forward and inverse
+// passes with 8 elements per thread are held to 64 registers, so that two
+// 1024-thread work-groups share a CU (as for the runtime-schedule kernel).
 template <int E, int MODE, int PREC, int L>
-__global__ void __launch_bounds__(pencil_ct_max_threads(E, L))
+__global__ void __launch_bounds__(pencil_ct_max_threads(E, L), (E == 8 && MODE <= PM_INV) ? 8 : 1)
     k_pencil_ct(float2* __restrict__ data, const float2* __restrict__ otf,
                 const float2* __restrict__ twg, PencilArgs a) {
   if (a.stop && *a.stop) return;  // stopped: the whole work-group leaves together
@@ -1724,7 +1726,7 @@ static hipError_t pencil_e(int E, int prec, dim3 g, dim3 b, size_t lds, hipStrea
     if (E == EV && a.L == LV)                                                           \
       return pencil_ct_one<MODE, EV, LV, 0>(g, b, lds, s, data, otf, tw, a, launch, ev0, ev1);
     RL_PCT(30, 2160) RL_PCT(6, 24) RL_PCT(6, 48) RL_PCT(6, 96) RL_PCT(12, 48) RL_PCT(12, 96)
-    RL_PCT(12, 192)
+    RL_PCT(12, 192) RL_PCT(8, 32) RL_PCT(8, 64) RL_PCT(8, 128) RL_PCT(8, 256) RL_PCT(8, 512)
 #undef RL_PCT
     switch (a.L) {
       case 128: return pencil_ct_prec<MODE, 128>(prec, g, b, lds, s, data, otf, tw, a, launch, ev0, ev1);

@@ -4,6 +4,8 @@ its pass):
 
 * pencils of 128, 256 and 512 points with 16 elements per thread (FP32 and both
   split precisions),
+* pencils of 32 ... 512 points with 8 elements per thread (up to 1024-thread
+  work-groups),
 * the 3 * 2^a pencils and X rows of the batched volumes (pencils of 24, 48 and
   96 points with 6 elements, of 48, 96 and 192 with 12; rows of 24, 48 and 96
   points with 6),
@@ -90,7 +92,9 @@ def test_compiled_pencils(torch, precision, shape, ly, lz):
 
 # (shape, elements per thread on Y and Z, Y length, Z length)
 BATCH_PENCIL_CASES = [((24, 48, 16), 6, 48, 24), ((48, 96, 16), 6, 96, 48),
-                      ((48, 96, 16), 12, 96, 48), ((96, 192, 16), 12, 192, 96)]
+                      ((48, 96, 16), 12, 96, 48), ((96, 192, 16), 12, 192, 96),
+                      ((64, 128, 16), 8, 128, 64), ((32, 512, 16), 8, 512, 32),
+                      ((256, 256, 8), 8, 256, 256)]
 
 
 @pytest.mark.parametrize("shape,e,ly,lz", BATCH_PENCIL_CASES)
