@@ -22,14 +22,23 @@
  *     shape given as {nz, ny, nx}.
  *   - Every data pointer is a DEVICE pointer on the plan's GPU, owned by the
  *     caller, at least 16-byte aligned, covering nz*ny*nx floats.
- *   - Transform lengths: o * 2^a with o in {1, 3, 5, 7, 9, 15}.  nx must be
- *     even with nx/2 such a length (4 <= nx <= 2048, and 2560 or 3072); ny and
- *     nz such lengths <= 1024.  A transform of length L splits over a
- *     power-of-two number of threads (at most 64 for nx/2, 1024 for ny, nz),
- *     each holding E in {1..10, 12, 14, 15, 16, 18, 20, 24, 30} elements that
- *     carry every odd factor of L, in at most 8 radix stages (16, 8, 4, 2, then
- *     7, 5, 3).  Other lengths return RL_E_UNSUPPORTED (for the zero boundary
- *     the rule applies to the padded transform grid).
+ *   - Transform lengths.  nx must be even, 4 <= nx <= 4096, with nx/2 =
+ *     o * 2^a, o in {1, 3, 5, 7, 9, 15}, split over a power-of-two number of
+ *     threads <= 64, each holding E in {1..10, 12, 14, 15, 16, 18, 20, 24, 30}
+ *     elements that carry every odd factor of nx/2 (e.g. nx = 2560).  ny and nz
+ *     are 2^a 3^b 5^c 7^d <= 4096: where an E carries the whole odd part the
+ *     rule is the same (threads <= 1024), else E needs each odd prime once and
+ *     the thread count carries the rest (e.g. 2160 = 16 * 135 as 30 elements on
+ *     72 threads).  At most 8 radix stages (16, 8, 4, 2, then 7, 5, 3), and a
+ *     pencil's work-group must fit the LDS (length x lanes x 8 bytes <= 160 KB).
+ *     Other lengths return RL_E_UNSUPPORTED (for the zero boundary the rule
+ *     applies to the padded transform grid).
+ *   - Environment: RLMI_TUNE_CACHE (see rl_options.autotune); RLMI_AUTOTUNE=1
+ *     or 0 turns the autotuner on or off for every plan whatever its options
+ *     say; RLMI_SYNC_DEBUG=1 synchronises the plan's stream after every kernel
+ *     launch (outside graph capture) and reports an execution fault as
+ *     RL_E_DEVICE against the launch that caused it (slow; for debugging).
+ *     Each is read once per process.
  *   - All argument checks run before any device work; a failing call leaves
  *     every buffer untouched.  No call aborts, exits or throws.
  *   - Work is enqueued on the plan's stream (default: the null stream) and

@@ -72,6 +72,42 @@ rl_status hip_fail(hipError_t e, const char* what) {
   return fail(RL_E_DEVICE, std::string(what) + ": " + (name ? name : "?"));
 }
 
+bool sync_debug_on();
+
+// Result of a kernel launch on `stream`; with RLMI_SYNC_DEBUG=1 (and the stream
+// not under graph capture) the stream is synchronised and an execution fault is
+// reported against this launch.
+rl_status launched(hipError_t e, hipStream_t stream, const char* what) {
+  if (e != hipSuccess) return hip_fail(e, (std::string(what) + " launch").c_str());
+  if (!sync_debug_on()) return RL_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+    return RL_OK;
+  if ((e = hipStreamSynchronize(stream)) != hipSuccess)
+    return hip_fail(e, (std::string("execution of ") + what + " (RLMI_SYNC_DEBUG)").c_str());
+  return RL_OK;
+}
+
+// Environment switches, read once per process: RLMI_SYNC_DEBUG=1 synchronises the
+// plan's stream after every kernel launch outside graph capture and reports an
+// execution fault against the launch that caused it; RLMI_AUTOTUNE=1 / 0 turns
+// the autotuner on / off for every plan, whatever its options ask.
+int env_flag(const char* name) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return -1;
+  return std::strcmp(v, "0") == 0 ? 0 : 1;
+}
+
+bool sync_debug_on() {
+  static const bool on = env_flag("RLMI_SYNC_DEBUG") == 1;
+  return on;
+}
+
+int autotune_override() {
+  static const int v = env_flag("RLMI_AUTOTUNE");
+  return v;
+}
+
 bool is_pow2(int64_t v) { return v >= 1 && (v & (v - 1)) == 0; }
 
 // A thread holds E elements of its transform, E carrying every odd factor of the
@@ -619,8 +655,7 @@ rl_status run_pencil(rl_plan p, const Pencil& pc, int mode, float2* data, const 
   args.stop = p->active_stop;
   hipError_t e = rlmi::launch_pencil(mode, pc.ax.E, p->precision, grid, pc.block, pc.lds,
                                      p->stream, data, p->otf, tw, args, pc.ax.sc, ev0, ev1);
-  if (e != hipSuccess) return hip_fail(e, "pencil pass launch");
-  return RL_OK;
+  return launched(e, p->stream, "pencil pass");
 }
 
 // Grid rows the X passes cover: the planes of the caller's volume.
@@ -660,8 +695,7 @@ rl_status run_x(rl_plan p, int mode, const XArgs& a, int kind, int64_t rows = 0)
   grid.y = (unsigned)a.nvol;
   hipError_t e = rlmi::launch_xrow(mode, p->axx.E, p->precision, grid, p->x_block, p->x_lds,
                                    p->stream, a, p->axx.sc, p->tw_x, ev0, ev1);
-  if (e != hipSuccess) return hip_fail(e, "X pass launch");
-  return RL_OK;
+  return launched(e, p->stream, "X pass");
 }
 
 // spectrum (X-transformed) -> spectrum (X-transformed) of H x or H^T x:
@@ -1229,7 +1263,8 @@ rl_status build_class(const Geometry& geo, int count, const float* const* psfs, 
       return fail(RL_E_UNSUPPORTED, "shape has no launch shapes for the persistent kernel");
     }
   }
-  const bool want_tune = opt && opt->autotune;
+  const bool want_tune =
+      autotune_override() >= 0 ? autotune_override() == 1 : (opt && opt->autotune);
   if (!configure(p, choice)) {
     delete p;
     return fail(RL_E_UNSUPPORTED, "shape needs more LDS or threads than a work-group may use");
@@ -1488,7 +1523,7 @@ rl_status enqueue_flux_reduce(rl_plan p, int n_iter, hipStream_t stream,
   if (st == RL_OK) {
     hipError_t e = rlmi::launch_flux_reduce(partials ? partials : p->partials, (int)p->x_grid.x,
                                             n_iter * p->count, p->flux, stream, ev0, ev1);
-    st = (e == hipSuccess) ? RL_OK : hip_fail(e, "flux reduction launch");
+    st = launched(e, stream, "flux reduction");
   }
   p->stream = keep;
   return st;
@@ -1527,7 +1562,7 @@ rl_status enqueue_accel_iteration(rl_plan p, const float* d, float* u, int it, b
   if ((st = timed_begin(p, RL_KERNEL_OTHER, &slot, &ev0, &ev1)) != RL_OK) return st;
   hipError_t e = rlmi::launch_accel_alpha(p->acc_partials, (int)p->x_grid.x, it, p->alpha32,
                                           p->alpha64, p->stream, ev0, ev1);
-  if (e != hipSuccess) return hip_fail(e, "alpha reduction launch");
+  if ((st = launched(e, p->stream, "alpha reduction")) != RL_OK) return st;
   return last ? RL_OK : enqueue_accel_predict(p, u, it + 1);
 }
 
@@ -1667,7 +1702,7 @@ rl_status enqueue_ssim(rl_plan p, const float* u, const float* ref, bool want_ra
   hipError_t e = rlmi::launch_ssim(u, ref, (int)p->vz, (int)p->vy, (int)p->vx, p->ssim_a, p->ssim_b,
                                    p->ssim_range + 1, kSsimRangeBlocks, p->ssim_range,
                                    p->ssim_part, want_range, p->active_stop, p->stream);
-  return e == hipSuccess ? RL_OK : hip_fail(e, "SSIM launch");
+  return launched(e, p->stream, "SSIM");
 }
 
 rl_status ssim_impl(rl_plan p, const float* u, const float* ref, double* value) {
@@ -1751,7 +1786,7 @@ rl_status enqueue_fsc_stop(rl_plan p, const float* u, int nbins, double fthr, in
   rl_plan sub = p->fsc_sub;
   hipError_t e = rlmi::launch_split_diag(u, (int)p->nz, (int)p->ny, (int)p->nx, p->fsc_a,
                                          p->fsc_b, p->stream, p->active_stop);
-  if (e != hipSuccess) return hip_fail(e, "split launch");
+  if (rl_status ls = launched(e, p->stream, "split"); ls != RL_OK) return ls;
   sub->stream = p->stream;
   sub->active_stop = p->active_stop;
   rl_status st = enqueue_fsc(sub, p->fsc_a, p->fsc_b, nbins, fthr, lcm);
@@ -1937,7 +1972,7 @@ rl_status enqueue_fsc(rl_plan p, const float* a, const float* b, int nbins, doub
   hipError_t e = rlmi::launch_fsc(p->spec, p->spec2, (int)p->nz, (int)p->ny, (int)p->nx,
                                   (int)p->xt, nbins, (long long)lcm, threshold, p->fsc_part,
                                   p->fsc_out, p->stream, p->active_stop);
-  return e == hipSuccess ? RL_OK : hip_fail(e, "shell correlation launch");
+  return launched(e, p->stream, "shell correlation");
 }
 
 rl_status fsc_impl(rl_plan p, const float* a, const float* b, int nbins, double threshold,
@@ -2398,9 +2433,10 @@ rl_status iterate_batch_impl(rl_plan b, const float* const* observed, float* con
       return hip_fail(e, "prologue join");
   }
   for (int it = 0; it < n_iter; ++it)
-    if ((e = hipGraphLaunch(it + 1 < n_iter ? b->graph_full : b->graph_last, b->stream)) !=
-        hipSuccess)
-      return hip_fail(e, "hipGraphLaunch");
+    if ((st = launched(hipGraphLaunch(it + 1 < n_iter ? b->graph_full : b->graph_last,
+                                      b->stream),
+                       b->stream, "batch iteration graph")) != RL_OK)
+      return st;
   for (rl_plan c : b->classes)
     if ((st = enqueue_flux_reduce(c, n_iter, b->stream)) != RL_OK) return st;
   b->batch_n = n_iter;
