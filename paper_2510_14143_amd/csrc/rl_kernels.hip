@@ -702,11 +702,27 @@ __device__ __forceinline__ void pencil_tile(float2* __restrict__ data,
   const long long base = (long long)vz * a.vstride + (long long)xb * a.xstride +
                          (long long)by * a.ostride + c;
 
+  // Every element index lies inside the spectrum buffer (padding columns and rows
+  // beyond lin included).  With few elements per thread, or short compiled
+  // pencils, the loads issue unconditionally, back to back, and the zeros are
+  // selected afterwards; otherwise the extra registers this takes (in the
+  // filtered passes the compiler then also hoists the transfer function's loads
+  // above the forward transform) cost more occupancy than the branches cost time
+  // (measured on the 256- and 2160-point pencils).
+  constexpr bool kUncond = E <= 6 || (E <= 12 && (MODE == PM_FWD || MODE == PM_INV)) ||
+                           (E <= 12 && CL > 0 && CL <= 192);
   float2 v[E];
+  if constexpr (kUncond) {
 #pragma unroll
-  for (int m = 0; m < E; ++m)
-    v[m] = (ok && i + P * m < a.lin) ? data[base + (long long)(i + P * m) * a.estride]
-                                        : make_float2(0.f, 0.f);
+    for (int m = 0; m < E; ++m) v[m] = data[base + (long long)(i + P * m) * a.estride];
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = (ok && i + P * m < a.lin) ? v[m] : make_float2(0.f, 0.f);
+  } else {
+#pragma unroll
+    for (int m = 0; m < E; ++m)
+      v[m] = (ok && i + P * m < a.lin) ? data[base + (long long)(i + P * m) * a.estride]
+                                          : make_float2(0.f, 0.f);
+  }
   __syncthreads();  // twiddles in LDS
 
   // split-precision stages stage their operands in this wave's slice of the exchange buffer
@@ -718,7 +734,13 @@ __device__ __forceinline__ void pencil_tile(float2* __restrict__ data,
   if constexpr (MODE == PM_FKI || MODE == PM_FCKI) {
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const float2 k = ok ? otf[base + (long long)(i + P * m) * a.estride] : make_float2(0.f, 0.f);
+      float2 k;
+      if constexpr (kUncond) {
+        k = otf[base + (long long)(i + P * m) * a.estride];
+        k = ok ? k : make_float2(0.f, 0.f);
+      } else {
+        k = ok ? otf[base + (long long)(i + P * m) * a.estride] : make_float2(0.f, 0.f);
+      }
       v[m] = (MODE == PM_FKI) ? cmul(v[m], k) : cmulc(v[m], k);
     }
   }
@@ -836,24 +858,83 @@ __device__ __forceinline__ float2 predict2(float2 x, float2 h, float al) {
   return make_float2(predict1(x.x, h.x, al), predict1(x.y, h.y, al));
 }
 
+// The volumes' rows are reached through pointers read from per-volume tables,
+// which the compiler cannot place in an address space: it would emit flat
+// accesses, each waited for on both the vector-memory and the LDS counter.  Rows
+// are therefore addressed as global memory explicitly (an aligned float pair
+// moves as one 8-byte scalar).
+typedef __attribute__((address_space(1))) const double gcdouble;
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) const float gcfloat;
+typedef __attribute__((address_space(1))) float gfloat;
+
+__device__ __forceinline__ float2 gload_pair(const float* row, int q) {
+  return __builtin_bit_cast(float2, ((gcdouble*)row)[q]);  // C-style: changes address space
+}
+
+__device__ __forceinline__ void gstore_pair(float* row, int q, float2 v) {
+  ((gdouble*)row)[q] = __builtin_bit_cast(double, v);
+}
+
 // Pair q (elements 2q, 2q+1) of a real row of `vx` floats; zero beyond the row
-// or when `on` is false.  Rows of odd length are not 8-byte aligned, so they
-// are read one float at a time.
+// or when `on` is false.  `row` must point at a readable row even when `on` is
+// false: rows of even length are read unconditionally (pair 0 stands in for
+// pairs beyond the row) and the zero selected afterwards, so that the loads of a
+// row issue back to back.  Rows of odd length are not 8-byte aligned, so they are
+// read one float at a time.
 __device__ __forceinline__ float2 load_pair(const float* row, int q, int vx, bool on) {
   const int x = 2 * q;
+  if ((vx & 1) == 0) {
+    const float2 t = gload_pair(row, x < vx ? q : 0);
+    return (on && x < vx) ? t : make_float2(0.f, 0.f);
+  }
   if (!on || x >= vx) return make_float2(0.f, 0.f);
-  if ((vx & 1) == 0) return reinterpret_cast<const float2*>(row)[q];
-  return make_float2(row[x], x + 1 < vx ? row[x + 1] : 0.f);
+  const gcfloat* r = (gcfloat*)row;
+  return make_float2(r[x], x + 1 < vx ? r[x + 1] : 0.f);
 }
+
+// Pairs i + P*m (m < E) of a row, as load_pair, for a row length whose parity
+// is known (EVEN): no branch between the loads, so that they issue back to back.
+template <bool EVEN, int E>
+__device__ __forceinline__ void load_pairs_p(float2 (&w)[E], const float* row, int i, int P,
+                                             int vx, bool on) {
+  if constexpr (EVEN) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int q = i + P * m;
+      w[m] = gload_pair(row, 2 * q < vx ? q : 0);
+    }
+#pragma unroll
+    for (int m = 0; m < E; ++m)
+      w[m] = (on && 2 * (i + P * m) < vx) ? w[m] : make_float2(0.f, 0.f);
+  } else {
+#pragma unroll
+    for (int m = 0; m < E; ++m) w[m] = load_pair(row, i + P * m, vx, on);
+  }
+}
+
+// The same with the parity decided once, outside the loads.
+template <int E>
+__device__ __forceinline__ void load_pairs(float2 (&w)[E], const float* row, int i, int P,
+                                           int vx, bool on) {
+  if ((vx & 1) == 0) load_pairs_p<true>(w, row, i, P, vx, on);
+  else load_pairs_p<false>(w, row, i, P, vx, on);
+}
+
+template <bool B>
+struct BoolC {
+  static constexpr bool value = B;
+};
 
 __device__ __forceinline__ void store_pair(float* row, int q, int vx, bool on, float2 v) {
   const int x = 2 * q;
   if (!on || x >= vx) return;
   if ((vx & 1) == 0) {
-    reinterpret_cast<float2*>(row)[q] = v;
+    gstore_pair(row, q, v);
   } else {
-    row[x] = v.x;
-    if (x + 1 < vx) row[x + 1] = v.y;
+    gfloat* r = (gfloat*)row;
+    r[x] = v.x;
+    if (x + 1 < vx) r[x + 1] = v.y;
   }
 }
 
@@ -899,7 +980,9 @@ __device__ __forceinline__ void xrow_tile(const XArgs& a, const Sched& sc,
   for (int t = tid; t < 2 * M; t += blockDim.x) tw[t] = twg[t];
   if constexpr (PREC > 0) split_atab_fill<PREC>();  // ordered by the barrier below
   const int rpw = 64 / P;                       // rows per wavefront
-  const int wave = tid >> 6, lane = tid & 63;
+  // the wave index is uniform across the wavefront: in a scalar register, rows of
+  // a whole wavefront (P = 64) get scalar row addresses
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int rw = lane / P, i = lane - rw * P;
   const int lrow = wave * rpw + rw;             // row within the work-group
   const int rowi = gx * a.RPW + lrow;
@@ -922,8 +1005,7 @@ __device__ __forceinline__ void xrow_tile(const XArgs& a, const Sched& sc,
   float2 v[E];
   if constexpr (MODE == XM_R2C) {
     const float* rin = (a.rin_tab ? a.rin_tab[vol] : a.rin) + rr * a.rin_stride;
-#pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = load_pair(rin, i + P * m, vx, rv);
+    load_pairs<E>(v, rin, i, P, vx, rv);
     __syncthreads();  // twiddles in LDS
     r2c_store<E, PREC, CM>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
   } else if constexpr (MODE == XM_PREDICT) {
@@ -931,11 +1013,9 @@ __device__ __forceinline__ void xrow_tile(const XArgs& a, const Sched& sc,
     const bool hist = a.iter > 0;
     const float al = hist ? a.alpha[a.iter] : 0.f;
     float2 hv[E];
-#pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = load_pair(a.u + ro, i + P * m, vx, rv);
+    load_pairs<E>(v, a.u + ro, i, P, vx, rv);
     if (hist) {
-#pragma unroll
-      for (int m = 0; m < E; ++m) hv[m] = load_pair(a.hstep + ro, i + P * m, vx, rv);
+      load_pairs<E>(hv, a.hstep + ro, i, P, vx, rv);
     } else {
 #pragma unroll
       for (int m = 0; m < E; ++m) hv[m] = make_float2(0.f, 0.f);
@@ -953,21 +1033,33 @@ __device__ __forceinline__ void xrow_tile(const XArgs& a, const Sched& sc,
     constexpr bool kUpdate = MODE == XM_UPDATE || MODE == XM_UPDATE_CHG || MODE == XM_UPDATE_PSNR;
     float2 w[(kRatio || kUpdate || kAcc) ? E : 1];
     float2 hv[kAcc ? E : 1], gv[kAcc ? E : 1];
+    // srow is a row of the spectrum for every thread (row 0 where the row is not
+    // wanted) and the real row pointers are valid likewise: every load of the row
+    // issues unconditionally, in one branch per row parity, and the zeros are
+    // selected afterwards
+    float2 nyq;
+    auto load_row = [&](auto even) {
+      constexpr bool kEven = decltype(even)::value;
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = ok ? srow[col_off(i + P * m, ts)] : make_float2(0.f, 0.f);
-    const float2 nyq = (ok && i == 0) ? srow[col_off(M, ts)] : make_float2(0.f, 0.f);
-    if constexpr (kRatio) {
-      const float* dr = (a.d_tab ? a.d_tab[vol] : a.d) + rr * vx;
+      for (int m = 0; m < E; ++m) v[m] = srow[col_off(i + P * m, ts)];
+      nyq = srow[col_off(M, ts)];
+      if constexpr (kRatio) {
+        const float* dr = (a.d_tab ? a.d_tab[vol] : a.d) + rr * vx;
+        load_pairs_p<kEven>(w, dr, i, P, vx, rv);
+      } else if constexpr (kUpdate) {
+        const float* ur = (a.u_tab ? a.u_tab[vol] : a.u) + rr * vx;
+        load_pairs_p<kEven>(w, ur, i, P, vx, rv);
+      } else if constexpr (kAcc) {
+        load_pairs_p<kEven>(w, a.u + rr * vx, i, P, vx, rv);
+      }
+    };
+    if ((vx & 1) == 0) load_row(BoolC<true>{});
+    else load_row(BoolC<false>{});
 #pragma unroll
-      for (int m = 0; m < E; ++m) w[m] = load_pair(dr, i + P * m, vx, rv);
-    } else if constexpr (kUpdate) {
-      const float* ur = (a.u_tab ? a.u_tab[vol] : a.u) + rr * vx;
-#pragma unroll
-      for (int m = 0; m < E; ++m) w[m] = load_pair(ur, i + P * m, vx, rv);
-    } else if constexpr (kAcc) {
+    for (int m = 0; m < E; ++m) v[m] = ok ? v[m] : make_float2(0.f, 0.f);
+    nyq = (ok && i == 0) ? nyq : make_float2(0.f, 0.f);
+    if constexpr (kAcc) {
       const long long ro = rr * vx;
-#pragma unroll
-      for (int m = 0; m < E; ++m) w[m] = load_pair(a.u + ro, i + P * m, vx, rv);
       if (a.iter > 0) {
 #pragma unroll
         for (int m = 0; m < E; ++m) {
@@ -1000,7 +1092,11 @@ __device__ __forceinline__ void xrow_tile(const XArgs& a, const Sched& sc,
           if (x0 < vx && q.x > 1e-12f) ll += (w[m].x > 0.f ? w[m].x * logf(q.x) : 0.f) - q.x;
           if (x0 + 1 < vx && q.y > 1e-12f) ll += (w[m].y > 0.f ? w[m].y * logf(q.y) : 0.f) - q.y;
         }
-        v[m] = make_float2(q.x > 1e-12f ? w[m].x / q.x : 0.f, q.y > 1e-12f ? w[m].y / q.y : 0.f);
+        // d / q as d times the hardware reciprocal (at most 1.5 ulp from the
+        // correctly rounded quotient; the pass is bound by vector instruction
+        // issue, and the IEEE division sequence costs about ten instructions)
+        v[m] = make_float2(q.x > 1e-12f ? w[m].x * __builtin_amdgcn_rcpf(q.x) : 0.f,
+                           q.y > 1e-12f ? w[m].y * __builtin_amdgcn_rcpf(q.y) : 0.f);
       }
       wave_sync();  // row buffer reuse
       r2c_store<E, PREC, CM>(v, M, P, sc, CM > 0 ? opaque_int(i) : i, tw, row, ok, srow, ts, stg);
