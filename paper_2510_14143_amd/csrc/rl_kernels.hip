@@ -690,8 +690,6 @@ __device__ __forceinline__ void pencil_tile(float2* __restrict__ data,
   const int P = CL > 0 ? CL / E : a.P;
   // twiddle table (L entries) after the exchange buffer
   float2* tw = lds + (size_t)a.L * a.TXP;
-  for (int t = tid; t < a.L; t += blockDim.x) tw[t] = twg[t];
-  if constexpr (PREC > 0) split_atab_fill<PREC>();
   const int lane = tid & (a.TXB - 1);
   const int i = tid / a.TXB;
   const int bx = a.swap ? gy : gx;  // tile (and split) index
@@ -723,6 +721,10 @@ __device__ __forceinline__ void pencil_tile(float2* __restrict__ data,
       v[m] = (ok && i + P * m < a.lin) ? data[base + (long long)(i + P * m) * a.estride]
                                           : make_float2(0.f, 0.f);
   }
+  // the table is copied after the pencil loads are issued, so that they are not
+  // held back behind its loads
+  for (int t = tid; t < a.L; t += blockDim.x) tw[t] = twg[t];
+  if constexpr (PREC > 0) split_atab_fill<PREC>();
   __syncthreads();  // twiddles in LDS
 
   // split-precision stages stage their operands in this wave's slice of the exchange buffer
@@ -895,6 +897,7 @@ __device__ __forceinline__ float2 load_pair(const float* row, int q, int vx, boo
 
 // Pairs i + P*m (m < E) of a row, as load_pair, for a row length whose parity
 // is known (EVEN): no branch between the loads, so that they issue back to back.
+// (EVEN: the loads only; zero_pairs selects the zeros once the values are needed)
 template <bool EVEN, int E>
 __device__ __forceinline__ void load_pairs_p(float2 (&w)[E], const float* row, int i, int P,
                                              int vx, bool on) {
@@ -904,21 +907,27 @@ __device__ __forceinline__ void load_pairs_p(float2 (&w)[E], const float* row, i
       const int q = i + P * m;
       w[m] = gload_pair(row, 2 * q < vx ? q : 0);
     }
-#pragma unroll
-    for (int m = 0; m < E; ++m)
-      w[m] = (on && 2 * (i + P * m) < vx) ? w[m] : make_float2(0.f, 0.f);
   } else {
 #pragma unroll
     for (int m = 0; m < E; ++m) w[m] = load_pair(row, i + P * m, vx, on);
   }
 }
 
-// The same with the parity decided once, outside the loads.
+// Zeros of the pairs load_pairs_p<true> read but the row does not have (or all
+// of them when `on` is false); a no-op for pairs load_pair already zeroed.
+template <int E>
+__device__ __forceinline__ void zero_pairs(float2 (&w)[E], int i, int P, int vx, bool on) {
+#pragma unroll
+  for (int m = 0; m < E; ++m) w[m] = (on && 2 * (i + P * m) < vx) ? w[m] : make_float2(0.f, 0.f);
+}
+
+// The same with the parity decided once, outside the loads, and the zeros selected.
 template <int E>
 __device__ __forceinline__ void load_pairs(float2 (&w)[E], const float* row, int i, int P,
                                            int vx, bool on) {
   if ((vx & 1) == 0) load_pairs_p<true>(w, row, i, P, vx, on);
   else load_pairs_p<false>(w, row, i, P, vx, on);
+  zero_pairs(w, i, P, vx, on);
 }
 
 template <bool B>
@@ -977,8 +986,22 @@ __device__ __forceinline__ void xrow_tile(const XArgs& a, const Sched& sc,
   const int M = CM > 0 ? CM : a.M, P = CM > 0 ? CM / E : a.P;
   const int tid = threadIdx.x;
   float2* tw = lds;  // 2M entries: exp(-2 pi i k / (2M))
-  for (int t = tid; t < 2 * M; t += blockDim.x) tw[t] = twg[t];
-  if constexpr (PREC > 0) split_atab_fill<PREC>();  // ordered by the barrier below
+  // The twiddle table (and the split-precision operand table) is copied after the
+  // row's loads are issued, so that they are not held back behind its loads; the
+  // barrier after the copy orders it before use.  Rows of compile-time length
+  // above 512 copy it first instead: held through their long copy, the loaded
+  // row would cost them occupancy.
+  constexpr bool kTwFirst = !(CM > 0 && CM <= 512);
+  auto fill_tw = [&]() {
+    if constexpr (!kTwFirst) {
+      for (int t = tid; t < 2 * M; t += blockDim.x) tw[t] = twg[t];
+      if constexpr (PREC > 0) split_atab_fill<PREC>();
+    }
+  };
+  if constexpr (kTwFirst) {
+    for (int t = tid; t < 2 * M; t += blockDim.x) tw[t] = twg[t];
+    if constexpr (PREC > 0) split_atab_fill<PREC>();
+  }
   const int rpw = 64 / P;                       // rows per wavefront
   // the wave index is uniform across the wavefront: in a scalar register, rows of
   // a whole wavefront (P = 64) get scalar row addresses
@@ -1006,6 +1029,7 @@ __device__ __forceinline__ void xrow_tile(const XArgs& a, const Sched& sc,
   if constexpr (MODE == XM_R2C) {
     const float* rin = (a.rin_tab ? a.rin_tab[vol] : a.rin) + rr * a.rin_stride;
     load_pairs<E>(v, rin, i, P, vx, rv);
+    fill_tw();
     __syncthreads();  // twiddles in LDS
     r2c_store<E, PREC, CM>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
   } else if constexpr (MODE == XM_PREDICT) {
@@ -1022,6 +1046,7 @@ __device__ __forceinline__ void xrow_tile(const XArgs& a, const Sched& sc,
     }
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = predict2(v[m], hv[m], al);
+    fill_tw();
     __syncthreads();  // twiddles in LDS
     r2c_store<E, PREC, CM>(v, M, P, sc, i, tw, row, ok, srow, ts, stg);
   } else {
@@ -1052,9 +1077,14 @@ __device__ __forceinline__ void xrow_tile(const XArgs& a, const Sched& sc,
       } else if constexpr (kAcc) {
         load_pairs_p<kEven>(w, a.u + rr * vx, i, P, vx, rv);
       }
+      // long rows select right away (fewer live registers), short ones after the
+      // table copy's loads have joined the row's
+      if constexpr (kTwFirst && (kRatio || kUpdate || kAcc)) zero_pairs(w, i, P, vx, rv);
     };
     if ((vx & 1) == 0) load_row(BoolC<true>{});
     else load_row(BoolC<false>{});
+    fill_tw();  // (short rows) its loads join the row's in flight
+    if constexpr (!kTwFirst && (kRatio || kUpdate || kAcc)) zero_pairs(w, i, P, vx, rv);
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = ok ? v[m] : make_float2(0.f, 0.f);
     nyq = (ok && i == 0) ? nyq : make_float2(0.f, 0.f);
