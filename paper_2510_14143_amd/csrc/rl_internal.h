@@ -33,6 +33,11 @@ struct Sched {
 // with ny rows and XT = ceil((nx/2 + 1) / 16) column tiles lives at
 //   ((z * XT + kx / 16) * ny + y) * 16 + kx % 16.
 // A tile column (fixed z and kx / 16) is ny * 128 contiguous bytes.
+// The transfer function (OTF) is stored "z major" instead, in the order the Z
+// pass (the only one that reads it) consumes it: element (z, y, kx) at
+//   ((kx / 16 * ny + y) * nz + z) * 16 + kx % 16,
+// so that a work-group's reads of one tile row over all z are nz * 128
+// contiguous bytes.
 constexpr int kTile = 16;
 
 // Geometry of a strided pencil pass (Y or Z axis).  A work-group covers TXB
@@ -226,6 +231,9 @@ hipError_t launch_persist(const PersistArgs& a, int grid, size_t lds, hipStream_
 hipError_t persist_occupancy(size_t lds, int* blocks_per_cu);
 // *counter = 0 for n ints (a fill kernel; graph-capture safe).
 hipError_t launch_zero_ints(int* p, long long n, hipStream_t s);
+// out <- in (nvol volumes of the x-tile-major layout) in the z-major OTF order.
+hipError_t launch_otf_zmajor(const float2* in, float2* out, int nvol, int nz, int ny, int xt,
+                             hipStream_t s);
 
 // Pencil kernels exist for work-groups of up to 512 threads (all E) and up to
 // 1024 threads (E = 8 and 16 only).

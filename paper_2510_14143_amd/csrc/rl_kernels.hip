@@ -734,14 +734,20 @@ __device__ __forceinline__ void pencil_tile(float2* __restrict__ data,
     else fft<E, -1, false, 0, PREC>(v, sc, i, P, tw, lds, a.TXP, lane, stg);
   }
   if constexpr (MODE == PM_FKI || MODE == PM_FCKI) {
+    // the transfer function in its z-major order: the work-group's tile (a
+    // uniform base) and this thread's row and column within it, element z at
+    // 16 z from there (the in-tile offset is below ny * 16 * L <= 2^28)
+    const float2* ot = otf + ((long long)vz * a.vstride + (long long)xb * a.xstride * a.L);
+    const int off = by * (int)a.ostride + c;  // within the tile's [y][16]
+    const int oo = (off >> 4) * (kTile * a.L) + (off & (kTile - 1)) + i * kTile;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       float2 k;
       if constexpr (kUncond) {
-        k = otf[base + (long long)(i + P * m) * a.estride];
+        k = ot[oo + P * m * kTile];
         k = ok ? k : make_float2(0.f, 0.f);
       } else {
-        k = ok ? otf[base + (long long)(i + P * m) * a.estride] : make_float2(0.f, 0.f);
+        k = ok ? ot[oo + P * m * kTile] : make_float2(0.f, 0.f);
       }
       v[m] = (MODE == PM_FKI) ? cmul(v[m], k) : cmulc(v[m], k);
     }
@@ -2203,6 +2209,32 @@ hipError_t persist_occupancy(size_t lds, int* blocks_per_cu) {
 __global__ void k_zero_ints(int* p, long long n) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) p[t] = 0;
+}
+
+__global__ void k_otf_zmajor(const float2* __restrict__ in, float2* __restrict__ out, long long n,
+                             int nz, int ny, int xt) {
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int col = (int)(idx & (kTile - 1));
+    long long r = idx >> 4;  // ((v * nz + z) * xt + t) * ny + y
+    const int y = (int)(r % ny);
+    r /= ny;
+    const int t = (int)(r % xt);
+    r /= xt;
+    const int z = (int)(r % nz);
+    const long long v = r / nz;
+    out[(((v * xt + t) * ny + y) * nz + z) * kTile + col] = in[idx];
+  }
+}
+
+hipError_t launch_otf_zmajor(const float2* in, float2* out, int nvol, int nz, int ny, int xt,
+                             hipStream_t s) {
+  const long long n = (long long)nvol * nz * ny * xt * kTile;
+  if (n <= 0) return hipSuccess;
+  const long long blocks = std::min<long long>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_otf_zmajor, dim3((unsigned)blocks), dim3(256), 0, s, in, out, n, nz, ny,
+                     xt);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero_ints(int* p, long long n, hipStream_t s) {
