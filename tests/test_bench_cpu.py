@@ -1,6 +1,7 @@
 """Host-side checks of bench.py that need no GPU: the one-GPU refusal, the
-algorithmic byte model of each pass, and the rocprofv3 summary step (CSV parsing,
-back-to-back launches, counter calibration, the source-hash guard)."""
+algorithmic byte model of each pass, the guard around the secondary workloads, and
+the rocprofv3 summary step (CSV parsing, back-to-back launches, counter
+calibration, the source-hash guard)."""
 
 import importlib.util
 import os
@@ -42,6 +43,20 @@ def test_kernel_bytes_model(bench):
     assert kb["x_update"] == 2 * spec + 2 * real
     assert kb["x_update_last"] == spec + 2 * real
     assert kb["x_r2c"] == kb["x_c2r"] == spec + real
+
+
+def test_optional_leg_records_a_failure(bench, capsys):
+    # a secondary workload that fails is logged and recorded in its place; the
+    # others (and the headline line) go on
+    assert bench.optional_leg("fine", lambda: {"value": 1.0}) == {"value": 1.0}
+
+    def broken():
+        raise RuntimeError("no memory left")
+
+    rec = bench.optional_leg("broken", broken)
+    assert rec == {"error": "RuntimeError: no memory left"}
+    err = capsys.readouterr().err
+    assert "broken failed" in err and "Traceback" in err
 
 
 def test_kernel_short_name(bench):
