@@ -1374,7 +1374,7 @@ rl_status build_class(const Geometry& geo, int count, const float* const* psfs, 
   // into the order the Z pass reads it (through the spectrum workspace)
   if (psfs) {
     RL_TRY(rlmi::launch_otf_zmajor(p->otf, p->spec, count, (int)nz, (int)ny, (int)p->xt,
-                                   p->stream));
+                                   (int)p->ncols, p->stream));
     RL_TRY(hipMemcpyAsync(p->otf, p->spec, spec_bytes, hipMemcpyDeviceToDevice, p->stream));
   }
   RL_TRY(hipStreamSynchronize(p->stream));

@@ -34,10 +34,13 @@ struct Sched {
 //   ((z * XT + kx / 16) * ny + y) * 16 + kx % 16.
 // A tile column (fixed z and kx / 16) is ny * 128 contiguous bytes.
 // The transfer function (OTF) is stored "z major" instead, in the order the Z
-// pass (the only one that reads it) consumes it: element (z, y, kx) at
-//   ((kx / 16 * ny + y) * nz + z) * 16 + kx % 16,
-// so that a work-group's reads of one tile row over all z are nz * 128
-// contiguous bytes.
+// pass (the only one that reads it) consumes it: with t = kx / 16 and w the
+// tile's width (16, or for the last tile the valid columns left, ncols - 16 t),
+// element (z, y, kx) at
+//   t * ny * nz * 16 + (y * nz + z) * w + kx % 16,
+// so that a work-group's reads of one tile row over all z are nz * 8 w
+// contiguous bytes, and the last tile's padding columns are not stored (for
+// even nx it holds the Nyquist column alone).
 constexpr int kTile = 16;
 
 // Geometry of a strided pencil pass (Y or Z axis).  A work-group covers TXB
@@ -231,9 +234,10 @@ hipError_t launch_persist(const PersistArgs& a, int grid, size_t lds, hipStream_
 hipError_t persist_occupancy(size_t lds, int* blocks_per_cu);
 // *counter = 0 for n ints (a fill kernel; graph-capture safe).
 hipError_t launch_zero_ints(int* p, long long n, hipStream_t s);
-// out <- in (nvol volumes of the x-tile-major layout) in the z-major OTF order.
+// out <- in (nvol volumes of the x-tile-major layout) in the z-major OTF order,
+// the last tile stored ncols - 16 (xt - 1) columns wide.
 hipError_t launch_otf_zmajor(const float2* in, float2* out, int nvol, int nz, int ny, int xt,
-                             hipStream_t s);
+                             int ncols, hipStream_t s);
 
 // Pencil kernels exist for work-groups of up to 512 threads (all E) and up to
 // 1024 threads (E = 8 and 16 only).

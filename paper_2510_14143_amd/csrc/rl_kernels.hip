@@ -735,19 +735,21 @@ __device__ __forceinline__ void pencil_tile(float2* __restrict__ data,
   }
   if constexpr (MODE == PM_FKI || MODE == PM_FCKI) {
     // the transfer function in its z-major order: the work-group's tile (a
-    // uniform base) and this thread's row and column within it, element z at
-    // 16 z from there (the in-tile offset is below ny * 16 * L <= 2^28)
+    // uniform base; the last tile stored only as wide as its valid columns)
+    // and this thread's row and column within it, element z at w z from there
+    // (the in-tile offset is below ny * 16 * L <= 2^28)
     const float2* ot = otf + ((long long)vz * a.vstride + (long long)xb * a.xstride * a.L);
+    const int w = min(kTile, a.ncols - xb * kTile);
     const int off = by * (int)a.ostride + c;  // within the tile's [y][16]
-    const int oo = (off >> 4) * (kTile * a.L) + (off & (kTile - 1)) + i * kTile;
+    const int oo = (off >> 4) * (w * a.L) + (ok ? (off & (kTile - 1)) : 0) + i * w;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       float2 k;
       if constexpr (kUncond) {
-        k = ot[oo + P * m * kTile];
+        k = ot[oo + P * m * w];
         k = ok ? k : make_float2(0.f, 0.f);
       } else {
-        k = ok ? ot[oo + P * m * kTile] : make_float2(0.f, 0.f);
+        k = ok ? ot[oo + P * m * w] : make_float2(0.f, 0.f);
       }
       v[m] = (MODE == PM_FKI) ? cmul(v[m], k) : cmulc(v[m], k);
     }
@@ -2212,7 +2214,7 @@ __global__ void k_zero_ints(int* p, long long n) {
 }
 
 __global__ void k_otf_zmajor(const float2* __restrict__ in, float2* __restrict__ out, long long n,
-                             int nz, int ny, int xt) {
+                             int nz, int ny, int xt, int ncols) {
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
        idx += (long long)gridDim.x * blockDim.x) {
     const int col = (int)(idx & (kTile - 1));
@@ -2223,17 +2225,20 @@ __global__ void k_otf_zmajor(const float2* __restrict__ in, float2* __restrict__
     r /= xt;
     const int z = (int)(r % nz);
     const long long v = r / nz;
-    out[(((v * xt + t) * ny + y) * nz + z) * kTile + col] = in[idx];
+    const int w = min(kTile, ncols - t * kTile);  // the tile's stored width
+    if (col >= w) continue;                       // padding: not stored
+    out[((v * xt + t) * ny * nz) * kTile + ((long long)y * nz + z) * w + col] = in[idx];
   }
 }
 
 hipError_t launch_otf_zmajor(const float2* in, float2* out, int nvol, int nz, int ny, int xt,
-                             hipStream_t s) {
+                             int ncols, hipStream_t s) {
   const long long n = (long long)nvol * nz * ny * xt * kTile;
   if (n <= 0) return hipSuccess;
+  if (ncols <= (xt - 1) * kTile || ncols > xt * kTile) return hipErrorInvalidValue;
   const long long blocks = std::min<long long>((n + 255) / 256, 65536);
   hipLaunchKernelGGL(k_otf_zmajor, dim3((unsigned)blocks), dim3(256), 0, s, in, out, n, nz, ny,
-                     xt);
+                     xt, ncols);
   return hipGetLastError();
 }
 
