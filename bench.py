@@ -354,7 +354,7 @@ def run_workload(torch, rl, synth, cfg: int, steps: int, warmup: int, workload: 
 def run_batched(torch, rl, synth, steps: int, warmup: int, count: int = 96, n_iter: int = 50,
                 autotune: bool = True):
     """Batched form: `count` uneven volumes with their own PSFs, one graph launch per
-    iteration (the per-pass kernels of every shape class), against the same volumes
+    shape class and iteration (the class's per-pass kernels), against the same volumes
     run one plain plan at a time.  With
     `autotune`, the batch plan tunes each shape class once and the plain plans reuse
     those choices through a temporary tuning cache (both sides tuned alike; plan

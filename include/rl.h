@@ -158,8 +158,9 @@ typedef enum {
                               volume's tiles run on one XCD.  Switched off in this
                               library: its completion waits did not finish on MI355X,
                               and plan creation returns RL_E_UNSUPPORTED */
-  RL_BATCH_GRAPH = 2       /* per-pass kernels of each shape class, one hipGraph branch
-                              per class */
+  RL_BATCH_GRAPH = 2       /* per-pass kernels of each shape class: one hipGraph of
+                              one iteration per class, replayed on the class's own
+                              stream */
 } rl_batch_mode;
 
 /*
@@ -236,9 +237,11 @@ rl_status rl_plan_create_batch(int count, const int64_t* shapes, const float* co
 /*
  * n_iter iterations of every volume of a batch plan: observed[v] and
  * estimate[v] are device pointers (host arrays of `count` pointers, read
- * during the call).  One iteration of all volumes is one hipGraph launch
- * (captured on the first call, replayed afterwards); the graph holds one
- * branch per shape class.  rl_plan_get_flux then returns count * n_iter values,
+ * during the call).  One iteration of one shape class is one hipGraph launch
+ * (captured on the first call, replayed afterwards) on the class's private
+ * stream; the classes run their iterations independently and join the plan's
+ * stream once, at the end of the call.  rl_plan_get_flux then returns
+ * count * n_iter values,
  * volume-major (flux[v * n_iter + t]).  Asynchronous like rl_iterate.
  */
 rl_status rl_iterate_batch(rl_plan p, const float* const* observed, float* const* estimate,

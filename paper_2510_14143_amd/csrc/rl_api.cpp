@@ -2290,41 +2290,23 @@ rl_status create_batch_impl(int count, const int64_t* shapes, const float* const
   return RL_OK;
 }
 
-// One iteration of every class, forked from and joined back into `origin`
-// (captured into a graph by the caller).
-rl_status enqueue_batch_iteration(rl_plan b, bool do_fwd, hipStream_t origin) {
-  hipError_t e;
-  rl_status st;
-  if ((e = hipEventRecord(b->fork_event, origin)) != hipSuccess)
-    return hip_fail(e, "hipEventRecord");
-  for (size_t c = 0; c < b->classes.size(); ++c) {
-    rl_plan cl = b->classes[c];
-    if ((e = hipStreamWaitEvent(cl->stream, b->fork_event, 0)) != hipSuccess)
-      return hip_fail(e, "hipStreamWaitEvent");
-    if ((st = enqueue_iteration(cl, nullptr, nullptr, 0, b->iter_dev, do_fwd)) != RL_OK) return st;
-    if ((e = hipEventRecord(b->cls_events[c], cl->stream)) != hipSuccess)
-      return hip_fail(e, "hipEventRecord");
-    if ((e = hipStreamWaitEvent(origin, b->cls_events[c], 0)) != hipSuccess)
-      return hip_fail(e, "hipStreamWaitEvent");
-  }
-  if ((e = rlmi::launch_advance(b->iter_dev, origin)) != hipSuccess)
-    return hip_fail(e, "iteration counter launch");
-  return RL_OK;
-}
-
-// Captured on the plan's private stream (the caller's stream may be the legacy
-// null stream, which cannot be captured); launched later on the caller's stream.
-rl_status capture_graph(rl_plan b, bool do_fwd, hipGraphExec_t* exec) {
+// One iteration of one shape class, advancing the class's own iteration counter,
+// captured on the class's private stream and launched there: the classes of a
+// batch run their iterations independently of each other and meet once per
+// call, not once per iteration.
+rl_status capture_class_graph(rl_plan c, bool do_fwd, hipGraphExec_t* exec) {
   hipGraph_t g = nullptr;
-  hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+  hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-  rl_status st = enqueue_batch_iteration(b, do_fwd, b->cap_stream);
-  e = hipStreamEndCapture(b->cap_stream, &g);
+  rl_status st = enqueue_iteration(c, nullptr, nullptr, 0, c->iter_dev, do_fwd);
+  if (st == RL_OK && (e = rlmi::launch_advance(c->iter_dev, c->stream)) != hipSuccess)
+    st = hip_fail(e, "iteration counter launch");
+  const hipError_t ee = hipStreamEndCapture(c->stream, &g);
   if (st != RL_OK) {
     if (g) (void)hipGraphDestroy(g);
     return st;
   }
-  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
   e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   return e == hipSuccess ? RL_OK : hip_fail(e, "hipGraphInstantiate");
@@ -2391,13 +2373,21 @@ rl_status iterate_batch_impl(rl_plan b, const float* const* observed, float* con
     if (b->graph_full) (void)hipGraphExecDestroy(b->graph_full);
     if (b->graph_last) (void)hipGraphExecDestroy(b->graph_last);
     b->graph_full = b->graph_last = nullptr;
+    for (rl_plan c : b->classes) {
+      if (c->graph_full) (void)hipGraphExecDestroy(c->graph_full);
+      if (c->graph_last) (void)hipGraphExecDestroy(c->graph_last);
+      c->graph_full = c->graph_last = nullptr;
+    }
   }
   if (b->persist) {
     if (!b->graph_full && (st = capture_persist_graph(b, 0, &b->graph_full)) != RL_OK) return st;
     if (!b->graph_last && (st = capture_persist_graph(b, 1, &b->graph_last)) != RL_OK) return st;
   } else {
-    if (!b->graph_full && (st = capture_graph(b, true, &b->graph_full)) != RL_OK) return st;
-    if (!b->graph_last && (st = capture_graph(b, false, &b->graph_last)) != RL_OK) return st;
+    for (rl_plan c : b->classes) {
+      if (!c->graph_full && (st = capture_class_graph(c, true, &c->graph_full)) != RL_OK) return st;
+      if (!c->graph_last && (st = capture_class_graph(c, false, &c->graph_last)) != RL_OK)
+        return st;
+    }
   }
   // per-volume pointer tables (ordered after earlier work on b->stream)
   for (size_t ci = 0; ci < b->classes.size(); ++ci) {
@@ -2426,7 +2416,9 @@ rl_status iterate_batch_impl(rl_plan b, const float* const* observed, float* con
        (e = rlmi::launch_zero_ints(b->p_error, rlmi::kPersistMaxQueues, b->stream)) !=
            hipSuccess))
     return hip_fail(e, "persistent counters");
-  // prologue per class, forked from and joined back into b->stream
+  // prologue per class, forked from b->stream; with the persistent kernel the
+  // classes join again before its iterations, otherwise each class runs its
+  // iterations on its own stream (its counter from 0) and they join at the end
   if ((e = hipEventRecord(b->fork_event, b->stream)) != hipSuccess)
     return hip_fail(e, "hipEventRecord");
   for (size_t ci = 0; ci < b->classes.size(); ++ci) {
@@ -2434,15 +2426,30 @@ rl_status iterate_batch_impl(rl_plan b, const float* const* observed, float* con
     if ((e = hipStreamWaitEvent(c->stream, b->fork_event, 0)) != hipSuccess)
       return hip_fail(e, "hipStreamWaitEvent");
     if ((st = enqueue_prologue(c, nullptr)) != RL_OK) return st;
-    if ((e = hipEventRecord(b->cls_events[ci], c->stream)) != hipSuccess ||
-        (e = hipStreamWaitEvent(b->stream, b->cls_events[ci], 0)) != hipSuccess)
+    if (!b->persist && (e = rlmi::launch_set_counter(c->iter_dev, 0, c->stream)) != hipSuccess)
+      return hip_fail(e, "iteration counter launch");
+    if (b->persist && ((e = hipEventRecord(b->cls_events[ci], c->stream)) != hipSuccess ||
+                       (e = hipStreamWaitEvent(b->stream, b->cls_events[ci], 0)) != hipSuccess))
       return hip_fail(e, "prologue join");
   }
-  for (int it = 0; it < n_iter; ++it)
-    if ((st = launched(hipGraphLaunch(it + 1 < n_iter ? b->graph_full : b->graph_last,
-                                      b->stream),
-                       b->stream, "batch iteration graph")) != RL_OK)
-      return st;
+  if (b->persist) {
+    for (int it = 0; it < n_iter; ++it)
+      if ((st = launched(hipGraphLaunch(it + 1 < n_iter ? b->graph_full : b->graph_last,
+                                        b->stream),
+                         b->stream, "batch iteration graph")) != RL_OK)
+        return st;
+  } else {
+    for (int it = 0; it < n_iter; ++it)
+      for (rl_plan c : b->classes)
+        if ((st = launched(hipGraphLaunch(it + 1 < n_iter ? c->graph_full : c->graph_last,
+                                          c->stream),
+                           c->stream, "class iteration graph")) != RL_OK)
+          return st;
+    for (size_t ci = 0; ci < b->classes.size(); ++ci)
+      if ((e = hipEventRecord(b->cls_events[ci], b->classes[ci]->stream)) != hipSuccess ||
+          (e = hipStreamWaitEvent(b->stream, b->cls_events[ci], 0)) != hipSuccess)
+        return hip_fail(e, "class join");
+  }
   for (rl_plan c : b->classes)
     if ((st = enqueue_flux_reduce(c, n_iter, b->stream)) != RL_OK) return st;
   b->batch_n = n_iter;
