@@ -706,9 +706,11 @@ __device__ __forceinline__ void pencil_tile(float2* __restrict__ data,
   // selected afterwards; otherwise the extra registers this takes (in the
   // filtered passes the compiler then also hoists the transfer function's loads
   // above the forward transform) cost more occupancy than the branches cost time
-  // (measured on the 256- and 2160-point pencils).
-  constexpr bool kUncond = E <= 6 || (E <= 12 && (MODE == PM_FWD || MODE == PM_INV)) ||
-                           (E <= 12 && CL > 0 && CL <= 192);
+  // (measured on the 256- and 2160-point pencils).  The runtime-schedule
+  // kernels keep the branches above 6 elements: held to 64 registers in
+  // 1024-thread work-groups, they would spill.
+  constexpr bool kUncond =
+      E <= 6 || (CL > 0 && E <= 12 && (MODE == PM_FWD || MODE == PM_INV || CL <= 192));
   float2 v[E];
   if constexpr (kUncond) {
 #pragma unroll
